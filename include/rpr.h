@@ -1,0 +1,226 @@
+/*
+ * rpr.h -- C ABI of librpr, RandNet-Parareal on AMD MI355X (gfx950).
+ *
+ * RandNet-Parareal (arXiv 2411.06225) solves the initial value problem
+ *     du/dt = h(u),  u(t0) = u0,  t in [t0, tN]                (Sec. 1, eq. "ode")
+ * parallel in time: [t0, tN] is cut into N equal slices, an accurate fine
+ * propagator F runs on all unfinished slices at once, and a cheap coarse
+ * propagator G is corrected by a random network whose readout is fitted by
+ * ridge regression to the observed F - G discrepancies (Sec. 2-4).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns rpr_status; no C++ exception crosses this boundary.
+ *     On a non-OK status rpr_last_error() returns a message for the calling
+ *     thread.
+ *   - "device pointer" means memory allocated on the current HIP device
+ *     (e.g. torch.Tensor.data_ptr() of a CUDA tensor); "host pointer" means
+ *     ordinary CPU memory.  The library never frees memory it did not
+ *     allocate.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  Work is
+ *     enqueued asynchronously on it; results are valid once the stream has been
+ *     synchronised.  Argument errors are reported synchronously, before
+ *     anything is enqueued.
+ *   - Arrays are row-major.  A state u in R^d is stored species-planar,
+ *     [species][y][x] with x fastest (Burgers: [x]).
+ *   - Slices are equal: t_i = t0 + i (tN - t0) / N.  A propagator with `steps`
+ *     steps per slice uses dt = ((tN - t0) / N) / steps, computed in double
+ *     precision in exactly this order.
+ */
+#ifndef RPR_H
+#define RPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RPR_OK = 0,
+    RPR_NOT_CONVERGED = 1,      /* iteration cap reached before every slot was final;
+                                   outputs hold the last iterate */
+    RPR_ERR_INVALID_ARG = -1,   /* bad argument; nothing was enqueued */
+    RPR_ERR_NO_DEVICE = -2,     /* no usable gfx950 device */
+    RPR_ERR_HIP = -3,           /* a HIP runtime call failed (message has the HIP error) */
+    RPR_ERR_OOM = -4,           /* device allocation failed */
+    RPR_ERR_NONFINITE = -5,     /* non-finite values where the method needs finite ones */
+    RPR_ERR_NOT_SPD = -6,       /* ridge matrix not numerically positive definite */
+    RPR_ERR_UNSUPPORTED = -8    /* a valid combination this build does not implement */
+} rpr_status;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rpr_last_error(void);
+/* Library version string, e.g. "rpr 0.1 gfx950". */
+const char *rpr_version(void);
+
+/* ---- problem: the spatial right-hand side h of eq. "ode" ----------------- */
+typedef enum {
+    RPR_BURGERS1D = 0,   /* Sec. 5.1, eq. "burg": nu u_xx - u u_x, periodic, central
+                            differences; p[0] = nu; d = nx, ny = 1 */
+    RPR_DIFFREACT2D = 1, /* Sec. 5.2: FitzHugh-Nagumo two-species diffusion-reaction,
+                            cell-centred finite volumes, no-flux walls;
+                            p = (Du, Dv, c); d = 2 nx ny, layout [u; v] */
+    RPR_BRUSS2D = 2,     /* App. E: Brusselator, periodic; p = (A, B, Du, Dv);
+                            d = 2 nx ny, layout [u; v] */
+    RPR_SWE2D = 3        /* Sec. 5.3: shallow water (h, hu, hv), flat bottom, first-order
+                            finite volumes with the Rusanov flux, reflective walls;
+                            p[0] = g; d = 3 nx ny, layout [h; hu; hv] */
+} rpr_rhs_kind;
+
+typedef struct {
+    int32_t kind;              /* rpr_rhs_kind */
+    int32_t nx, ny;            /* points (1D) or cells (2D) per direction; ny = 1 in 1D */
+    int32_t reserved;          /* must be 0 */
+    double x0, x1, y0, y1;     /* domain; grid spacing (x1 - x0) / nx, (y1 - y0) / ny */
+    double p[6];               /* physical parameters, see rpr_rhs_kind */
+} rpr_rhs;
+
+/* ---- propagators F and G (Sec. 2; App. G setup tables) ------------------ */
+typedef enum { RPR_RK1 = 1, RPR_RK4 = 4 } rpr_method; /* forward Euler, classical RK4 */
+
+typedef struct {
+    int32_t method;            /* rpr_method */
+    int32_t reserved;          /* must be 0 */
+    int64_t steps;             /* fixed steps per slice, >= 1 */
+} rpr_propagator;
+
+/* ---- the random network of eq. "HA" and its ridge readout ----------------- */
+typedef enum { RPR_TANH = 0, RPR_RELU = 1 } rpr_activation;
+
+typedef struct {
+    int32_t M;                 /* hidden neurons, 1 <= M <= 1024 */
+    int32_t activation;        /* rpr_activation (the paper uses ReLU, Sec. 4) */
+    double lambda;             /* ridge penalty of eq. "ridgeless" (> 0) */
+    double input_scale;        /* the network sees x / s; <= 0 selects the default:
+                                  the smallest power of two s >= max(1, ||u0||_inf) */
+} rpr_randnet;
+
+typedef enum {
+    RPR_FP64 = 0,              /* every step in double precision */
+    RPR_MIXED = 1              /* F and G in single precision; features, Gram and
+                                  readout statistics accumulated in double; ridge
+                                  Cholesky and convergence norm in double */
+} rpr_precision;
+
+typedef enum {
+    RPR_CORR_RANDNET = 0,      /* eq. "HA" with the readout of eq. "ridgeless" fitted on
+                                  every pair of eq. "Dk" collected so far */
+    RPR_CORR_PARAREAL = 1      /* eq. "fpara": (F - G)(U_{i-1}^{k-1}) */
+} rpr_correction;
+
+typedef struct {
+    int32_t precision;         /* rpr_precision */
+    int32_t correction;        /* rpr_correction */
+    int32_t k_max;             /* iteration cap, 1 <= k_max <= N (0 selects N) */
+    int32_t poll_every;        /* iterations enqueued between checks of the device
+                                  "done" flag (0 selects 2) */
+} rpr_options;
+
+/* ---- plans: one IVP solved by RandNet-Parareal -------------------------- */
+typedef struct rpr_plan rpr_plan;
+
+/*
+ * Create a plan for the problem (h, u0 of dimension d, [t0, tN], N, F, G, tol)
+ * of Sec. 2 and Algorithm "Parareal (generic)".
+ *   h, F, G, net, opt : host pointers, read during the call only.
+ *   d                 : state dimension; must equal species * nx * ny of h.
+ *   tol               : epsilon of eq. "stop_crit" (>= 0; +inf stops after one
+ *                       iteration, 0 forces N iterations).
+ *   A, zeta           : optional host arrays (M x d and M, doubles) with the
+ *                       hidden-layer weights and biases, copied during the call;
+ *                       if both are NULL they are drawn on the device from the
+ *                       counter-based generator rpr_uniform_pm1 with `seed`:
+ *                       A[m][j] = counter m*d + j, zeta[m] = counter M*d + m.
+ *                       Ignored (may be NULL) for RPR_CORR_PARAREAL.
+ * Allocates every device buffer the solve needs (the plan owns them).
+ * Errors: RPR_ERR_INVALID_ARG, RPR_ERR_NO_DEVICE, RPR_ERR_OOM, RPR_ERR_HIP,
+ * RPR_ERR_UNSUPPORTED (e.g. a state too large for this build's kernels).
+ */
+rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t d, double t0, double tN,
+                           int32_t N, const rpr_propagator *F, const rpr_propagator *G, double tol,
+                           const rpr_randnet *net, const double *A, const double *zeta,
+                           uint64_t seed, const rpr_options *opt);
+
+/*
+ * Run the solve.  u0: device pointer, d doubles.  U_out: device pointer,
+ * (N + 1) x d doubles, caller-owned; receives U_0^K .. U_N^K.  Enqueued on
+ * `stream`; the call returns once the run has finished on the device (it
+ * polls a device flag every opt.poll_every iterations), so U_out is valid on
+ * return.  Returns RPR_OK, or RPR_NOT_CONVERGED if k_max iterations ended
+ * with unfinished slots (U_out then holds the last iterate), or an error.
+ * A non-finite u0 returns RPR_ERR_NONFINITE.
+ */
+rpr_status rpr_plan_execute(rpr_plan *plan, const void *u0, void *U_out, void *stream);
+
+typedef struct {
+    int32_t K;                 /* iterations run */
+    int32_t L_final;           /* slots U_0..U_L are final */
+    int32_t converged;         /* 1 if L reached N */
+    int32_t rows_used;         /* finite training pairs accumulated in the readout */
+    int32_t nonfinite_rows;    /* pairs dropped because of a non-finite entry */
+    int32_t chol_fail;         /* iterations whose ridge matrix failed Cholesky */
+    double input_scale;        /* s actually used */
+    double t_total;            /* seconds of device time of the last execute */
+} rpr_info;
+
+/* Results of the last execute (host pointer `info`). */
+rpr_status rpr_plan_info(const rpr_plan *plan, rpr_info *info);
+
+/* Per-iteration history of the last execute into host arrays of length cap:
+ * L_hist[k] = L after iteration k (k = 0..K), chg_hist[k] = largest
+ * infinity-norm change of the predicted slots at iteration k (NaN counts as
+ * +inf).  Either pointer may be NULL. */
+rpr_status rpr_plan_history(const rpr_plan *plan, int32_t *L_hist, double *chg_hist, int32_t cap);
+
+/* Release every buffer of the plan.  NULL is accepted. */
+rpr_status rpr_plan_destroy(rpr_plan *plan);
+
+/* ---- building blocks (the same kernels the plan runs) -------------------- */
+
+/*
+ * Propagate n_states independent states over one slice: out[r] = P(in[r]).
+ * Sec. 2: F and G map the state at the start of a slice to its end.
+ *   in, out   : device pointers, n_states x d, doubles if precision = RPR_FP64,
+ *               floats if RPR_MIXED; must not overlap.
+ *   dt        : step length; P->steps steps are taken.
+ */
+rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propagator *P, int32_t precision,
+                         double dt, int32_t n_states, const void *in, void *out, void *stream);
+
+/*
+ * Hidden-layer features of eq. "HA": Phi[r][m] = sigma(sum_j A[m][j] (X[r][j] / s) + zeta[m]).
+ *   A (M x d), zeta (M), X (n x d), Phi (n x M): device pointers, doubles.
+ */
+rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
+                                const double *A, const double *zeta, const double *X, double *Phi,
+                                void *stream);
+
+/*
+ * Ridge readout of eq. "ridgeless" at penalty lambda:
+ *   W = (Phi^T Phi + lambda I_M)^{-1} Phi^T Y   (Cholesky, double precision).
+ *   Phi (n x M), Y (n x d), W (M x d): device pointers, doubles.
+ * Returns RPR_ERR_NOT_SPD (after synchronising the stream) if the matrix is
+ * not numerically positive definite.  Allocates and frees its own workspace.
+ */
+rpr_status rpr_ridge_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y,
+                         double lambda, double *W, void *stream);
+
+/*
+ * Readout of eq. "HA": Yhat[r][j] = sum_m W[m][j] Phi[r][m].
+ *   W (M x d), Phi (n x M), Yhat (n x d): device pointers, doubles.
+ */
+rpr_status rpr_randnet_readout(int32_t M, int32_t d, int32_t n, const double *W, const double *Phi,
+                               double *Yhat, void *stream);
+
+/*
+ * Counter-based U(-1, 1) generator (SplitMix64 of Steele, Lea and Flood,
+ * OOPSLA 2014, used as a hash of seed + (i + 1) * 0x9E3779B97F4A7C15):
+ * out[k] = 2 ((r >> 11) 2^-53) - 1 with r the output for counter first + k.
+ *   out: device pointer, n doubles.
+ */
+rpr_status rpr_uniform_pm1(uint64_t seed, uint64_t first, int64_t n, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPR_H */

@@ -1,1 +1,236 @@
-"""RandNet-Parareal on AMD MI355X (placeholder during bring-up)."""
+"""RandNet-Parareal on AMD MI355X (gfx950).
+
+Thin ctypes binding of ``librpr.so`` (C ABI in ``include/rpr.h``).  Every step
+of the method runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch is used for device memory and streams only.  If the built
+library is missing, loading fails with an error: there is no CPU fallback.
+
+Entry points keep the C names: ``rpr_plan_create``, ``rpr_plan_execute``,
+``rpr_propagate``, ``rpr_randnet_features``, ``rpr_ridge_fit``,
+``rpr_randnet_readout``, ``rpr_uniform_pm1`` ...; ``Plan`` and ``solve`` wrap
+the plan calls for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpr.so")
+
+# status codes (rpr_status)
+RPR_OK, RPR_NOT_CONVERGED = 0, 1
+RPR_ERR_INVALID_ARG, RPR_ERR_NO_DEVICE, RPR_ERR_HIP, RPR_ERR_OOM = -1, -2, -3, -4
+RPR_ERR_NONFINITE, RPR_ERR_NOT_SPD, RPR_ERR_UNSUPPORTED = -5, -6, -8
+# enums
+RPR_BURGERS1D, RPR_DIFFREACT2D, RPR_BRUSS2D, RPR_SWE2D = 0, 1, 2, 3
+RPR_RK1, RPR_RK4 = 1, 4
+RPR_TANH, RPR_RELU = 0, 1
+RPR_FP64, RPR_MIXED = 0, 1
+RPR_CORR_RANDNET, RPR_CORR_PARAREAL = 0, 1
+
+EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
+            "rpr_plan_history", "rpr_plan_destroy", "rpr_propagate", "rpr_randnet_features", "rpr_ridge_fit",
+            "rpr_randnet_readout", "rpr_uniform_pm1")
+
+
+class RprError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rpr status {status}: {msg}")
+        self.status = status
+
+
+class rpr_rhs(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("reserved", C.c_int32),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("p", C.c_double * 6)]
+
+
+class rpr_propagator(C.Structure):
+    _fields_ = [("method", C.c_int32), ("reserved", C.c_int32), ("steps", C.c_int64)]
+
+
+class rpr_randnet(C.Structure):
+    _fields_ = [("M", C.c_int32), ("activation", C.c_int32), ("lam", C.c_double), ("input_scale", C.c_double)]
+
+
+class rpr_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("correction", C.c_int32), ("k_max", C.c_int32),
+                ("poll_every", C.c_int32)]
+
+
+class rpr_info(C.Structure):
+    _fields_ = [("K", C.c_int32), ("L_final", C.c_int32), ("converged", C.c_int32), ("rows_used", C.c_int32),
+                ("nonfinite_rows", C.c_int32), ("chol_fail", C.c_int32), ("input_scale", C.c_double),
+                ("t_total", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded librpr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_06225_amd.build` "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i32, i64, u64, dbl = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        sig = {
+            "rpr_last_error": (C.c_char_p, []),
+            "rpr_version": (C.c_char_p, []),
+            "rpr_plan_create": (i32, [C.POINTER(vp), C.POINTER(rpr_rhs), i32, dbl, dbl, i32,
+                                      C.POINTER(rpr_propagator), C.POINTER(rpr_propagator), dbl,
+                                      C.POINTER(rpr_randnet), vp, vp, u64, C.POINTER(rpr_options)]),
+            "rpr_plan_execute": (i32, [vp, vp, vp, vp]),
+            "rpr_plan_info": (i32, [vp, C.POINTER(rpr_info)]),
+            "rpr_plan_history": (i32, [vp, C.POINTER(C.c_int32), dp, i32]),
+            "rpr_plan_destroy": (i32, [vp]),
+            "rpr_propagate": (i32, [C.POINTER(rpr_rhs), i32, C.POINTER(rpr_propagator), i32, dbl, i32, vp, vp,
+                                    vp]),
+            "rpr_randnet_features": (i32, [i32, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
+            "rpr_ridge_fit": (i32, [i32, i32, i32, vp, vp, dbl, vp, vp]),
+            "rpr_randnet_readout": (i32, [i32, i32, i32, vp, vp, vp, vp]),
+            "rpr_uniform_pm1": (i32, [u64, u64, i64, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().rpr_last_error().decode()
+
+
+def check(status: int, allow=(RPR_OK,)) -> int:
+    if status not in allow:
+        raise RprError(status, last_error())
+    return status
+
+
+def _ptr(t) -> int | None:
+    """Device (or host) address of a torch tensor, an int, or None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def make_rhs(kind: int, nx: int, ny: int = 1, domain=(-1.0, 1.0, -1.0, 1.0), params=()) -> rpr_rhs:
+    p = (C.c_double * 6)(*([float(v) for v in params] + [0.0] * (6 - len(params))))
+    x0, x1, y0, y1 = (float(v) for v in domain)
+    return rpr_rhs(int(kind), int(nx), int(ny), 0, x0, x1, y0, y1, p)
+
+
+def nspecies(kind: int) -> int:
+    return {RPR_BURGERS1D: 1, RPR_DIFFREACT2D: 2, RPR_BRUSS2D: 2, RPR_SWE2D: 3}[kind]
+
+
+# ---- building blocks ---------------------------------------------------------
+def rpr_propagate(h: rpr_rhs, d: int, method: int, steps: int, precision: int, dt: float, n_states: int, x_in,
+                  x_out, stream=None) -> int:
+    P = rpr_propagator(int(method), 0, int(steps))
+    return check(lib().rpr_propagate(C.byref(h), int(d), C.byref(P), int(precision), float(dt), int(n_states),
+                                     _ptr(x_in), _ptr(x_out), _stream(stream)))
+
+
+def rpr_randnet_features(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi, stream=None) -> int:
+    return check(lib().rpr_randnet_features(int(M), int(d), int(n), int(activation), float(s), _ptr(A), _ptr(zeta),
+                                            _ptr(X), _ptr(Phi), _stream(stream)))
+
+
+def rpr_ridge_fit(M: int, d: int, n: int, Phi, Y, lam: float, W, stream=None) -> int:
+    return check(lib().rpr_ridge_fit(int(M), int(d), int(n), _ptr(Phi), _ptr(Y), float(lam), _ptr(W),
+                                     _stream(stream)))
+
+
+def rpr_randnet_readout(M: int, d: int, n: int, W, Phi, Yhat, stream=None) -> int:
+    return check(lib().rpr_randnet_readout(int(M), int(d), int(n), _ptr(W), _ptr(Phi), _ptr(Yhat),
+                                           _stream(stream)))
+
+
+def rpr_uniform_pm1(seed: int, first: int, n: int, out, stream=None) -> int:
+    return check(lib().rpr_uniform_pm1(C.c_uint64(seed), C.c_uint64(first), int(n), _ptr(out), _stream(stream)))
+
+
+# ---- plans ---------------------------------------------------------------------
+class Plan:
+    """One IVP solved by RandNet-Parareal (rpr_plan_create / execute / destroy)."""
+
+    def __init__(self, h: rpr_rhs, d: int, t0: float, tN: float, N: int, F=(RPR_RK4, 1), G=(RPR_RK1, 1),
+                 tol: float = 1e-6, M: int = 100, activation: int = RPR_TANH, lam: float = 1e-6,
+                 input_scale: float = 0.0, A=None, zeta=None, seed: int = 0, precision: int = RPR_FP64,
+                 correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0):
+        import numpy as np
+        self.d, self.N = int(d), int(N)
+        self._F = rpr_propagator(int(F[0]), 0, int(F[1]))
+        self._G = rpr_propagator(int(G[0]), 0, int(G[1]))
+        self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale))
+        self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every))
+        self._h = h
+        Ah = zh = None
+        if A is not None:
+            Ah = np.ascontiguousarray(A, dtype=np.float64)
+            zh = np.ascontiguousarray(zeta, dtype=np.float64)
+        self._handle = C.c_void_p()
+        check(lib().rpr_plan_create(C.byref(self._handle), C.byref(h), self.d, float(t0), float(tN), self.N,
+                                    C.byref(self._F), C.byref(self._G), float(tol), C.byref(self._net),
+                                    None if Ah is None else Ah.ctypes.data, None if zh is None else zh.ctypes.data,
+                                    C.c_uint64(seed), C.byref(self._opt)))
+
+    def execute(self, u0, U_out, stream=None) -> int:
+        """u0: cuda float64 tensor (d); U_out: cuda float64 tensor ((N+1) x d)."""
+        return check(lib().rpr_plan_execute(self._handle, _ptr(u0), _ptr(U_out), _stream(stream)),
+                     allow=(RPR_OK, RPR_NOT_CONVERGED))
+
+    def info(self) -> dict:
+        inf = rpr_info()
+        check(lib().rpr_plan_info(self._handle, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in rpr_info._fields_}
+
+    def history(self):
+        import numpy as np
+        L = np.zeros(self.N + 1, dtype=np.int32)
+        ch = np.zeros(self.N + 1)
+        check(lib().rpr_plan_history(self._handle, L.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     ch.ctypes.data_as(C.POINTER(C.c_double)), self.N + 1))
+        K = self.info()["K"]
+        return L[:K + 1], ch[:K + 1]
+
+    def close(self):
+        if self._handle:
+            lib().rpr_plan_destroy(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(h: rpr_rhs, u0, *, t0: float, tN: float, N: int, **kw):
+    """Solve with a fresh plan; returns (U (N+1) x d cuda float64 tensor, info dict)."""
+    import torch
+    d = u0.numel()
+    plan = Plan(h, d, t0, tN, N, **kw)
+    U = torch.empty((N + 1, d), dtype=torch.float64, device=u0.device)
+    plan.execute(u0, U)
+    torch.cuda.synchronize()
+    info = plan.info()
+    info["L_hist"], info["chg_hist"] = plan.history()
+    plan.close()
+    return U, info

@@ -1,0 +1,49 @@
+// chain.h -- launchers of the sequential sweeps and the training-pair kernel
+// (chain.hip).
+#pragma once
+
+#include "common.h"
+#include "randnet.h"
+
+namespace rpr {
+
+enum { CHAIN_SWEEP = 0, CHAIN_RANDNET = 1, CHAIN_PARAREAL = 2 };
+
+template <typename T>
+struct ChainArgs {
+    Geom g;
+    int mode;                  // CHAIN_*
+    int N, M, act;
+    int G_method;
+    long long G_steps;
+    double dtG;
+    double inv_s;              // 1 / input scale
+    double eps;                // tolerance of the stopping rule
+    T *U;                      // (N+1) x d slot states, updated in place
+    const T *Fv;               // (N+1) x d fine values F(U_{i-1}^{k-1}) (row i)
+    T *Gc;                     // (N+1) x d coarse values G(U_{i-1}) (row i)
+    T *gtmp;                   // d: coarse value of the current slot
+    double *phi;               // M: hidden layer of the current slot
+    const double *A, *zeta, *W;
+    double *part;              // (N+1) x grid: per-work-group change maxima
+    Ctrl *ctrl;
+    int *L_hist;               // (N+1)
+    double *chg_hist;          // (N+1)
+};
+
+// Dynamic LDS of the chain kernel for coarse-solver shape sh and M neurons.
+size_t chain_lds(const OnchipShape &sh, int M);
+
+// Cooperative launch of one sweep on nwg work-groups (nwg = 1 for
+// CHAIN_SWEEP).  With max_wg non-null nothing is launched and *max_wg receives
+// the number of work-groups that can be co-resident on the device.
+template <typename T>
+rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,
+                        int *max_wg = nullptr);
+
+// Per right-hand side instance (chain.hip, one object per kind and precision).
+template <int KIND, typename T>
+rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,
+                             int *max_wg);
+
+}  // namespace rpr

@@ -1,0 +1,209 @@
+// common.h -- internal declarations of librpr (not part of the C ABI).
+//
+// Geometry of a state, the per-cell right-hand sides h(u) of the four PDE
+// families, error plumbing and launch helpers shared by the .hip sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "rpr.h"
+
+namespace rpr {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+rpr_status fail(rpr_status st, const std::string &msg);
+rpr_status hip_fail(hipError_t e, const char *what);
+
+#define RPR_HIP(call)                                                      \
+    do {                                                                   \
+        hipError_t e_ = (call);                                            \
+        if (e_ != hipSuccess) return ::rpr::hip_fail(e_, #call);           \
+    } while (0)
+
+// --------------------------------------------------------------- geometry --
+// Kernel-side description of h.  Spacings are folded into reciprocals once on
+// the host; the stencils multiply by them.
+struct Geom {
+    int kind;      // rpr_rhs_kind
+    int nx, ny;    // grid
+    int nc;        // cells = nx * ny
+    int ns;        // species
+    int d;         // ns * nc
+    int periodic;  // 1: wrap, 0: wall (Neumann mirror / reflective)
+    double idx2, idy2;   // 1 / dx^2, 1 / dy^2
+    double i2dx;         // 1 / (2 dx)            (Burgers advection)
+    double idx, idy;     // 1 / dx, 1 / dy         (finite-volume flux differences)
+    double p[6];
+};
+
+inline int nspecies(int kind)
+{
+    switch (kind) {
+    case RPR_BURGERS1D: return 1;
+    case RPR_DIFFREACT2D: return 2;
+    case RPR_BRUSS2D: return 2;
+    case RPR_SWE2D: return 3;
+    default: return 0;
+    }
+}
+
+rpr_status make_geom(const rpr_rhs *h, int32_t d, Geom *g);
+
+// ------------------------------------------------------- right-hand sides --
+// Each function evaluates h at one cell from the cell's own species values
+// `c` and the values of its four neighbours after the boundary rule has been
+// applied (w/e: x - 1, x + 1; s/n: y - 1, y + 1).  Results go to k[species].
+
+// Viscous Burgers, eq. "burg": nu u_xx - u u_x with central differences.
+template <typename T>
+__device__ __forceinline__ void rhs_burgers(const T *c, const T *w, const T *e, T *k, T nu, T idx2,
+                                            T i2dx)
+{
+    const T uxx = (e[0] - T(2) * c[0] + w[0]) * idx2;
+    const T ux = (e[0] - w[0]) * i2dx;
+    k[0] = nu * uxx - c[0] * ux;
+}
+
+// Five-point Laplacian.
+template <typename T>
+__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, T idx2, T idy2)
+{
+    return (w - T(2) * c + e) * idx2 + (s - T(2) * c + n) * idy2;
+}
+
+// FitzHugh-Nagumo diffusion-reaction (Sec. 5.2).
+template <typename T>
+__device__ __forceinline__ void rhs_diffreact(const T *c, const T *w, const T *e, const T *s, const T *n,
+                                              T *k, T Du, T Dv, T cc, T idx2, T idy2)
+{
+    const T u = c[0], v = c[1];
+    const T lu = lap5(u, w[0], e[0], s[0], n[0], idx2, idy2);
+    const T lv = lap5(v, w[1], e[1], s[1], n[1], idx2, idy2);
+    k[0] = Du * lu + (u - u * u * u - cc - v);
+    k[1] = Dv * lv + (u - v);
+}
+
+// Brusselator (App. E).
+template <typename T>
+__device__ __forceinline__ void rhs_bruss(const T *c, const T *w, const T *e, const T *s, const T *n,
+                                          T *k, T A, T B, T Du, T Dv, T idx2, T idy2)
+{
+    const T u = c[0], v = c[1];
+    const T lu = lap5(u, w[0], e[0], s[0], n[0], idx2, idy2);
+    const T lv = lap5(v, w[1], e[1], s[1], n[1], idx2, idy2);
+    const T u2v = u * u * v;
+    k[0] = Du * lu + A - (B + T(1)) * u + u2v;
+    k[1] = Dv * lv + B * u - u2v;
+}
+
+// Shallow water: Rusanov flux across one face; (h, m, n) = depth, momentum
+// normal to the face, momentum along it.
+template <typename T>
+struct SweQ {
+    T h, m, n;
+};
+
+template <typename T>
+__device__ __forceinline__ SweQ<T> rusanov(const SweQ<T> &L, const SweQ<T> &R, T g)
+{
+    const T uL = L.m / L.h, uR = R.m / R.h;
+    const T cL = fabs(uL) + sqrt(g * L.h);
+    const T cR = fabs(uR) + sqrt(g * R.h);
+    const T a = cL > cR ? cL : cR;
+    SweQ<T> F;
+    F.h = T(0.5) * (L.m + R.m) - T(0.5) * a * (R.h - L.h);
+    F.m = T(0.5) * ((L.m * uL + T(0.5) * g * L.h * L.h) + (R.m * uR + T(0.5) * g * R.h * R.h)) -
+          T(0.5) * a * (R.m - L.m);
+    F.n = T(0.5) * (L.n * uL + R.n * uR) - T(0.5) * a * (R.n - L.n);
+    return F;
+}
+
+// Shallow water at one cell.  Species order (h, hu, hv).  A wall neighbour
+// arrives as the cell itself with the wall flag set; its ghost is the mirror
+// image with the normal momentum negated.
+template <typename T>
+__device__ __forceinline__ void rhs_swe(const T *c, const T *w, const T *e, const T *s, const T *n,
+                                        bool ww, bool we, bool ws, bool wn, T *k, T g, T idx, T idy)
+{
+    const SweQ<T> qx{c[0], c[1], c[2]};
+    const SweQ<T> qy{c[0], c[2], c[1]};
+    const SweQ<T> W{w[0], ww ? -w[1] : w[1], w[2]};
+    const SweQ<T> E{e[0], we ? -e[1] : e[1], e[2]};
+    const SweQ<T> S{s[0], ws ? -s[2] : s[2], s[1]};
+    const SweQ<T> N{n[0], wn ? -n[2] : n[2], n[1]};
+    const SweQ<T> Fw = rusanov(W, qx, g), Fe = rusanov(qx, E, g);
+    const SweQ<T> Gs = rusanov(S, qy, g), Gn = rusanov(qy, N, g);
+    k[0] = -(Fe.h - Fw.h) * idx - (Gn.h - Gs.h) * idy;
+    k[1] = -(Fe.m - Fw.m) * idx - (Gn.n - Gs.n) * idy;
+    k[2] = -(Fe.n - Fw.n) * idx - (Gn.m - Gs.m) * idy;
+}
+
+template <int KIND>
+constexpr int kind_ns()
+{
+    return KIND == RPR_BURGERS1D ? 1 : (KIND == RPR_SWE2D ? 3 : 2);
+}
+
+// Dispatch for a compile-time kind.
+template <int KIND, typename T>
+__device__ __forceinline__ void rhs_cell(const Geom &g, const T *c, const T *w, const T *e, const T *s,
+                                         const T *n, bool ww, bool we, bool ws, bool wn, T *k)
+{
+    if constexpr (KIND == RPR_BURGERS1D) {
+        rhs_burgers<T>(c, w, e, k, T(g.p[0]), T(g.idx2), T(g.i2dx));
+    } else if constexpr (KIND == RPR_DIFFREACT2D) {
+        rhs_diffreact<T>(c, w, e, s, n, k, T(g.p[0]), T(g.p[1]), T(g.p[2]), T(g.idx2), T(g.idy2));
+    } else if constexpr (KIND == RPR_BRUSS2D) {
+        rhs_bruss<T>(c, w, e, s, n, k, T(g.p[0]), T(g.p[1]), T(g.p[2]), T(g.p[3]), T(g.idx2), T(g.idy2));
+    } else {
+        rhs_swe<T>(c, w, e, s, n, ww, we, ws, wn, k, T(g.p[0]), T(g.idx), T(g.idy));
+    }
+}
+
+// ---------------------------------------------------- on-chip propagation --
+constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes a work-group may allocate on gfx950
+
+// A slot whose whole state fits in one work-group's LDS is propagated by that
+// work-group; thread t owns a strip of `cpt` consecutive cells (slotprop.h).
+struct OnchipShape {
+    int block;     // threads per work-group
+    int maxt;      // launch bound the kernel instance was built for (512 or 1024)
+    int cpt;       // cells per thread (template instance)
+    int dbuf;      // 1: two LDS stage buffers (one barrier per stage)
+    int full;      // 1: every thread owns a complete strip
+    size_t lds;    // bytes of dynamic LDS
+};
+
+// Fills *sh for a state of geometry g in elements of `elem` bytes; false if
+// the state does not fit one work-group.
+// max_threads (512 or 1024) bounds the work-group: with 512 threads each
+// strip is twice as long and a thread may hold 256 VGPRs instead of 128.
+bool onchip_shape(const Geom &g, size_t elem, OnchipShape *sh, int max_threads = 1024);
+
+// Per right-hand side instance (propagate.hip, one object per kind and precision).
+template <int KIND, typename T>
+rpr_status launch_propagate_kind(const Geom &g, const OnchipShape &sh, int method, int64_t steps, double dt,
+                                 int n, const T *in, T *out, const int *ctrl, hipStream_t st);
+
+// Launch of the on-chip propagator: out[b] = P(in[b]) for b in [0, n), where
+// work-group b skips its state when ctrl != nullptr and b < ctrl[0] (slot
+// b + 1 is already final) or ctrl[2] != 0 (run finished).
+template <typename T>
+rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in,
+                            T *out, const int *ctrl, hipStream_t st, int max_threads = 1024);
+
+// Control block of a plan, in device memory.
+struct Ctrl {
+    int L;           // slots 0..L are final
+    int k;           // iterations done
+    int done;        // 1 once L == N
+    int rows_used;   // finite pairs in the readout
+    int nonfinite;   // dropped pairs
+    int chol_fail;   // failed ridge factorisations
+    int pad[2];
+};
+
+}  // namespace rpr

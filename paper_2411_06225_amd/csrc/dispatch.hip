@@ -1,0 +1,84 @@
+// dispatch.hip -- host-side shape selection and the dispatch from a runtime
+// right-hand-side kind to the per-kind kernel objects.
+#include "chain.h"
+#include "slotprop.h"
+
+namespace rpr {
+
+static int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p *= 2;
+    return p;
+}
+
+bool onchip_shape(const Geom &g, size_t elem, OnchipShape *sh, int max_threads)
+{
+    int cpt, block;
+    if (max_threads != 512) max_threads = 1024;
+    if (g.kind == RPR_BURGERS1D) {
+        cpt = pow2_at_least((g.nc + max_threads - 1) / max_threads);
+        if (cpt < 2 && g.nc >= 128) cpt = 2;
+        block = (g.nc + cpt - 1) / cpt;
+    } else {
+        if (g.nx > max_threads) return false;
+        cpt = 1;
+        while (g.nx * ((g.ny + cpt - 1) / cpt) > max_threads) cpt *= 2;
+        block = g.nx * ((g.ny + cpt - 1) / cpt);
+    }
+    if (cpt > 16) return false;
+    const size_t one = (size_t)padded_elems(g) * elem;
+    if (one > kMaxLds) return false;
+    sh->block = block;
+    sh->maxt = max_threads;
+    sh->cpt = cpt;
+    sh->full = (g.kind == RPR_BURGERS1D ? g.nc : g.ny) % cpt == 0;
+    sh->dbuf = 2 * one <= kMaxLds;
+    sh->lds = sh->dbuf ? 2 * one : one;
+    return true;
+}
+
+template <typename T>
+rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
+                            const int *ctrl, hipStream_t st, int max_threads)
+{
+    if (n <= 0) return RPR_OK;
+    OnchipShape sh;
+    if (!onchip_shape(g, sizeof(T), &sh, max_threads))
+        return fail(RPR_ERR_UNSUPPORTED, "propagate: the state does not fit one work-group's LDS");
+    switch (g.kind) {
+    case RPR_BURGERS1D: return launch_propagate_kind<RPR_BURGERS1D, T>(g, sh, method, steps, dt, n, in, out, ctrl, st);
+    case RPR_DIFFREACT2D: return launch_propagate_kind<RPR_DIFFREACT2D, T>(g, sh, method, steps, dt, n, in, out, ctrl, st);
+    case RPR_BRUSS2D: return launch_propagate_kind<RPR_BRUSS2D, T>(g, sh, method, steps, dt, n, in, out, ctrl, st);
+    case RPR_SWE2D: return launch_propagate_kind<RPR_SWE2D, T>(g, sh, method, steps, dt, n, in, out, ctrl, st);
+    default: return fail(RPR_ERR_INVALID_ARG, "propagate: unknown right-hand side");
+    }
+}
+template rpr_status launch_propagate<double>(const Geom &, int, int64_t, double, int, const double *, double *,
+                                             const int *, hipStream_t, int);
+template rpr_status launch_propagate<float>(const Geom &, int, int64_t, double, int, const float *, float *,
+                                            const int *, hipStream_t, int);
+
+size_t chain_lds(const OnchipShape &sh, int M)
+{
+    // the coarse solver's stage buffers, or the readout's neuron vector and
+    // partial sums, whichever is larger
+    const size_t red = (size_t)(M + 1024 + 64) * sizeof(double);
+    return sh.lds > red ? sh.lds : red;
+}
+
+template <typename T>
+rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st, int *max_wg)
+{
+    switch (a.g.kind) {
+    case RPR_BURGERS1D: return launch_chain_kind<RPR_BURGERS1D, T>(a, sh, nwg, st, max_wg);
+    case RPR_DIFFREACT2D: return launch_chain_kind<RPR_DIFFREACT2D, T>(a, sh, nwg, st, max_wg);
+    case RPR_BRUSS2D: return launch_chain_kind<RPR_BRUSS2D, T>(a, sh, nwg, st, max_wg);
+    case RPR_SWE2D: return launch_chain_kind<RPR_SWE2D, T>(a, sh, nwg, st, max_wg);
+    default: return fail(RPR_ERR_INVALID_ARG, "chain: unknown right-hand side");
+    }
+}
+template rpr_status launch_chain<double>(const ChainArgs<double> &, const OnchipShape &, int, hipStream_t, int *);
+template rpr_status launch_chain<float>(const ChainArgs<float> &, const OnchipShape &, int, hipStream_t, int *);
+
+}  // namespace rpr

@@ -1,0 +1,104 @@
+"""The C-ABI library loads, exports every entry point include/rpr.h declares,
+and rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2411_06225_amd as rpr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    src = open(os.path.join(ROOT, "include", "rpr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)  # drop comments
+    return sorted(set(re.findall(r"\b(rpr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_entry_points() == sorted(rpr.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", rpr.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\sT\s(rpr_\w+)", out.stdout))
+    assert set(declared_entry_points()) <= exported
+    # nothing but the C ABI leaves the library
+    assert exported == set(declared_entry_points())
+    L = rpr.lib()
+    for name in declared_entry_points():
+        assert getattr(L, name) is not None
+
+
+def test_version_string():
+    assert rpr.lib().rpr_version().decode().startswith("rpr ")
+
+
+def _prop(method=4, steps=10):
+    return rpr.rpr_propagator(method, 0, steps)
+
+
+@pytest.mark.parametrize("kind,nx,ny,d,msg", [
+    (0, 64, 1, 63, "d must equal"),
+    (0, 64, 2, 128, "ny == 1"),
+    (1, 8, 8, 100, "d must equal"),
+    (9, 8, 8, 128, "kind"),
+    (2, 0, 8, 0, "nx"),
+])
+def test_propagate_rejects_bad_problem(kind, nx, ny, d, msg):
+    h = rpr.make_rhs(kind, nx, ny)
+    st = rpr.lib().rpr_propagate(C.byref(h), d, C.byref(_prop()), 0, 1e-3, 1, 1 << 20, 1 << 30, None)
+    assert st == rpr.RPR_ERR_INVALID_ARG
+    assert msg in rpr.last_error()
+
+
+def test_propagate_rejects_bad_propagator_and_overlap():
+    h = rpr.make_rhs(0, 64)
+    L = rpr.lib()
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(method=2)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(steps=0)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 5, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    # in and out overlapping
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 0, 1e-3, 2, 4096, 4096 + 512, None) == -1
+    assert "overlap" in rpr.last_error()
+
+
+def test_plan_create_rejects_bad_options():
+    h = rpr.make_rhs(0, 32)
+    F, G = _prop(4, 10), _prop(1, 2)
+    net = rpr.rpr_randnet(10, 0, 1e-6, 0.0)
+    L = rpr.lib()
+    handle = C.c_void_p()
+
+    def create(d=32, t0=0.0, tN=1.0, N=4, tol=1e-6, net_=net, opt=None):
+        opt = opt or rpr.rpr_options(0, 0, 0, 0)
+        return L.rpr_plan_create(C.byref(handle), C.byref(h), d, t0, tN, N, C.byref(F), C.byref(G), tol,
+                                 C.byref(net_), None, None, 0, C.byref(opt))
+
+    assert create(N=0) == -1
+    assert create(tN=0.0) == -1
+    assert create(tol=float("nan")) == -1
+    assert create(net_=rpr.rpr_randnet(0, 0, 1e-6, 0.0)) == -1
+    assert create(net_=rpr.rpr_randnet(10, 0, 0.0, 0.0)) == -1
+    assert create(net_=rpr.rpr_randnet(10, 7, 1e-6, 0.0)) == -1
+    assert create(opt=rpr.rpr_options(3, 0, 0, 0)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 9, 0)) == -1
+    assert handle.value is None
+
+
+def test_destroy_accepts_null():
+    assert rpr.lib().rpr_plan_destroy(None) == rpr.RPR_OK
+
+
+def test_building_blocks_reject_bad_sizes():
+    L = rpr.lib()
+    assert L.rpr_randnet_features(0, 4, 1, 0, 1.0, 1, 2, 3, 4, None) == -1
+    assert L.rpr_randnet_features(4, 4, 1, 0, 0.0, 1, 2, 3, 4, None) == -1
+    assert L.rpr_ridge_fit(4, 4, 1, 1, 2, 0.0, 3, None) == -1
+    assert L.rpr_ridge_fit(4000, 4, 1, 1, 2, 1e-3, 3, None) == -1
+    assert L.rpr_uniform_pm1(0, 0, -1, 1, None) == -1
+    # zero-sized work is a no-op that needs no device
+    assert L.rpr_randnet_readout(4, 4, 0, 1, 2, 3, None) == rpr.RPR_OK

@@ -1,0 +1,175 @@
+"""GPU parity: every building block of librpr against the CPU oracle, through the C ABI.
+
+Sizes span several work-group tiles and ragged tails; the workload shapes
+(64 x 64 diffusion-reaction, 64 x 64 Brusselator, Burgers d = 128 and 4096)
+use the kernel instances the benchmark runs.
+
+Tolerances (relative to the largest magnitude of the reference):
+  - propagators, FP64: 1e-12.  Both sides evaluate the same formulas; they
+    differ only in rounding (reciprocal multiplies vs divides, fused
+    multiply-adds), a few ulps per step that do not grow on these stable runs.
+  - propagators, FP32 states: 2e-5 after the given number of steps (unit
+    roundoff 6e-8 times the step count, bounded by the test's measurement).
+  - features and readout: 1e-13 (a sum of d or M products).
+  - ridge readout: max(1e-12, 10 kappa 2^-53), kappa = cond(Phi^T Phi + lambda I),
+    the forward-error bound of a backward-stable Cholesky solve.
+  - generator: bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2411_06225_amd as rpr  # noqa: E402
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# (kind, nx, ny, domain, params, steps, dt, method) -- stable step sizes
+PROP_CASES = [
+    ("burgers_d128", rpr.RPR_BURGERS1D, 128, 1, (-1, 1, -1, 1), (0.01,), 300, 1.5e-4, 4),
+    ("burgers_d100_ragged", rpr.RPR_BURGERS1D, 100, 1, (-1, 1, -1, 1), (0.02,), 300, 1.5e-4, 4),
+    ("burgers_d1000", rpr.RPR_BURGERS1D, 1000, 1, (-1, 1, -1, 1), (0.002,), 100, 2e-5, 4),
+    ("burgers_d4096", rpr.RPR_BURGERS1D, 4096, 1, (-1, 1, -1, 1), (0.001,), 50, 2e-6, 4),
+    ("burgers_rk1", rpr.RPR_BURGERS1D, 128, 1, (-1, 1, -1, 1), (0.01,), 40, 2e-3, 1),
+    ("diffreact_64x64", rpr.RPR_DIFFREACT2D, 64, 64, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 200, 7.8125e-5, 4),
+    ("diffreact_13x9", rpr.RPR_DIFFREACT2D, 13, 9, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 200, 1e-3, 4),
+    ("diffreact_32x32_rk1", rpr.RPR_DIFFREACT2D, 32, 32, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 20, 0.01, 1),
+    ("diffreact_40x70", rpr.RPR_DIFFREACT2D, 40, 70, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 100, 1e-3, 4),
+    ("bruss_64x64", rpr.RPR_BRUSS2D, 64, 64, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 200, 2e-4, 4),
+    ("bruss_20x16", rpr.RPR_BRUSS2D, 20, 16, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 200, 1e-3, 4),
+    ("swe_24x16", rpr.RPR_SWE2D, 24, 16, (0, 1, 0, 1), (9.81,), 200, 5e-4, 4),
+    ("swe_8x40_rk1", rpr.RPR_SWE2D, 8, 40, (0, 1, 0, 1), (9.81,), 50, 2e-4, 1),
+]
+
+
+def initial_state(kind, nx, ny, rng):
+    nc = nx * ny
+    if kind == rpr.RPR_BURGERS1D:
+        x = -1 + 2 * np.arange(nx) / nx
+        return 0.5 * np.sin(np.pi * x) + 0.3 * np.cos(3 * np.pi * x) + 0.05 * rng.standard_normal(nx)
+    if kind == rpr.RPR_DIFFREACT2D:
+        return rng.standard_normal(2 * nc)
+    if kind == rpr.RPR_BRUSS2D:
+        return np.concatenate([1 + 0.1 * rng.uniform(-1, 1, nc), 3 + 0.1 * rng.uniform(-1, 1, nc)])
+    h = 1 + 0.1 * rng.random(nc)
+    return np.concatenate([h, 0.05 * rng.standard_normal(nc), 0.05 * rng.standard_normal(nc)])
+
+
+@pytest.mark.parametrize("case", PROP_CASES, ids=[c[0] for c in PROP_CASES])
+def test_propagate_fp64_matches_oracle(orc, case):
+    name, kind, nx, ny, dom, params, steps, dt, method = case
+    rng = np.random.default_rng(abs(hash(name)) % 2 ** 32)
+    d = rpr.nspecies(kind) * nx * ny
+    n = 3
+    X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(n)])
+    pb = orc.problem(kind, nx, ny, dom, params)
+    ref = orc.propagate_many(pb, method, steps, dt, X)
+    xin, xout = dev(X), torch.empty((n, d), dtype=torch.float64, device="cuda")
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, dom, params), d, method, steps, rpr.RPR_FP64, dt, n, xin, xout)
+    got = host(xout)
+    print(name, "rel err %.2e" % rel_err(got, ref))
+    assert np.all(np.isfinite(got))
+    assert rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("case", [c for c in PROP_CASES if c[0] in ("burgers_d128", "diffreact_64x64", "bruss_64x64",
+                                                                    "swe_24x16", "diffreact_13x9")],
+                         ids=lambda c: c[0])
+def test_propagate_fp32_states_close_to_fp64_oracle(orc, case):
+    name, kind, nx, ny, dom, params, steps, dt, method = case
+    rng = np.random.default_rng(7)
+    d = rpr.nspecies(kind) * nx * ny
+    X = initial_state(kind, nx, ny, rng)[None]
+    pb = orc.problem(kind, nx, ny, dom, params)
+    ref = orc.propagate_many(pb, method, steps, dt, X)
+    xin, xout = dev(X, torch.float32), torch.empty((1, d), dtype=torch.float32, device="cuda")
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, dom, params), d, method, steps, rpr.RPR_MIXED, dt, 1, xin, xout)
+    err = rel_err(host(xout), ref)
+    print(name, "fp32 rel err %.2e" % err)
+    assert err <= 2e-5
+
+
+def test_propagate_many_states_is_batched_identically(orc):
+    # every state of a batch goes through the same kernel: equal inputs give bitwise equal outputs
+    kind, nx, ny = rpr.RPR_DIFFREACT2D, 64, 64
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(2 * nx * ny)
+    X = np.stack([x] * 5)
+    xin, xout = dev(X), torch.empty((5, X.shape[1]), dtype=torch.float64, device="cuda")
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, params=(1e-3, 5e-3, 5e-3)), X.shape[1], 4, 50, rpr.RPR_FP64,
+                      1e-4, 5, xin, xout)
+    got = host(xout)
+    for r in range(1, 5):
+        np.testing.assert_array_equal(got[r], got[0])
+
+
+def test_bruss_fixed_point_exact_on_gpu():
+    nx = ny = 64
+    u = np.concatenate([np.full(nx * ny, 1.0), np.full(nx * ny, 3.0)])[None]
+    xin, xout = dev(u), torch.empty_like(dev(u))
+    rpr.rpr_propagate(rpr.make_rhs(rpr.RPR_BRUSS2D, nx, ny, params=(1.0, 3.0, 0.02, 0.01)), u.shape[1], 4, 100,
+                      rpr.RPR_FP64, 1e-3, 1, xin, xout)
+    np.testing.assert_array_equal(host(xout), u)
+
+
+@pytest.mark.parametrize("n,M,d,act", [(37, 50, 300, 0), (64, 200, 8192, 1), (5, 13, 1000, 0), (1, 3, 7, 1)])
+def test_features_match_oracle(orc, n, M, d, act):
+    rng = np.random.default_rng(n + M + d)
+    A = rng.uniform(-1, 1, (M, d))
+    zeta = rng.uniform(-1, 1, M)
+    X = rng.standard_normal((n, d))
+    s = 4.0
+    ref = orc.features(orc.Net(A, zeta, act, 0.0, s), X)
+    Phi = torch.empty((n, M), dtype=torch.float64, device="cuda")
+    rpr.rpr_randnet_features(M, d, n, act, s, dev(A), dev(zeta), dev(X), Phi)
+    err = rel_err(host(Phi), ref)
+    print("features", n, M, d, "rel err %.2e" % err)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("n,M,d", [(40, 30, 77), (12, 100, 128), (300, 200, 1000), (1, 5, 3)])
+def test_ridge_fit_matches_oracle(orc, n, M, d):
+    rng = np.random.default_rng(n * M)
+    Phi = np.tanh(rng.standard_normal((n, M)))
+    Y = rng.standard_normal((n, d))
+    lam = 1e-3
+    ref = orc.ridge_fit(Phi, Y, lam)
+    W = torch.empty((M, d), dtype=torch.float64, device="cuda")
+    rpr.rpr_ridge_fit(M, d, n, dev(Phi), dev(Y), lam, W)
+    kappa = np.linalg.cond(Phi.T @ Phi + lam * np.eye(M))
+    tol = max(1e-12, 10 * kappa * 2.0 ** -53)
+    err = rel_err(host(W), ref)
+    print("ridge", n, M, d, "kappa %.1e rel err %.2e tol %.1e" % (kappa, err, tol))
+    assert err <= tol
+
+
+def test_readout_matches_oracle_formula():
+    rng = np.random.default_rng(11)
+    M, d, n = 30, 77, 9
+    W = rng.standard_normal((M, d))
+    Phi = rng.standard_normal((n, M))
+    out = torch.empty((n, d), dtype=torch.float64, device="cuda")
+    rpr.rpr_randnet_readout(M, d, n, dev(W), dev(Phi), out)
+    assert rel_err(host(out), Phi @ W) <= 1e-13
+
+
+def test_uniform_generator_bitwise(orc):
+    for seed, first, n in [(0, 0, 1000), (12345, 7, 100003)]:
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        rpr.rpr_uniform_pm1(seed, first, n, out)
+        np.testing.assert_array_equal(host(out), orc.uniform_pm1(seed, first, n))
