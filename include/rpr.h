@@ -88,7 +88,7 @@ typedef struct {
 typedef enum { RPR_TANH = 0, RPR_RELU = 1 } rpr_activation;
 
 typedef struct {
-    int32_t M;                 /* hidden neurons, 1 <= M <= 1024 */
+    int32_t M;                 /* hidden neurons, 1 <= M <= 512 */
     int32_t activation;        /* rpr_activation (the paper uses ReLU, Sec. 4) */
     double lambda;             /* ridge penalty of eq. "ridgeless" (> 0) */
     double input_scale;        /* the network sees x / s; <= 0 selects the default:
@@ -97,9 +97,11 @@ typedef struct {
 
 typedef enum {
     RPR_FP64 = 0,              /* every step in double precision */
-    RPR_MIXED = 1              /* F and G in single precision; features, Gram and
-                                  readout statistics accumulated in double; ridge
-                                  Cholesky and convergence norm in double */
+    RPR_MIXED = 1              /* slot states, F and G in single precision (state
+                                  updates compensated); hidden layer in bfloat16
+                                  with single-precision sums on the matrix cores;
+                                  Gram and readout statistics, ridge Cholesky and
+                                  convergence norm in double */
 } rpr_precision;
 
 typedef enum {
@@ -194,6 +196,18 @@ rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propagator *P, i
 rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
                                 const double *A, const double *zeta, const double *X, double *Phi,
                                 void *stream);
+
+/*
+ * Reduced-precision features, the recipe of RPR_MIXED plans: x/s and A rounded
+ * to bfloat16 (round to nearest even), products summed in single precision on
+ * the matrix cores, zeta added and sigma applied in single precision, result
+ * rounded to bfloat16 and returned as doubles.
+ *   A (M x d, doubles), zeta (M, doubles), X (n x d, floats), Phi (n x M,
+ *   doubles): device pointers.  Allocates and frees its own workspace.
+ */
+rpr_status rpr_randnet_features_bf16(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
+                                     const double *A, const double *zeta, const float *X, double *Phi,
+                                     void *stream);
 
 /*
  * Ridge readout of eq. "ridgeless" at penalty lambda:

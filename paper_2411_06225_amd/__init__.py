@@ -32,7 +32,7 @@ RPR_CORR_RANDNET, RPR_CORR_PARAREAL = 0, 1
 
 EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
             "rpr_plan_history", "rpr_plan_destroy", "rpr_propagate", "rpr_randnet_features", "rpr_ridge_fit",
-            "rpr_randnet_readout", "rpr_uniform_pm1")
+            "rpr_randnet_readout", "rpr_uniform_pm1", "rpr_randnet_features_bf16")
 
 
 class RprError(RuntimeError):
@@ -91,6 +91,7 @@ def lib() -> C.CDLL:
             "rpr_propagate": (i32, [C.POINTER(rpr_rhs), i32, C.POINTER(rpr_propagator), i32, dbl, i32, vp, vp,
                                     vp]),
             "rpr_randnet_features": (i32, [i32, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
+            "rpr_randnet_features_bf16": (i32, [i32, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
             "rpr_ridge_fit": (i32, [i32, i32, i32, vp, vp, dbl, vp, vp]),
             "rpr_randnet_readout": (i32, [i32, i32, i32, vp, vp, vp, vp]),
             "rpr_uniform_pm1": (i32, [u64, u64, i64, vp, vp]),
@@ -150,6 +151,12 @@ def rpr_propagate(h: rpr_rhs, d: int, method: int, steps: int, precision: int, d
 def rpr_randnet_features(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi, stream=None) -> int:
     return check(lib().rpr_randnet_features(int(M), int(d), int(n), int(activation), float(s), _ptr(A), _ptr(zeta),
                                             _ptr(X), _ptr(Phi), _stream(stream)))
+
+
+def rpr_randnet_features_bf16(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi,
+                              stream=None) -> int:
+    return check(lib().rpr_randnet_features_bf16(int(M), int(d), int(n), int(activation), float(s), _ptr(A),
+                                                 _ptr(zeta), _ptr(X), _ptr(Phi), _stream(stream)))
 
 
 def rpr_ridge_fit(M: int, d: int, n: int, Phi, Y, lam: float, W, stream=None) -> int:

@@ -191,6 +191,8 @@ struct rpr_plan {
            *Lt = nullptr, *Bm = nullptr, *W = nullptr, *phi = nullptr, *part = nullptr, *chg_hist = nullptr,
            *u0max = nullptr;
     int *ok = nullptr, *nrows = nullptr, *L_hist = nullptr, *cfail = nullptr, *u0bad = nullptr;
+    uint16_t *Ab = nullptr;   // bf16 copy of A (reduced precision)
+    float *fpart32 = nullptr; // split-K partials of the bf16 feature GEMM
     Ctrl *ctrl = nullptr;
     Ctrl *ctrl_host = nullptr;  // pinned
     OnchipShape shF{}, shG{};
@@ -205,7 +207,7 @@ static void plan_free(rpr_plan *p)
 {
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
                     p->Lt, p->Bm, p->W, p->phi, p->part, p->chg_hist, p->u0max, p->ok, p->nrows, p->L_hist,
-                    p->cfail, p->u0bad, p->ctrl};
+                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->ctrl_host) (void)hipHostFree(p->ctrl_host);
@@ -267,8 +269,13 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
         } else {
             RPR_TRY(launch_uniform(seed, 0, (int64_t)M * d, p->A, nullptr));
             RPR_TRY(launch_uniform(seed, (uint64_t)M * d, M, p->zeta, nullptr));
-            RPR_HIP(hipDeviceSynchronize());
         }
+        if (p->prec == RPR_MIXED) {
+            RPR_TRY(dalloc(&p->Ab, (size_t)M * d));
+            RPR_TRY(dalloc(&p->fpart32, (size_t)feat_bf16_splits(d) * N * M));
+            RPR_TRY(launch_to_bf16(p->A, p->Ab, (size_t)M * d, nullptr));
+        }
+        RPR_HIP(hipDeviceSynchronize());
     }
     void *h = nullptr;
     RPR_HIP(hipHostMalloc(&h, sizeof(Ctrl), hipHostMallocDefault));
@@ -436,6 +443,7 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     a.A = p->A;
     a.zeta = p->zeta;
     a.W = p->W;
+    a.Ab = p->Ab;
     a.part = p->part;
     a.ctrl = p->ctrl;
     a.L_hist = p->L_hist;
@@ -458,8 +466,12 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
             if (net) {
                 T *X = static_cast<T *>(p->X), *Y = static_cast<T *>(p->Y);
                 RPR_TRY(launch_pairs<T>(N, d, U, Fv, Gc, X, Y, p->ok, p->nrows, p->ctrl, st));
-                RPR_TRY(launch_features<T>(N, M, d, p->act, 1.0 / s, p->A, p->zeta, X, p->Phi, p->fpart, p->nrows,
-                                           st));
+                if (p->Ab)
+                    RPR_TRY(launch_features_bf16<T>(N, M, d, p->act, 1.0 / s, p->Ab, p->zeta, X, p->Phi, p->fpart32,
+                                                    p->nrows, st));
+                else
+                    RPR_TRY(launch_features<T>(N, M, d, p->act, 1.0 / s, p->A, p->zeta, X, p->Phi, p->fpart,
+                                               p->nrows, st));
                 RPR_TRY(launch_stats<T>(N, M, d, p->Phi, Y, p->ok, p->Gm, p->Bm, p->nrows, st));
                 RPR_TRY(launch_ridge_solve(M, d, p->Gm, p->lambda, p->Lf, p->Lt, p->W, p->Bm, p->cfail,
                                            &p->ctrl->chol_fail, &p->ctrl->done, st));
@@ -565,6 +577,28 @@ extern "C" rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int3
     double *part = nullptr;
     RPR_HIP(hipMallocAsync((void **)&part, sizeof(double) * feat_splits(d) * n * M, st));
     const rpr_status rc = launch_features<double>(n, M, d, activation, 1.0 / s, A, zeta, X, Phi, part, nullptr, st);
+    RPR_HIP(hipFreeAsync(part, st));
+    return rc;
+}
+
+extern "C" rpr_status rpr_randnet_features_bf16(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
+                                                const double *A, const double *zeta, const float *X, double *Phi,
+                                                void *stream)
+{
+    if (M < 1 || d < 1 || n < 0) return fail(RPR_ERR_INVALID_ARG, "need M >= 1, d >= 1, n >= 0");
+    if (activation != RPR_TANH && activation != RPR_RELU) return fail(RPR_ERR_INVALID_ARG, "bad activation");
+    if (!(s > 0) || !is_finite(s)) return fail(RPR_ERR_INVALID_ARG, "s must be > 0");
+    if (n == 0) return RPR_OK;
+    if (!A || !zeta || !X || !Phi) return fail(RPR_ERR_INVALID_ARG, "NULL device pointer");
+    RPR_TRY(check_device());
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint16_t *Ab = nullptr;
+    float *part = nullptr;
+    RPR_HIP(hipMallocAsync((void **)&Ab, sizeof(uint16_t) * (size_t)M * d, st));
+    RPR_HIP(hipMallocAsync((void **)&part, sizeof(float) * feat_bf16_splits(d) * n * M, st));
+    rpr_status rc = launch_to_bf16(A, Ab, (size_t)M * d, st);
+    if (rc == RPR_OK) rc = launch_features_bf16<float>(n, M, d, activation, 1.0 / s, Ab, zeta, X, Phi, part, nullptr, st);
+    RPR_HIP(hipFreeAsync(Ab, st));
     RPR_HIP(hipFreeAsync(part, st));
     return rc;
 }

@@ -25,6 +25,7 @@ struct ChainArgs {
     T *gtmp;                   // d: coarse value of the current slot
     double *phi;               // M: hidden layer of the current slot
     const double *A, *zeta, *W;
+    const uint16_t *Ab;        // bf16 copy of A (reduced-precision plans), else null
     double *part;              // (N+1) x grid: per-work-group change maxima
     Ctrl *ctrl;
     int *L_hist;               // (N+1)

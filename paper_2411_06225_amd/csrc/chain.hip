@@ -42,6 +42,20 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
+// Same for floats (reduced-precision hidden layer).
+__device__ __forceinline__ float block_sum_f(float v, float *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float s = 0.0f;
+    const int nw = (blockDim.x + 63) / 64;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
 __device__ __forceinline__ double nan_max(double a, double b)
 {
     if (a != a) a = INFINITY;
@@ -96,11 +110,23 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
         if (net && (wg > 0 || nwg == 1)) {
             const int first = nwg == 1 ? 0 : wg - 1, step = nwg == 1 ? 1 : nwg - 1;
             for (int m = first; m < a.M; m += step) {
-                const double *Am = a.A + (size_t)m * d;
-                double part = 0.0;
-                for (int j = t; j < d; j += B) part = fma(Am[j], double(x[j]) * a.inv_s, part);
-                const double z = block_sum(part, scratch) + a.zeta[m];
-                if (t == 0) a.phi[m] = a.act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
+                if (a.Ab != nullptr) {
+                    // reduced precision: bf16 weights and inputs, FP32 sums and sigma, bf16 output
+                    const uint16_t *Am = a.Ab + (size_t)m * d;
+                    const float xs = (float)a.inv_s;
+                    float part = 0.0f;
+                    for (int j = t; j < d; j += B)
+                        part = fmaf(from_bf16(Am[j]), from_bf16(to_bf16(float(x[j]) * xs)), part);
+                    const float z = block_sum_f(part, reinterpret_cast<float *>(scratch)) + (float)a.zeta[m];
+                    const float sg = a.act == RPR_RELU ? (z > 0.0f ? z : 0.0f) : tanhf(z);
+                    if (t == 0) a.phi[m] = (double)from_bf16(to_bf16(sg));
+                } else {
+                    const double *Am = a.A + (size_t)m * d;
+                    double part = 0.0;
+                    for (int j = t; j < d; j += B) part = fma(Am[j], double(x[j]) * a.inv_s, part);
+                    const double z = block_sum(part, scratch) + a.zeta[m];
+                    if (t == 0) a.phi[m] = a.act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
+                }
             }
         }
         grid.sync();

@@ -163,6 +163,18 @@ __device__ __forceinline__ void rhs_cell(const Geom &g, const T *c, const T *w, 
     }
 }
 
+// --------------------------------------------------------------- bfloat16 --
+// Round a float to bfloat16 with round-to-nearest-even (NaN kept quiet).
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)(u >> 16);  // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
 // ---------------------------------------------------- on-chip propagation --
 constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes a work-group may allocate on gfx950
 

@@ -88,6 +88,129 @@ template rpr_status launch_features<double>(int, int, int, int, double, const do
 template rpr_status launch_features<float>(int, int, int, int, double, const double *, const double *,
                                            const float *, double *, double *, const int *, hipStream_t);
 
+// ------------------------------------------------- reduced-precision features ---
+// Mixed-precision hidden layer: inputs x/s and weights rounded to bfloat16
+// (round to nearest even), products accumulated in FP32 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), zeta and sigma in FP32, result rounded to bf16
+// and stored as a double (exactly representable) for the FP64 statistics.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__global__ void k_to_bf16(const double *__restrict__ in, uint16_t *__restrict__ out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = to_bf16((float)in[i]);
+}
+
+rpr_status launch_to_bf16(const double *in, uint16_t *out, size_t n, hipStream_t st)
+{
+    if (n == 0) return RPR_OK;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+    RPR_HIP(hipGetLastError());
+    return RPR_OK;
+}
+
+// Work-group tile: 64 rows of X x 64 neurons, 4 waves; wave w owns rows
+// 16w..16w+15 and all four 16-neuron tiles.  K advances 32 at a time through
+// LDS.  Operand layout of the 16x16x32 instruction: lane l holds A[l%16][8(l/16)..+7],
+// B[8(l/16)..+7][l%16], and D[4(l/16)+e][l%16], e = 0..3.
+constexpr int BT = 64, BK = 32, BKP = 40;  // LDS row pitch 80 B keeps 16-byte alignment
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, int kchunk,
+                                                           const TX *__restrict__ X,
+                                                           const uint16_t *__restrict__ Ab, float xs,
+                                                           float *__restrict__ part,
+                                                           const int *__restrict__ nrows_dev)
+{
+    const int nr = nrows_dev ? *nrows_dev : n;
+    const int r0 = blockIdx.x * BT, m0 = blockIdx.y * BT;
+    if (r0 >= nr) return;
+    const int k0 = blockIdx.z * kchunk, k1 = min(d, k0 + kchunk);
+    __shared__ __align__(16) uint16_t Xs[BT][BKP], As[BT][BKP];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int lr = t >> 2, lk = (t & 3) * 8;  // loader: row, first k of 8
+    f32x4_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int kb = k0; kb < k1; kb += BK) {
+        {
+            const int r = r0 + lr, m = m0 + lr;
+            uint16_t xv[8], av[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = kb + lk + e;
+                const bool kin = k < k1;
+                xv[e] = (r < nr && kin) ? to_bf16(float(X[(size_t)r * d + k]) * xs) : (uint16_t)0;
+                av[e] = (m < M && kin) ? Ab[(size_t)m * d + k] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                Xs[lr][lk + e] = xv[e];
+                As[lr][lk + e] = av[e];
+            }
+        }
+        __syncthreads();
+        const uint4 a4 = *reinterpret_cast<const uint4 *>(&Xs[w * 16 + (lane & 15)][8 * (lane >> 4)]);
+        const bf16x8_t a = __builtin_bit_cast(bf16x8_t, a4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4 b4 = *reinterpret_cast<const uint4 *>(&As[j * 16 + (lane & 15)][8 * (lane >> 4)]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8_t, b4), acc[j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = r0 + w * 16 + 4 * (lane >> 4) + e, m = m0 + j * 16 + (lane & 15);
+            if (r < nr && m < M) part[((size_t)blockIdx.z * n + r) * M + m] = acc[j][e];
+        }
+}
+
+__global__ void k_feat_bf16_finish(int n, int M, int nsplit, const float *__restrict__ part,
+                                   const double *__restrict__ zeta, int act, double *__restrict__ Phi,
+                                   const int *__restrict__ nrows_dev)
+{
+    const int nr = nrows_dev ? *nrows_dev : n;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr * M) return;
+    float z = 0.0f;
+    for (int s = 0; s < nsplit; ++s) z += part[(size_t)s * n * M + i];
+    z += (float)zeta[i % M];
+    const float sg = act == RPR_RELU ? (z > 0.0f ? z : 0.0f) : tanhf(z);
+    Phi[i] = (double)from_bf16(to_bf16(sg));
+}
+
+int feat_bf16_splits(int d)
+{
+    int s = (d + 2047) / 2048;  // about 2048 of K per work-group
+    return s < 1 ? 1 : (s > 64 ? 64 : s);
+}
+
+template <typename TX>
+rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, const uint16_t *Ab,
+                                const double *zeta, const TX *X, double *Phi, float *part,
+                                const int *nrows_dev, hipStream_t st)
+{
+    if (n <= 0) return RPR_OK;
+    const int ns = feat_bf16_splits(d);
+    const int kchunk = ((d + ns - 1) / ns + BK - 1) / BK * BK;
+    dim3 grid((n + BT - 1) / BT, (M + BT - 1) / BT, ns);
+    hipLaunchKernelGGL(k_feat_bf16_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, (float)inv_s,
+                       part, nrows_dev);
+    RPR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_feat_bf16_finish, dim3((n * M + 255) / 256), dim3(256), 0, st, n, M, ns, part, zeta,
+                       act, Phi, nrows_dev);
+    RPR_HIP(hipGetLastError());
+    return RPR_OK;
+}
+template rpr_status launch_features_bf16<float>(int, int, int, int, double, const uint16_t *, const double *,
+                                                const float *, double *, float *, const int *, hipStream_t);
+template rpr_status launch_features_bf16<double>(int, int, int, int, double, const uint16_t *, const double *,
+                                                 const double *, double *, float *, const int *, hipStream_t);
+
 // ----------------------------------------------------------- statistics ---
 // G[a][b] += sum_r ok_r Phi[r][a] Phi[r][b]; rows in order r = 0..n-1.
 __global__ __launch_bounds__(256) void k_gram(int n, int M, const double *__restrict__ Phi,

@@ -102,7 +102,12 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
         }
     }
 
-    T u[CPT][NS], acc[CPT][NS], y[CPT][NS];
+    // In single precision the state update u += dt * (...) is compensated
+    // (Kahan summation): the increments are ~1e-4 of the state, so plain
+    // FP32 adds would lose their low bits every step.  cmp holds the running
+    // compensation.  Double precision uses the plain update.
+    constexpr bool KAHAN = sizeof(T) == 4;
+    T u[CPT][NS], acc[CPT][NS], y[CPT][NS], cmp[KAHAN ? CPT : 1][NS];
     auto publish = [&](T *buf, const int c) {
         const int pi = pbase0 + c * pstride;
         // in 1D only the strip ends are read by other threads
@@ -126,6 +131,7 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
                 u[c][sp] = src[sp * nc + cell0 + c * gstride];
                 acc[c][sp] = T(0);
                 y[c][sp] = u[c][sp];
+                if constexpr (KAHAN) cmp[c][sp] = T(0);
             }
             publish(buf0, c);
         }
@@ -172,11 +178,16 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
                     } else if (which == 3) {
                         acc[c][sp] = acc[c][sp] + T(2) * k[sp];
                         nxt = u[c][sp] + dt * k[sp];
-                    } else if (which == 4) {
-                        u[c][sp] = u[c][sp] + dt6 * (acc[c][sp] + k[sp]);
-                        nxt = u[c][sp];
                     } else {
-                        u[c][sp] = u[c][sp] + dt * k[sp];
+                        const T inc = which == 4 ? dt6 * (acc[c][sp] + k[sp]) : dt * k[sp];
+                        if constexpr (KAHAN) {
+                            const T yk = inc - cmp[c][sp];
+                            const T un = u[c][sp] + yk;
+                            cmp[c][sp] = (un - u[c][sp]) - yk;
+                            u[c][sp] = un;
+                        } else {
+                            u[c][sp] = u[c][sp] + inc;
+                        }
                         nxt = u[c][sp];
                     }
                     y[c][sp] = nxt;

@@ -173,3 +173,28 @@ def test_uniform_generator_bitwise(orc):
         out = torch.empty(n, dtype=torch.float64, device="cuda")
         rpr.rpr_uniform_pm1(seed, first, n, out)
         np.testing.assert_array_equal(host(out), orc.uniform_pm1(seed, first, n))
+
+
+@pytest.mark.parametrize("n,M,d,act", [(64, 200, 8192, 1), (37, 50, 300, 0), (5, 13, 1000, 0), (130, 70, 96, 1)])
+def test_bf16_features_match_emulated_oracle(orc, n, M, d, act):
+    # Same recipe on both sides (bf16 inputs and weights, FP32 sums, FP32 sigma,
+    # bf16 result).  The matrix cores sum in their own order, so z may differ by
+    # the FP32 summation error (<= d 2^-24 sum |a x|) and the final bf16 rounding
+    # may land one bf16 ulp (2^-8 relative) apart.
+    rng = np.random.default_rng(n * 7 + d)
+    A = rng.uniform(-1, 1, (M, d))
+    zeta = rng.uniform(-1, 1, M)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    s = 4.0
+    ref = orc.features_bf16(orc.Net(A, zeta, act, 0.0, s), X)
+    Phi = torch.empty((n, M), dtype=torch.float64, device="cuda")
+    rpr.rpr_randnet_features_bf16(M, d, n, act, s, dev(A), dev(zeta), dev(X, torch.float32), Phi)
+    got = host(Phi)
+    # outputs are bfloat16 numbers
+    np.testing.assert_array_equal(got, np.vectorize(orc.bf16_rne)(got))
+    zsum = np.abs(A).sum(axis=1).max() * np.abs(X / s).max()
+    tol = 2.0 ** -7 * np.abs(ref) + d * 2.0 ** -24 * zsum
+    bad = np.abs(got - ref) > tol
+    print("bf16 features", n, M, d, "max |diff| %.2e, flipped %d of %d" % (np.abs(got - ref).max(),
+                                                                            int((got != ref).sum()), ref.size))
+    assert not bad.any()
