@@ -73,7 +73,7 @@ def main():
 
     def make_plan(prec):
         return rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
-                        A=A, zeta=zeta, precision=prec, correction=rpr.RPR_CORR_RANDNET)
+                        A=A, zeta=zeta, precision=prec, correction=rpr.RPR_CORR_RANDNET, autotune=1)
 
     def timed_solves(plan, steps, warmup):
         U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)

@@ -110,12 +110,29 @@ typedef enum {
     RPR_CORR_PARAREAL = 1      /* eq. "fpara": (F - G)(U_{i-1}^{k-1}) */
 } rpr_correction;
 
+typedef enum {
+    RPR_FEAT_AUTO = 0,         /* FP64 for RPR_FP64 plans, bfloat16 for RPR_MIXED plans */
+    RPR_FEAT_FP64 = 1,         /* hidden layer in double precision */
+    RPR_FEAT_BF16 = 2          /* bf16 inputs and weights, single-precision sums on the
+                                  matrix cores, bf16 result (see rpr_randnet_features_bf16) */
+} rpr_feature_precision;
+
 typedef struct {
-    int32_t precision;         /* rpr_precision */
+    int32_t precision;         /* rpr_precision: slot states, F and G */
     int32_t correction;        /* rpr_correction */
     int32_t k_max;             /* iteration cap, 1 <= k_max <= N (0 selects N) */
     int32_t poll_every;        /* iterations enqueued between checks of the device
                                   "done" flag (0 selects 2) */
+    int32_t features;          /* rpr_feature_precision */
+    int32_t autotune;          /* 0: launch shapes from built-in rules; 1: time the
+                                  candidate shapes at plan creation and keep the
+                                  fastest (results cached per shape class in the
+                                  process, and in the JSON file named by the
+                                  environment variable RPR_TUNE_CACHE if set) */
+    int32_t graph;             /* 1: capture a block of poll_every iterations as a
+                                  hipGraph on the first execute (again when the input
+                                  scale changes) and replay it; 0: plain launches */
+    int32_t reserved;          /* must be 0 */
 } rpr_options;
 
 /* ---- plans: one IVP solved by RandNet-Parareal -------------------------- */
@@ -174,7 +191,35 @@ rpr_status rpr_plan_info(const rpr_plan *plan, rpr_info *info);
  * +inf).  Either pointer may be NULL. */
 rpr_status rpr_plan_history(const rpr_plan *plan, int32_t *L_hist, double *chg_hist, int32_t cap);
 
-/* Release every buffer of the plan.  NULL is accepted. */
+/*
+ * Batches: n_inst independent IVPs (same right-hand-side kind, precision and
+ * correction; sizes, parameters, slices and propagators may differ), solved
+ * together.  Every argument is an array of n_inst entries with the meaning of
+ * the rpr_plan_create argument of the same name (A, zeta: arrays of host
+ * pointers, or NULL to draw instance b's weights with seed + b); opt is
+ * shared.  Per iteration the fine solves of every unfinished slot of every
+ * instance run in one persistent launch whose work-groups take (instance,
+ * slot) items from a longest-first list, and all instances' predictor-
+ * corrector sweeps run in one launch, one work-group per instance.
+ * Errors as rpr_plan_create; RPR_ERR_UNSUPPORTED if the instances' grids
+ * cannot share the strip shape of the largest one.
+ */
+rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, const rpr_rhs *h, const int32_t *d,
+                                 const double *t0, const double *tN, const int32_t *N,
+                                 const rpr_propagator *F, const rpr_propagator *G, const double *tol,
+                                 const rpr_randnet *net, const double *const *A, const double *const *zeta,
+                                 uint64_t seed, const rpr_options *opt);
+
+/* Run a batch: u0[b] and U_out[b] are device pointers of instance b (host
+ * arrays of n_inst pointers), with the layout of rpr_plan_execute.  Returns
+ * RPR_OK once every instance has converged, RPR_NOT_CONVERGED otherwise. */
+rpr_status rpr_plan_execute_batch(rpr_plan *plan, const void *const *u0, void *const *U_out, void *stream);
+
+/* The plan of instance b of a batch, for rpr_plan_info / rpr_plan_history.
+ * The handle belongs to the batch: do not destroy it. */
+rpr_status rpr_plan_instance(const rpr_plan *batch, int32_t b, const rpr_plan **inst);
+
+/* Release every buffer of the plan (a batch releases its instances).  NULL is accepted. */
 rpr_status rpr_plan_destroy(rpr_plan *plan);
 
 /* ---- building blocks (the same kernels the plan runs) -------------------- */

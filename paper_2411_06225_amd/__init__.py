@@ -29,10 +29,12 @@ RPR_RK1, RPR_RK4 = 1, 4
 RPR_TANH, RPR_RELU = 0, 1
 RPR_FP64, RPR_MIXED = 0, 1
 RPR_CORR_RANDNET, RPR_CORR_PARAREAL = 0, 1
+RPR_FEAT_AUTO, RPR_FEAT_FP64, RPR_FEAT_BF16 = 0, 1, 2
 
 EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
             "rpr_plan_history", "rpr_plan_destroy", "rpr_propagate", "rpr_randnet_features", "rpr_ridge_fit",
-            "rpr_randnet_readout", "rpr_uniform_pm1", "rpr_randnet_features_bf16")
+            "rpr_randnet_readout", "rpr_uniform_pm1", "rpr_randnet_features_bf16", "rpr_plan_create_batch",
+            "rpr_plan_execute_batch", "rpr_plan_instance")
 
 
 class RprError(RuntimeError):
@@ -57,7 +59,8 @@ class rpr_randnet(C.Structure):
 
 class rpr_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("correction", C.c_int32), ("k_max", C.c_int32),
-                ("poll_every", C.c_int32)]
+                ("poll_every", C.c_int32), ("features", C.c_int32), ("autotune", C.c_int32),
+                ("graph", C.c_int32), ("reserved", C.c_int32)]
 
 
 class rpr_info(C.Structure):
@@ -85,6 +88,12 @@ def lib() -> C.CDLL:
                                       C.POINTER(rpr_propagator), C.POINTER(rpr_propagator), dbl,
                                       C.POINTER(rpr_randnet), vp, vp, u64, C.POINTER(rpr_options)]),
             "rpr_plan_execute": (i32, [vp, vp, vp, vp]),
+            "rpr_plan_create_batch": (i32, [C.POINTER(vp), i32, C.POINTER(rpr_rhs), C.POINTER(C.c_int32), dp, dp,
+                                            C.POINTER(C.c_int32), C.POINTER(rpr_propagator),
+                                            C.POINTER(rpr_propagator), dp, C.POINTER(rpr_randnet),
+                                            C.POINTER(vp), C.POINTER(vp), u64, C.POINTER(rpr_options)]),
+            "rpr_plan_execute_batch": (i32, [vp, C.POINTER(vp), C.POINTER(vp), vp]),
+            "rpr_plan_instance": (i32, [vp, i32, C.POINTER(vp)]),
             "rpr_plan_info": (i32, [vp, C.POINTER(rpr_info)]),
             "rpr_plan_history": (i32, [vp, C.POINTER(C.c_int32), dp, i32]),
             "rpr_plan_destroy": (i32, [vp]),
@@ -180,13 +189,15 @@ class Plan:
     def __init__(self, h: rpr_rhs, d: int, t0: float, tN: float, N: int, F=(RPR_RK4, 1), G=(RPR_RK1, 1),
                  tol: float = 1e-6, M: int = 100, activation: int = RPR_TANH, lam: float = 1e-6,
                  input_scale: float = 0.0, A=None, zeta=None, seed: int = 0, precision: int = RPR_FP64,
-                 correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0):
+                 correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0,
+                 features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0):
         import numpy as np
         self.d, self.N = int(d), int(N)
         self._F = rpr_propagator(int(F[0]), 0, int(F[1]))
         self._G = rpr_propagator(int(G[0]), 0, int(G[1]))
         self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale))
-        self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every))
+        self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features),
+                                int(autotune), int(graph), 0)
         self._h = h
         Ah = zh = None
         if A is not None:
@@ -216,6 +227,79 @@ class Plan:
                                      ch.ctypes.data_as(C.POINTER(C.c_double)), self.N + 1))
         K = self.info()["K"]
         return L[:K + 1], ch[:K + 1]
+
+    def close(self):
+        if self._handle:
+            lib().rpr_plan_destroy(self._handle)
+            self._handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Handle:
+    """Instance view of a batch (info / history only)."""
+
+    def __init__(self, handle, N):
+        self._handle, self.N = handle, N
+
+    info = Plan.info
+    history = Plan.history
+
+
+class BatchPlan:
+    """Many independent IVPs solved together (rpr_plan_create_batch / execute_batch)."""
+
+    def __init__(self, problems, *, tol=1e-6, precision: int = RPR_FP64, correction: int = RPR_CORR_RANDNET,
+                 k_max: int = 0, poll_every: int = 0, features: int = RPR_FEAT_AUTO, seed: int = 0, graph: int = 0):
+        """problems: list of dicts with keys h, d, t0, tN, N, F, G, M, activation, lam, A, zeta."""
+        import numpy as np
+        n = len(problems)
+        self.n = n
+        self.Ns = [int(q["N"]) for q in problems]
+        self.ds = [int(q["d"]) for q in problems]
+        H = (rpr_rhs * n)(*[q["h"] for q in problems])
+        D = (C.c_int32 * n)(*self.ds)
+        T0 = (C.c_double * n)(*[float(q["t0"]) for q in problems])
+        TN = (C.c_double * n)(*[float(q["tN"]) for q in problems])
+        NN = (C.c_int32 * n)(*self.Ns)
+        F = (rpr_propagator * n)(*[rpr_propagator(int(q["F"][0]), 0, int(q["F"][1])) for q in problems])
+        G = (rpr_propagator * n)(*[rpr_propagator(int(q["G"][0]), 0, int(q["G"][1])) for q in problems])
+        TOL = (C.c_double * n)(*([float(tol)] * n if not isinstance(tol, (list, tuple)) else [float(t) for t in tol]))
+        NET = (rpr_randnet * n)(*[rpr_randnet(int(q.get("M", 100)), int(q.get("activation", RPR_TANH)),
+                                              float(q.get("lam", 1e-6)), float(q.get("input_scale", 0.0)))
+                                  for q in problems])
+        self._keep = []
+        Ap = (C.c_void_p * n)()
+        Zp = (C.c_void_p * n)()
+        have = all(q.get("A") is not None for q in problems)
+        if have:
+            for b, q in enumerate(problems):
+                a = np.ascontiguousarray(q["A"], dtype=np.float64)
+                z = np.ascontiguousarray(q["zeta"], dtype=np.float64)
+                self._keep += [a, z]
+                Ap[b], Zp[b] = a.ctypes.data, z.ctypes.data
+        opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features), 0, int(graph),
+                          0)
+        self._handle = C.c_void_p()
+        check(lib().rpr_plan_create_batch(C.byref(self._handle), n, H, D, T0, TN, NN, F, G, TOL, NET,
+                                          Ap if have else None, Zp if have else None, C.c_uint64(seed),
+                                          C.byref(opt)))
+
+    def execute(self, u0s, U_outs, stream=None) -> int:
+        n = self.n
+        U0 = (C.c_void_p * n)(*[_ptr(u) for u in u0s])
+        UO = (C.c_void_p * n)(*[_ptr(u) for u in U_outs])
+        return check(lib().rpr_plan_execute_batch(self._handle, U0, UO, _stream(stream)),
+                     allow=(RPR_OK, RPR_NOT_CONVERGED))
+
+    def instance(self, b: int) -> "_Handle":
+        h = C.c_void_p()
+        check(lib().rpr_plan_instance(self._handle, int(b), C.byref(h)))
+        return _Handle(h, self.Ns[b])
 
     def close(self):
         if self._handle:

@@ -8,8 +8,10 @@
 // enqueuing once it is set.  Kernels enqueued after convergence exit at once.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "chain.h"
@@ -197,6 +199,26 @@ struct rpr_plan {
     Ctrl *ctrl_host = nullptr;  // pinned
     OnchipShape shF{}, shG{};
     int nwg = 1;
+    bool feat_bf16 = false;
+    int autotune = 0;
+    int use_graph = 0;
+    hipGraph_t graph = nullptr;         // captured block of `poll` iterations
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_s = 0.0;               // input scale the captured block was built for
+    hipStream_t cap_stream = nullptr;   // private stream the block is captured on
+    void *gchain = nullptr;             // device ChainArgs<T> of the captured chain
+    std::vector<double> bscale;         // batch: input scales the captured block was built for
+    // batch plans: one sub-plan per instance plus the shared persistent fine solve
+    std::vector<rpr_plan *> sub;
+    void *binsts = nullptr;   // device BatchInst<T>[n_inst]
+    int2 *bitems = nullptr;   // device (instance, slot) items, longest first
+    int bn_items = 0;
+    int *bcounter = nullptr;
+    void *bchain = nullptr;   // device ChainArgs<T>[n_inst]
+    std::vector<char> hchain; // host staging of the chain arguments
+    Geom bgmax{};
+    OnchipShape bshF{}, bshG{};
+    int bgrid = 0, bM = 0, bkmax = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     rpr_info info{};
     std::vector<int> Lh;
@@ -205,12 +227,21 @@ struct rpr_plan {
 
 static void plan_free(rpr_plan *p)
 {
+    for (rpr_plan *q : p->sub) plan_free(q);
+    p->sub.clear();
+    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain};
+    for (void *b : bb)
+        if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
                     p->Lt, p->Bm, p->W, p->phi, p->part, p->chg_hist, p->u0max, p->ok, p->nrows, p->L_hist,
                     p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->ctrl_host) (void)hipHostFree(p->ctrl_host);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->gchain) (void)hipFree(p->gchain);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     delete p;
@@ -270,7 +301,7 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
             RPR_TRY(launch_uniform(seed, 0, (int64_t)M * d, p->A, nullptr));
             RPR_TRY(launch_uniform(seed, (uint64_t)M * d, M, p->zeta, nullptr));
         }
-        if (p->prec == RPR_MIXED) {
+        if (p->feat_bf16) {
             RPR_TRY(dalloc(&p->Ab, (size_t)M * d));
             RPR_TRY(dalloc(&p->fpart32, (size_t)feat_bf16_splits(d) * N * M));
             RPR_TRY(launch_to_bf16(p->A, p->Ab, (size_t)M * d, nullptr));
@@ -282,6 +313,165 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
     p->ctrl_host = static_cast<Ctrl *>(h);
     RPR_HIP(hipEventCreate(&p->ev0));
     RPR_HIP(hipEventCreate(&p->ev1));
+    if (p->use_graph) {
+        RPR_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        RPR_HIP(hipMalloc(&p->gchain, sizeof(ChainArgs<double>)));
+    }
+    return RPR_OK;
+}
+
+// --------------------------------------------------------------- autotuner --
+// Candidate launch shapes are timed on the plan's own buffers (zero-filled)
+// with events on a private stream; the fastest is kept.  Results are cached
+// per shape class in the process and, if RPR_TUNE_CACHE names a file, in that
+// JSON file ({"key": value, ...}).
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune;
+static bool g_tune_loaded = false;
+
+static void tune_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("RPR_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    size_t pos = 0;
+    while ((pos = txt.find('"', pos)) != std::string::npos) {
+        const size_t end = txt.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = txt.substr(pos + 1, end - pos - 1);
+        const size_t colon = txt.find(':', end);
+        if (colon == std::string::npos) break;
+        g_tune[key] = std::atoi(txt.c_str() + colon + 1);
+        pos = txt.find_first_of(",}", colon);
+        if (pos == std::string::npos) break;
+    }
+}
+
+static void tune_store()
+{
+    const char *path = std::getenv("RPR_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path);
+    f << "{";
+    bool first = true;
+    for (const auto &kv : g_tune) {
+        f << (first ? "" : ",") << "\n  \"" << kv.first << "\": " << kv.second;
+        first = false;
+    }
+    f << "\n}\n";
+}
+
+template <typename T>
+static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    const Geom &g = p->g;
+    const int N = p->N, d = g.d;
+    std::ostringstream kf, kc;
+    kf << "prop:" << g.kind << ":" << g.nx << "x" << g.ny << ":" << p->esz << ":" << p->F.method;
+    kc << "chain:" << g.kind << ":" << g.nx << "x" << g.ny << ":" << p->esz << ":M" << p->M << ":N" << N << ":"
+       << p->corr << ":" << (p->feat_bf16 ? 1 : 0);
+    const bool haveF = g_tune.count(kf.str()) != 0, haveC = g_tune.count(kc.str()) != 0;
+    hipStream_t st;
+    RPR_HIP(hipStreamCreate(&st));
+    hipEvent_t e0, e1;
+    RPR_HIP(hipEventCreate(&e0));
+    RPR_HIP(hipEventCreate(&e1));
+    T *U = static_cast<T *>(p->U), *Fv = static_cast<T *>(p->Fv), *Gc = static_cast<T *>(p->Gc);
+    rpr_status rc = RPR_OK;
+    auto done = [&]() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(st);
+    };
+    rc = zero(U, (size_t)(N + 1) * d, st);
+    if (rc == RPR_OK) rc = zero(Fv, (size_t)(N + 1) * d, st);
+    if (rc == RPR_OK) rc = zero(Gc, (size_t)(N + 1) * d, st);
+    if (rc == RPR_OK && p->W) rc = zero(p->W, (size_t)p->M * d, st);
+    if (rc != RPR_OK) { done(); return rc; }
+
+    // fine propagator: 1024-thread (short strips) or 512-thread (long strips) work-groups
+    if (!haveF) {
+        const int64_t steps = p->F.steps < 32 ? p->F.steps : 32;
+        float best = 1e30f;
+        int best_mt = p->shF.maxt;
+        for (int mt : {1024, 512}) {
+            OnchipShape sh;
+            if (!onchip_shape(g, p->esz, &sh, mt)) continue;
+            if (launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt) != RPR_OK) continue;
+            float ms = 0.f;
+            RPR_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; ++r)
+                RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt));
+            RPR_HIP(hipEventRecord(e1, st));
+            RPR_HIP(hipEventSynchronize(e1));
+            RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_mt = mt; }
+        }
+        g_tune[kf.str()] = best_mt;
+    }
+    const int mt = g_tune[kf.str()];
+    if (!onchip_shape(g, p->esz, &p->shF, mt)) { done(); return fail(RPR_ERR_HIP, "autotune: lost the F shape"); }
+
+    // chain grid: one work-group, or a quarter, half or all of the CUs
+    if (!haveC) {
+        ChainArgs<T> a{};
+        a.g = g;
+        a.mode = p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+        a.N = N;
+        a.M = p->M;
+        a.act = p->act;
+        a.k_max = N;
+        a.G_method = p->G.method;
+        a.G_steps = p->G.steps;
+        a.dtG = p->dtG;
+        a.inv_s = 1.0;
+        a.eps = 0.0;
+        a.U = U;
+        a.Fv = Fv;
+        a.Gc = Gc;
+        a.gtmp = static_cast<T *>(p->gtmp);
+        a.phi = p->phi;
+        a.A = p->A;
+        a.zeta = p->zeta;
+        a.W = p->W;
+        a.Ab = p->Ab;
+        a.part = p->part;
+        a.ctrl = p->ctrl;
+        float best = 1e30f;
+        int best_n = p->nwg;
+        const int cands[] = {1, cus / 4, cus / 2, cus};
+        for (int c : cands) {
+            if (c < 1 || c > max_wg) continue;
+            if (p->corr == RPR_CORR_RANDNET && c > 1 && c - 1 > p->M && c != cus) continue;
+            float ms = 0.f;
+            hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
+            RPR_TRY(launch_chain<T>(a, p->shG, c, st));
+            RPR_HIP(hipEventRecord(e0, st));
+            hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
+            RPR_TRY(launch_chain<T>(a, p->shG, c, st));
+            RPR_HIP(hipEventRecord(e1, st));
+            RPR_HIP(hipEventSynchronize(e1));
+            RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_n = c; }
+        }
+        g_tune[kc.str()] = best_n;
+    }
+    p->nwg = g_tune[kc.str()] < max_wg ? g_tune[kc.str()] : max_wg;
+    if (!haveF || !haveC) tune_store();
+    done();
     return RPR_OK;
 }
 
@@ -310,6 +500,11 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         return fail(RPR_ERR_INVALID_ARG, "opt.correction must be RPR_CORR_RANDNET or RPR_CORR_PARAREAL");
     if (opt->k_max < 0 || opt->k_max > N) return fail(RPR_ERR_INVALID_ARG, "opt.k_max must be in [0, N]");
     if (opt->poll_every < 0) return fail(RPR_ERR_INVALID_ARG, "opt.poll_every must be >= 0");
+    if (opt->features < RPR_FEAT_AUTO || opt->features > RPR_FEAT_BF16)
+        return fail(RPR_ERR_INVALID_ARG, "opt.features must be an rpr_feature_precision");
+    if (opt->autotune != 0 && opt->autotune != 1) return fail(RPR_ERR_INVALID_ARG, "opt.autotune must be 0 or 1");
+    if (opt->graph != 0 && opt->graph != 1) return fail(RPR_ERR_INVALID_ARG, "opt.graph must be 0 or 1");
+    if (opt->reserved != 0) return fail(RPR_ERR_INVALID_ARG, "opt.reserved must be 0");
     const bool use_net = opt->correction == RPR_CORR_RANDNET;
     if (use_net) {
         if (!net) return fail(RPR_ERR_INVALID_ARG, "net is NULL");
@@ -335,6 +530,9 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     p->k_max = opt->k_max == 0 ? N : opt->k_max;
     p->poll = opt->poll_every == 0 ? 2 : opt->poll_every;
     p->esz = p->prec == RPR_FP64 ? 8 : 4;
+    p->feat_bf16 = opt->features == RPR_FEAT_BF16 || (opt->features == RPR_FEAT_AUTO && p->prec == RPR_MIXED);
+    p->autotune = opt->autotune;
+    p->use_graph = opt->graph;
     if (use_net) {
         p->M = net->M;
         p->act = net->activation;
@@ -387,57 +585,37 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     if (nwg > max_wg) nwg = max_wg;
     if (nwg > 4096) nwg = 4096;
     p->nwg = nwg < 1 ? 1 : nwg;
+    if (p->autotune) {
+        st = p->esz == 8 ? autotune_plan<double>(p, max_wg, cus) : autotune_plan<float>(p, max_wg, cus);
+        if (st != RPR_OK) {
+            const std::string keep = g_err;
+            plan_free(p);
+            g_err = keep;
+            return st;
+        }
+    }
     *plan = p;
     return RPR_OK;
 }
 
+// ---- phases of a solve (shared by single and batched plans) ----
 template <typename T>
-static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hipStream_t st)
+static ChainArgs<T> chain_args(rpr_plan *p, double s)
 {
-    const Geom &g = p->g;
-    const int N = p->N, d = g.d, M = p->M;
-    T *U = static_cast<T *>(p->U), *Fv = static_cast<T *>(p->Fv), *Gc = static_cast<T *>(p->Gc);
-
-    // setup: input checks and scale s (Algorithm "Parareal (generic)", initialisation)
-    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st, u0, d, p->u0max, p->u0bad);
-    RPR_HIP(hipGetLastError());
-    double umax = 0.0;
-    int bad = 0;
-    RPR_HIP(hipMemcpyAsync(&umax, p->u0max, sizeof(double), hipMemcpyDeviceToHost, st));
-    RPR_HIP(hipMemcpyAsync(&bad, p->u0bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    RPR_HIP(hipStreamSynchronize(st));
-    if (bad) return fail(RPR_ERR_NONFINITE, "u0 has non-finite entries");
-    double s = p->scale_opt;
-    if (!(s > 0)) {
-        s = 1.0;
-        while (s < umax) s *= 2.0;
-    }
-    p->info = rpr_info{};
-    p->info.input_scale = s;
-
-    RPR_HIP(hipEventRecord(p->ev0, st));
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
-    RPR_HIP(hipGetLastError());
-    RPR_TRY((convert<double, T>(u0, U, (size_t)d, st)));
-    const bool net = p->corr == RPR_CORR_RANDNET;
-    if (net) {
-        RPR_TRY(zero(p->Gm, (size_t)M * M, st));
-        RPR_TRY(zero(p->Bm, (size_t)M * d, st));
-    }
-
     ChainArgs<T> a{};
-    a.g = g;
-    a.N = N;
-    a.M = M;
+    a.g = p->g;
+    a.N = p->N;
+    a.M = p->M;
     a.act = p->act;
+    a.k_max = p->k_max;
     a.G_method = p->G.method;
     a.G_steps = p->G.steps;
     a.dtG = p->dtG;
     a.inv_s = 1.0 / s;
     a.eps = p->tol;
-    a.U = U;
-    a.Fv = Fv;
-    a.Gc = Gc;
+    a.U = static_cast<T *>(p->U);
+    a.Fv = static_cast<T *>(p->Fv);
+    a.Gc = static_cast<T *>(p->Gc);
     a.gtmp = static_cast<T *>(p->gtmp);
     a.phi = p->phi;
     a.A = p->A;
@@ -448,70 +626,397 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     a.ctrl = p->ctrl;
     a.L_hist = p->L_hist;
     a.chg_hist = p->chg_hist;
+    a.mode = p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+    return a;
+}
 
-    // k = 0: coarse sweep
+// max |u0| and the non-finite flag (enqueued; read after a stream sync)
+static rpr_status phase_check_u0(rpr_plan *p, const double *u0, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st, u0, p->g.d, p->u0max, p->u0bad);
+    RPR_HIP(hipGetLastError());
+    return RPR_OK;
+}
+
+// input scale (Algorithm "Parareal (generic)", initialisation), control block,
+// U_0 = u0, zeroed ridge statistics, coarse sweep
+template <typename T>
+static rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStream_t st, ChainArgs<T> *out)
+{
+    double s = p->scale_opt;
+    if (!(s > 0)) {
+        s = 1.0;
+        while (s < umax) s *= 2.0;
+    }
+    p->info = rpr_info{};
+    p->info.input_scale = s;
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
+    RPR_HIP(hipGetLastError());
+    RPR_TRY((convert<double, T>(u0, static_cast<T *>(p->U), (size_t)p->g.d, st)));
+    if (p->corr == RPR_CORR_RANDNET) {
+        RPR_TRY(zero(p->Gm, (size_t)p->M * p->M, st));
+        RPR_TRY(zero(p->Bm, (size_t)p->M * p->g.d, st));
+    }
+    ChainArgs<T> a = chain_args<T>(p, s);
     a.mode = CHAIN_SWEEP;
     RPR_TRY(launch_chain<T>(a, p->shG, 1, st));
-    a.mode = net ? CHAIN_RANDNET : CHAIN_PARAREAL;
+    a.mode = p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+    *out = a;
+    return RPR_OK;
+}
 
-    const int *ctrl_i = reinterpret_cast<const int *>(p->ctrl);
-    int k = 0;
-    bool done = false;
-    while (k < p->k_max && !done) {
-        const int burst = (p->k_max - k) < p->poll ? (p->k_max - k) : p->poll;
-        for (int b = 0; b < burst; ++b) {
-            // fine solves of the slots that are not final: Fv[i] = F(U[i-1])
-            RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, st,
-                                        p->shF.maxt));
-            if (net) {
-                T *X = static_cast<T *>(p->X), *Y = static_cast<T *>(p->Y);
-                RPR_TRY(launch_pairs<T>(N, d, U, Fv, Gc, X, Y, p->ok, p->nrows, p->ctrl, st));
-                if (p->Ab)
-                    RPR_TRY(launch_features_bf16<T>(N, M, d, p->act, 1.0 / s, p->Ab, p->zeta, X, p->Phi, p->fpart32,
-                                                    p->nrows, st));
-                else
-                    RPR_TRY(launch_features<T>(N, M, d, p->act, 1.0 / s, p->A, p->zeta, X, p->Phi, p->fpart,
-                                               p->nrows, st));
-                RPR_TRY(launch_stats<T>(N, M, d, p->Phi, Y, p->ok, p->Gm, p->Bm, p->nrows, st));
-                RPR_TRY(launch_ridge_solve(M, d, p->Gm, p->lambda, p->Lf, p->Lt, p->W, p->Bm, p->cfail,
-                                           &p->ctrl->chol_fail, &p->ctrl->done, st));
-            }
-            RPR_TRY(launch_chain<T>(a, p->shG, p->nwg, st));
-            ++k;
-        }
-        RPR_HIP(hipMemcpyAsync(p->ctrl_host, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-        RPR_HIP(hipStreamSynchronize(st));
-        done = p->ctrl_host->done != 0;
-    }
-    RPR_TRY((convert<T, double>(U, U_out, (size_t)(N + 1) * d, st)));
-    RPR_HIP(hipEventRecord(p->ev1, st));
-    RPR_HIP(hipStreamSynchronize(st));
-    float ms = 0.f;
-    RPR_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+// training pairs, hidden layer, ridge statistics and solve of one iteration
+template <typename T>
+static rpr_status phase_model(rpr_plan *p, double inv_s, hipStream_t st)
+{
+    if (p->corr != RPR_CORR_RANDNET) return RPR_OK;
+    const int N = p->N, d = p->g.d, M = p->M;
+    T *U = static_cast<T *>(p->U), *Fv = static_cast<T *>(p->Fv), *Gc = static_cast<T *>(p->Gc);
+    T *X = static_cast<T *>(p->X), *Y = static_cast<T *>(p->Y);
+    RPR_TRY(launch_pairs<T>(N, d, U, Fv, Gc, X, Y, p->ok, p->nrows, p->ctrl, st));
+    if (p->Ab)
+        RPR_TRY(launch_features_bf16<T>(N, M, d, p->act, inv_s, p->Ab, p->zeta, X, p->Phi, p->fpart32, p->nrows, st));
+    else
+        RPR_TRY(launch_features<T>(N, M, d, p->act, inv_s, p->A, p->zeta, X, p->Phi, p->fpart, p->nrows, st));
+    RPR_TRY(launch_stats<T>(N, M, d, p->Phi, Y, p->ok, p->Gm, p->Bm, p->nrows, st));
+    RPR_TRY(launch_ridge_solve(M, d, p->Gm, p->lambda, p->Lf, p->Lt, p->W, p->Bm, p->cfail, &p->ctrl->chol_fail,
+                               &p->ctrl->done, st));
+    return RPR_OK;
+}
 
+// results after the final stream synchronisation
+template <typename T>
+static rpr_status phase_finish(rpr_plan *p, double *U_out, float ms, hipStream_t st)
+{
     const Ctrl &c = *p->ctrl_host;
+    const int N = p->N;
+    RPR_TRY((convert<T, double>(static_cast<T *>(p->U), U_out, (size_t)(N + 1) * p->g.d, st)));
     p->info.K = c.k;
     p->info.L_final = c.L;
-    p->info.converged = c.done;
+    p->info.converged = c.L >= N;
     p->info.rows_used = c.rows_used;
     p->info.nonfinite_rows = c.nonfinite;
     p->info.chol_fail = c.chol_fail;
     p->info.t_total = ms * 1e-3;
     p->Lh.assign(N + 1, 0);
     p->ch.assign(N + 1, 0.0);
-    RPR_HIP(hipMemcpy(p->Lh.data(), p->L_hist, sizeof(int) * (c.k + 1), hipMemcpyDeviceToHost));
-    RPR_HIP(hipMemcpy(p->ch.data(), p->chg_hist, sizeof(double) * (c.k + 1), hipMemcpyDeviceToHost));
-    return c.done ? RPR_OK : RPR_NOT_CONVERGED;
+    RPR_HIP(hipMemcpyAsync(p->Lh.data(), p->L_hist, sizeof(int) * (c.k + 1), hipMemcpyDeviceToHost, st));
+    RPR_HIP(hipMemcpyAsync(p->ch.data(), p->chg_hist, sizeof(double) * (c.k + 1), hipMemcpyDeviceToHost, st));
+    return RPR_OK;
+}
+
+// Records what `enqueue` puts on the plan's capture stream as the plan's
+// graph, replacing the previous one.  Nothing runs during the capture.
+template <typename F>
+static rpr_status capture_block(rpr_plan *p, F enqueue)
+{
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    RPR_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+    const rpr_status cap = enqueue();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (cap != RPR_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cap != RPR_OK ? cap : hip_fail(e, "hipStreamEndCapture");
+    }
+    p->graph = graph;
+    RPR_HIP(hipGraphInstantiate(&p->graph_exec, graph, nullptr, nullptr, 0));
+    return RPR_OK;
+}
+
+template <typename T>
+static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hipStream_t st)
+{
+    const Geom &g = p->g;
+    const int N = p->N, d = g.d;
+    T *U = static_cast<T *>(p->U), *Fv = static_cast<T *>(p->Fv);
+
+    RPR_TRY(phase_check_u0(p, u0, st));
+    double umax = 0.0;
+    int bad = 0;
+    RPR_HIP(hipMemcpyAsync(&umax, p->u0max, sizeof(double), hipMemcpyDeviceToHost, st));
+    RPR_HIP(hipMemcpyAsync(&bad, p->u0bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    RPR_HIP(hipStreamSynchronize(st));
+    if (bad) return fail(RPR_ERR_NONFINITE, "u0 has non-finite entries");
+
+    RPR_HIP(hipEventRecord(p->ev0, st));
+    ChainArgs<T> a;
+    RPR_TRY(phase_setup<T>(p, u0, umax, st, &a));
+    const int *ctrl_i = reinterpret_cast<const int *>(p->ctrl);
+    // one iteration: fine solves of the unfinished slots (Fv[i] = F(U[i-1])),
+    // the model, the predictor-corrector sweep with the stopping rule
+    // `s` is the stream the iteration is enqueued on (the caller's, or the
+    // capture stream); inside a graph the chain runs as one work-group with
+    // plain barriers, so the graph holds no grid-wide barrier
+    auto iteration = [&](hipStream_t s, bool graph) -> rpr_status {
+        RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, s, p->shF.maxt));
+        RPR_TRY(phase_model<T>(p, a.inv_s, s));
+        if (graph)
+            RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->gchain), 1, g, p->shG, p->M, s));
+        else
+            RPR_TRY(launch_chain<T>(a, p->shG, p->nwg, s));
+        return RPR_OK;
+    };
+    if (p->use_graph) RPR_HIP(hipMemcpyAsync(p->gchain, &a, sizeof(a), hipMemcpyHostToDevice, st));
+    // graph mode: a block of `poll` iterations is captured once (again when
+    // the input scale changes) and replayed; iterations after the stop flag
+    // is raised return at once
+    if (p->use_graph && (!p->graph_exec || p->graph_s != a.inv_s)) {
+        RPR_TRY(capture_block(p, [&]() -> rpr_status {
+            for (int b = 0; b < p->poll; ++b) RPR_TRY(iteration(p->cap_stream, true));
+            return RPR_OK;
+        }));
+        p->graph_s = a.inv_s;
+    }
+    int k = 0;
+    bool done = false;
+    while (k < p->k_max && !done) {
+        const int burst = (p->k_max - k) < p->poll ? (p->k_max - k) : p->poll;
+        if (p->use_graph) {
+            RPR_HIP(hipGraphLaunch(p->graph_exec, st));
+            k += p->poll;
+        } else {
+            for (int b = 0; b < burst; ++b) {
+                RPR_TRY(iteration(st, false));
+                ++k;
+            }
+        }
+        RPR_HIP(hipMemcpyAsync(p->ctrl_host, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        RPR_HIP(hipStreamSynchronize(st));
+        done = p->ctrl_host->done != 0;
+    }
+    RPR_HIP(hipEventRecord(p->ev1, st));
+    RPR_HIP(hipEventSynchronize(p->ev1));
+    float ms = 0.f;
+    RPR_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    RPR_TRY(phase_finish<T>(p, U_out, ms, st));
+    RPR_HIP(hipStreamSynchronize(st));
+    return p->ctrl_host->L >= N ? RPR_OK : RPR_NOT_CONVERGED;
 }
 
 extern "C" rpr_status rpr_plan_execute(rpr_plan *plan, const void *u0, void *U_out, void *stream)
 {
     if (!plan) return fail(RPR_ERR_INVALID_ARG, "plan is NULL");
     if (!u0 || !U_out) return fail(RPR_ERR_INVALID_ARG, "u0 and U_out must be device pointers");
+    if (!plan->sub.empty()) return fail(RPR_ERR_INVALID_ARG, "batch plan: use rpr_plan_execute_batch");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (plan->esz == 8)
         return execute_impl<double>(plan, static_cast<const double *>(u0), static_cast<double *>(U_out), st);
     return execute_impl<float>(plan, static_cast<const double *>(u0), static_cast<double *>(U_out), st);
+}
+
+// ------------------------------------------------------------------ batches --
+extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, const rpr_rhs *h, const int32_t *d,
+                                            const double *t0, const double *tN, const int32_t *N,
+                                            const rpr_propagator *F, const rpr_propagator *G, const double *tol,
+                                            const rpr_randnet *net, const double *const *A,
+                                            const double *const *zeta, uint64_t seed, const rpr_options *opt)
+{
+    if (!plan) return fail(RPR_ERR_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (n_inst < 1) return fail(RPR_ERR_INVALID_ARG, "n_inst must be >= 1");
+    if (!h || !d || !t0 || !tN || !N || !F || !G || !tol || !opt)
+        return fail(RPR_ERR_INVALID_ARG, "batch arrays must not be NULL");
+    for (int b = 1; b < n_inst; ++b)
+        if (h[b].kind != h[0].kind) return fail(RPR_ERR_INVALID_ARG, "all instances of a batch need the same rhs kind");
+    rpr_plan *p = new rpr_plan();
+    auto bail = [&](rpr_status st) {
+        const std::string keep = g_err;
+        plan_free(p);
+        g_err = keep;
+        return st;
+    };
+    rpr_options o = *opt;
+    o.autotune = 0;
+    o.graph = 0;  // the batch captures its own iteration block
+    for (int b = 0; b < n_inst; ++b) {
+        rpr_plan *q = nullptr;
+        const rpr_status st = rpr_plan_create(&q, &h[b], d[b], t0[b], tN[b], N[b], &F[b], &G[b], tol[b],
+                                              net ? &net[b] : nullptr, A ? A[b] : nullptr, zeta ? zeta[b] : nullptr,
+                                              seed + (uint64_t)b, &o);
+        if (st != RPR_OK) {
+            g_err = "instance " + std::to_string(b) + ": " + g_err;
+            return bail(st);
+        }
+        q->nwg = 1;
+        p->sub.push_back(q);
+    }
+    rpr_plan *q0 = p->sub[0];
+    p->prec = q0->prec;
+    p->esz = q0->esz;
+    p->corr = q0->corr;
+    for (rpr_plan *q : p->sub)
+        if (q->prec != p->prec || q->corr != p->corr)
+            return bail(fail(RPR_ERR_INVALID_ARG, "all instances of a batch need the same precision and correction"));
+    // the kernel shape of the largest instance serves every instance
+    int big = 0;
+    for (int b = 1; b < n_inst; ++b)
+        if (padded_elems(p->sub[b]->g) > padded_elems(p->sub[big]->g)) big = b;
+    p->bgmax = p->sub[big]->g;
+    if (!onchip_shape(p->bgmax, p->esz, &p->bshF, 1024))
+        return bail(fail(RPR_ERR_UNSUPPORTED, "largest batch instance does not fit one work-group"));
+    p->bshF.full = 0;
+    p->bshG = p->bshF;
+    for (rpr_plan *q : p->sub) {
+        const Geom &g = q->g;
+        const int need = g.kind == RPR_BURGERS1D ? (g.nc + p->bshF.cpt - 1) / p->bshF.cpt
+                                                 : g.nx * ((g.ny + p->bshF.cpt - 1) / p->bshF.cpt);
+        if (need > p->bshF.block)
+            return bail(fail(RPR_ERR_UNSUPPORTED, "batch instance grids do not share one strip shape"));
+        p->bM = q->M > p->bM ? q->M : p->bM;
+        p->bkmax = q->k_max > p->bkmax ? q->k_max : p->bkmax;
+    }
+    p->poll = q0->poll;
+    // longest-first (LPT) list of (instance, slot) fine solves
+    struct Work { int b, i; double cost; };
+    std::vector<Work> work;
+    for (int b = 0; b < n_inst; ++b) {
+        const rpr_plan *q = p->sub[b];
+        const double c = (double)q->g.d * (double)q->F.steps * (q->F.method == RPR_RK4 ? 4.0 : 1.0);
+        for (int i = 1; i <= q->N; ++i) work.push_back({b, i, c});
+    }
+    std::stable_sort(work.begin(), work.end(), [](const Work &x, const Work &y) { return x.cost > y.cost; });
+    std::vector<int2> items(work.size());
+    for (size_t k = 0; k < work.size(); ++k) items[k] = make_int2(work[k].b, work[k].i);
+    p->bn_items = (int)items.size();
+    rpr_status st = dalloc(&p->bitems, items.size());
+    if (st == RPR_OK) st = dalloc(&p->bcounter, 1);
+    if (st != RPR_OK) return bail(st);
+    if (hipMemcpy(p->bitems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(RPR_ERR_HIP, "batch: item upload failed"));
+    const size_t isz = p->esz == 8 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
+    const size_t csz = p->esz == 8 ? sizeof(ChainArgs<double>) : sizeof(ChainArgs<float>);
+    char *tmp;
+    if ((st = dalloc(&tmp, isz * n_inst)) != RPR_OK) return bail(st);
+    p->binsts = tmp;
+    if ((st = dalloc(&tmp, csz * n_inst)) != RPR_OK) return bail(st);
+    p->bchain = tmp;
+    p->hchain.assign(csz * n_inst, 0);
+    std::vector<char> hinst(isz * n_inst);
+    for (int b = 0; b < n_inst; ++b) {
+        rpr_plan *q = p->sub[b];
+        if (p->esz == 8) {
+            BatchInst<double> I{q->g, q->F.method, (long long)q->F.steps, q->dtF, static_cast<const double *>(q->U),
+                                static_cast<double *>(q->Fv), reinterpret_cast<const int *>(q->ctrl)};
+            std::memcpy(hinst.data() + b * isz, &I, isz);
+        } else {
+            BatchInst<float> I{q->g, q->F.method, (long long)q->F.steps, q->dtF, static_cast<const float *>(q->U),
+                               static_cast<float *>(q->Fv), reinterpret_cast<const int *>(q->ctrl)};
+            std::memcpy(hinst.data() + b * isz, &I, isz);
+        }
+    }
+    if (hipMemcpy(p->binsts, hinst.data(), hinst.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(RPR_ERR_HIP, "batch: instance upload failed"));
+    int dev = 0, cus = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    p->bgrid = p->bn_items < 2 * cus ? p->bn_items : 2 * cus;
+    if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+        return bail(fail(RPR_ERR_HIP, "batch: event creation failed"));
+    p->use_graph = opt->graph;
+    if (p->use_graph && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(RPR_ERR_HIP, "batch: capture stream creation failed"));
+    *plan = p;
+    return RPR_OK;
+}
+
+template <typename T>
+static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, double *const *U_out, hipStream_t st)
+{
+    const int n = (int)p->sub.size();
+    for (int b = 0; b < n; ++b) RPR_TRY(phase_check_u0(p->sub[b], u0[b], st));
+    std::vector<double> umax(n);
+    std::vector<int> bad(n);
+    for (int b = 0; b < n; ++b) {
+        RPR_HIP(hipMemcpyAsync(&umax[b], p->sub[b]->u0max, sizeof(double), hipMemcpyDeviceToHost, st));
+        RPR_HIP(hipMemcpyAsync(&bad[b], p->sub[b]->u0bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+    RPR_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < n; ++b)
+        if (bad[b]) return fail(RPR_ERR_NONFINITE, "u0 of instance " + std::to_string(b) + " has non-finite entries");
+
+    RPR_HIP(hipEventRecord(p->ev0, st));
+    std::vector<ChainArgs<T>> args(n);
+    for (int b = 0; b < n; ++b) RPR_TRY(phase_setup<T>(p->sub[b], u0[b], umax[b], st, &args[b]));
+    std::memcpy(p->hchain.data(), args.data(), sizeof(ChainArgs<T>) * n);
+    RPR_HIP(hipMemcpyAsync(p->bchain, p->hchain.data(), sizeof(ChainArgs<T>) * n, hipMemcpyHostToDevice, st));
+    const auto *insts = static_cast<const BatchInst<T> *>(p->binsts);
+    auto iteration = [&](hipStream_t s) -> rpr_status {
+        // every unfinished (instance, slot) fine solve in one persistent launch
+        RPR_TRY(zero(p->bcounter, 1, s));
+        RPR_TRY(launch_prop_persistent<T>(insts, p->bitems, p->bn_items, p->bcounter, p->bgmax, p->bshF, p->bgrid,
+                                          s));
+        for (int b = 0; b < n; ++b) RPR_TRY(phase_model<T>(p->sub[b], args[b].inv_s, s));
+        // every instance's predictor-corrector sweep, one work-group each
+        RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->bchain), n, p->bgmax, p->bshG, p->bM, s));
+        return RPR_OK;
+    };
+    if (p->use_graph) {
+        // captured once per set of input scales (the feature kernels take the
+        // scale by value); the chain arguments are read from device memory
+        bool same = p->graph_exec != nullptr && p->bscale.size() == (size_t)n;
+        for (int b = 0; same && b < n; ++b) same = p->bscale[b] == args[b].inv_s;
+        if (!same) RPR_TRY(capture_block(p, [&]() -> rpr_status {
+            for (int it = 0; it < p->poll; ++it) RPR_TRY(iteration(p->cap_stream));
+            return RPR_OK;
+        }));
+        p->bscale.resize(n);
+        for (int b = 0; b < n; ++b) p->bscale[b] = args[b].inv_s;
+    }
+    int k = 0;
+    bool done = false;
+    while (k < p->bkmax && !done) {
+        const int burst = (p->bkmax - k) < p->poll ? (p->bkmax - k) : p->poll;
+        if (p->use_graph) {
+            RPR_HIP(hipGraphLaunch(p->graph_exec, st));
+            k += p->poll;
+        } else {
+            for (int it = 0; it < burst; ++it) {
+                RPR_TRY(iteration(st));
+                ++k;
+            }
+        }
+        for (int b = 0; b < n; ++b)
+            RPR_HIP(hipMemcpyAsync(p->sub[b]->ctrl_host, p->sub[b]->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        RPR_HIP(hipStreamSynchronize(st));
+        done = true;
+        for (int b = 0; b < n; ++b) done = done && p->sub[b]->ctrl_host->done != 0;
+    }
+    RPR_HIP(hipEventRecord(p->ev1, st));
+    RPR_HIP(hipEventSynchronize(p->ev1));
+    float ms = 0.f;
+    RPR_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    for (int b = 0; b < n; ++b) RPR_TRY(phase_finish<T>(p->sub[b], U_out[b], ms, st));
+    RPR_HIP(hipStreamSynchronize(st));
+    bool conv = true;
+    for (int b = 0; b < n; ++b) conv = conv && p->sub[b]->ctrl_host->L >= p->sub[b]->N;
+    return conv ? RPR_OK : RPR_NOT_CONVERGED;
+}
+
+extern "C" rpr_status rpr_plan_execute_batch(rpr_plan *plan, const void *const *u0, void *const *U_out,
+                                             void *stream)
+{
+    if (!plan || plan->sub.empty()) return fail(RPR_ERR_INVALID_ARG, "not a batch plan");
+    if (!u0 || !U_out) return fail(RPR_ERR_INVALID_ARG, "u0 and U_out must be host arrays of device pointers");
+    for (size_t b = 0; b < plan->sub.size(); ++b)
+        if (!u0[b] || !U_out[b]) return fail(RPR_ERR_INVALID_ARG, "NULL device pointer in u0 / U_out");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (plan->esz == 8)
+        return execute_batch_impl<double>(plan, reinterpret_cast<const double *const *>(u0),
+                                          reinterpret_cast<double *const *>(U_out), st);
+    return execute_batch_impl<float>(plan, reinterpret_cast<const double *const *>(u0),
+                                     reinterpret_cast<double *const *>(U_out), st);
+}
+
+extern "C" rpr_status rpr_plan_instance(const rpr_plan *batch, int32_t b, const rpr_plan **inst)
+{
+    if (!batch || !inst || b < 0 || b >= (int)batch->sub.size())
+        return fail(RPR_ERR_INVALID_ARG, "need a batch plan, an instance index in range and an output pointer");
+    *inst = batch->sub[b];
+    return RPR_OK;
 }
 
 extern "C" rpr_status rpr_plan_info(const rpr_plan *plan, rpr_info *info)

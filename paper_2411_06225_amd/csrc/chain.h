@@ -14,6 +14,7 @@ struct ChainArgs {
     Geom g;
     int mode;                  // CHAIN_*
     int N, M, act;
+    int k_max;                 // iteration cap: the sweep that reaches it raises the stop flag
     int G_method;
     long long G_steps;
     double dtG;
@@ -46,5 +47,15 @@ rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, h
 template <int KIND, typename T>
 rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,
                              int *max_wg);
+
+// Independent instances in one launch, one work-group each (nwg = 1 sweeps).
+// args_dev: device array of n_inst argument blocks; every instance must be
+// served by the generic kernel instance of shape sh (built for geometry gmax).
+template <typename T>
+rpr_status launch_chain_multi(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax, const OnchipShape &sh,
+                              int M, hipStream_t st);
+template <int KIND, typename T>
+rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax, const OnchipShape &sh,
+                                   int M, hipStream_t st);
 
 }  // namespace rpr

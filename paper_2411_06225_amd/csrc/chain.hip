@@ -63,14 +63,16 @@ __device__ __forceinline__ double nan_max(double a, double b)
     return a > b ? a : b;
 }
 
-template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
+// One sweep of one instance.  wg / nwg: this work-group and the number of
+// work-groups sharing the instance; sync(): a barrier over those work-groups
+// (a grid barrier, or a work-group barrier when nwg == 1).
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, typename Sync>
+__device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, const int nwg, Sync sync,
+                                           unsigned char *lds_raw)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
     double *scratch = reinterpret_cast<double *>(lds_raw);
-    cg::grid_group grid = cg::this_grid();
-    const int wg = blockIdx.x, nwg = gridDim.x, t = threadIdx.x, B = blockDim.x;
+    const int t = threadIdx.x, B = blockDim.x;
     const Geom &g = a.g;
     const int d = g.d;
     Ctrl *ctrl = a.ctrl;
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
 
     // exact slot
     for (int j = j0 + t; j < j1; j += B) a.U[(size_t)(L + 1) * d + j] = a.Fv[(size_t)(L + 1) * d + j];
-    grid.sync();
+    sync();
 
     const bool net = a.mode == CHAIN_RANDNET;
     for (int i = L + 2; i <= N; ++i) {
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
                 }
             }
         }
-        grid.sync();
+        sync();
 
         // ---- phase 2: readout, update and change norm on this block of columns
         double emax = 0.0;
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
             for (int w = 0; w < (B + 63) / 64; ++w) m = nan_max(m, scratch[w]);
             a.part[(size_t)i * nwg + wg] = m;
         }
-        grid.sync();
+        sync();
     }
 
     // ---- stopping rule (eq. "stop_crit"), work-group 0
@@ -200,11 +202,63 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
         const int k = ctrl->k + 1;
         ctrl->k = k;
         ctrl->L = Lnew;
-        if (Lnew >= N) ctrl->done = 1;
+        if (Lnew >= N || k >= a.k_max) ctrl->done = 1;  // converged, or iteration cap reached
         if (a.L_hist) a.L_hist[k] = Lnew;
         if (a.chg_hist) a.chg_hist[k] = chg;
     }
 }
+
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cg::grid_group grid = cg::this_grid();
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
+}
+
+// Independent instances: work-group b runs the whole sweep of instance b.
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_chain_multi(const ChainArgs<T> *__restrict__ args)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const ChainArgs<T> a = args[blockIdx.x];
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+}
+
+template <int KIND, typename T>
+struct ChainMultiLauncher {
+    const ChainArgs<T> *args;
+    int n_inst;
+    const OnchipShape &sh;
+    int M;
+    hipStream_t st;
+
+    template <int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
+    rpr_status run()
+    {
+        auto kern = k_chain_multi<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT>;
+        static bool attr_set = false;
+        if (!attr_set) {
+            RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxLds));
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(n_inst), dim3(sh.block), chain_lds(sh, M), st, args);
+        RPR_HIP(hipGetLastError());
+        return RPR_OK;
+    }
+};
+
+template <int KIND, typename T>
+rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax, const OnchipShape &sh,
+                                   int M, hipStream_t st)
+{
+    ChainMultiLauncher<KIND, T> L{args_dev, n_inst, sh, M, st};
+    return visit_shape_kind<KIND, T>(gmax, sh, L);
+}
+
+template rpr_status launch_chain_multi_kind<RPR_KIND, RPR_REAL>(const ChainArgs<RPR_REAL> *, int, const Geom &,
+                                                                 const OnchipShape &, int, hipStream_t);
 
 template <int KIND, typename T>
 struct ChainLauncher {

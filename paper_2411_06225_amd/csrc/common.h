@@ -176,7 +176,8 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ---------------------------------------------------- on-chip propagation --
-constexpr size_t kMaxLds = 160 * 1024;  // LDS bytes a work-group may allocate on gfx950
+constexpr size_t kMaxLds = 160 * 1024 - 1024;  // dynamic LDS per work-group on gfx950 (160 KB),
+                                               // less 1 KB kept for static LDS buffers
 
 // A slot whose whole state fits in one work-group's LDS is propagated by that
 // work-group; thread t owns a strip of `cpt` consecutive cells (slotprop.h).
@@ -207,11 +208,34 @@ template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in,
                             T *out, const int *ctrl, hipStream_t st, int max_threads = 1024);
 
+// One instance of a batch, as the persistent fine-solve kernel sees it.
+template <typename T>
+struct BatchInst {
+    Geom g;
+    int method;
+    long long steps;
+    double dt;
+    const T *U;        // (N+1) x d slot states of the instance
+    T *Fv;             // (N+1) x d fine values (row i = F(U[i-1]))
+    const int *ctrl;   // the instance's control block (L at [0], done at [2])
+};
+
+// Persistent fine solves over a batch: items[q] = (instance, slot), processed
+// in list order (longest first) by work-groups that take the next index from
+// *counter (zeroed before the launch) until the list is exhausted.  sh: the
+// generic strip shape of the largest instance; grid: work-groups launched.
+template <int KIND, typename T>
+rpr_status launch_prop_persistent_kind(const BatchInst<T> *insts, const int2 *items, int n_items, int *counter,
+                                       const Geom &gmax, const OnchipShape &sh, int grid, hipStream_t st);
+template <typename T>
+rpr_status launch_prop_persistent(const BatchInst<T> *insts, const int2 *items, int n_items, int *counter,
+                                  const Geom &gmax, const OnchipShape &sh, int grid, hipStream_t st);
+
 // Control block of a plan, in device memory.
 struct Ctrl {
     int L;           // slots 0..L are final
     int k;           // iterations done
-    int done;        // 1 once L == N
+    int done;        // stop flag: 1 once L == N or k == k_max
     int rows_used;   // finite pairs in the readout
     int nonfinite;   // dropped pairs
     int chol_fail;   // failed ridge factorisations

@@ -81,4 +81,38 @@ rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, h
 template rpr_status launch_chain<double>(const ChainArgs<double> &, const OnchipShape &, int, hipStream_t, int *);
 template rpr_status launch_chain<float>(const ChainArgs<float> &, const OnchipShape &, int, hipStream_t, int *);
 
+template <typename T>
+rpr_status launch_prop_persistent(const BatchInst<T> *insts, const int2 *items, int n_items, int *counter,
+                                  const Geom &gmax, const OnchipShape &sh, int grid, hipStream_t st)
+{
+    switch (gmax.kind) {
+    case RPR_BURGERS1D: return launch_prop_persistent_kind<RPR_BURGERS1D, T>(insts, items, n_items, counter, gmax, sh, grid, st);
+    case RPR_DIFFREACT2D: return launch_prop_persistent_kind<RPR_DIFFREACT2D, T>(insts, items, n_items, counter, gmax, sh, grid, st);
+    case RPR_BRUSS2D: return launch_prop_persistent_kind<RPR_BRUSS2D, T>(insts, items, n_items, counter, gmax, sh, grid, st);
+    case RPR_SWE2D: return launch_prop_persistent_kind<RPR_SWE2D, T>(insts, items, n_items, counter, gmax, sh, grid, st);
+    default: return fail(RPR_ERR_INVALID_ARG, "batch: unknown right-hand side");
+    }
+}
+template rpr_status launch_prop_persistent<double>(const BatchInst<double> *, const int2 *, int, int *, const Geom &,
+                                                   const OnchipShape &, int, hipStream_t);
+template rpr_status launch_prop_persistent<float>(const BatchInst<float> *, const int2 *, int, int *, const Geom &,
+                                                  const OnchipShape &, int, hipStream_t);
+
+template <typename T>
+rpr_status launch_chain_multi(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax, const OnchipShape &sh,
+                              int M, hipStream_t st)
+{
+    switch (gmax.kind) {
+    case RPR_BURGERS1D: return launch_chain_multi_kind<RPR_BURGERS1D, T>(args_dev, n_inst, gmax, sh, M, st);
+    case RPR_DIFFREACT2D: return launch_chain_multi_kind<RPR_DIFFREACT2D, T>(args_dev, n_inst, gmax, sh, M, st);
+    case RPR_BRUSS2D: return launch_chain_multi_kind<RPR_BRUSS2D, T>(args_dev, n_inst, gmax, sh, M, st);
+    case RPR_SWE2D: return launch_chain_multi_kind<RPR_SWE2D, T>(args_dev, n_inst, gmax, sh, M, st);
+    default: return fail(RPR_ERR_INVALID_ARG, "batch: unknown right-hand side");
+    }
+}
+template rpr_status launch_chain_multi<double>(const ChainArgs<double> *, int, const Geom &, const OnchipShape &, int,
+                                               hipStream_t);
+template rpr_status launch_chain_multi<float>(const ChainArgs<float> *, int, const Geom &, const OnchipShape &, int,
+                                              hipStream_t);
+
 }  // namespace rpr

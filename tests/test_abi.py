@@ -74,7 +74,7 @@ def test_plan_create_rejects_bad_options():
     handle = C.c_void_p()
 
     def create(d=32, t0=0.0, tN=1.0, N=4, tol=1e-6, net_=net, opt=None):
-        opt = opt or rpr.rpr_options(0, 0, 0, 0)
+        opt = opt or rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 0)
         return L.rpr_plan_create(C.byref(handle), C.byref(h), d, t0, tN, N, C.byref(F), C.byref(G), tol,
                                  C.byref(net_), None, None, 0, C.byref(opt))
 
@@ -84,8 +84,12 @@ def test_plan_create_rejects_bad_options():
     assert create(net_=rpr.rpr_randnet(0, 0, 1e-6, 0.0)) == -1
     assert create(net_=rpr.rpr_randnet(10, 0, 0.0, 0.0)) == -1
     assert create(net_=rpr.rpr_randnet(10, 7, 1e-6, 0.0)) == -1
-    assert create(opt=rpr.rpr_options(3, 0, 0, 0)) == -1
-    assert create(opt=rpr.rpr_options(0, 0, 9, 0)) == -1
+    assert create(opt=rpr.rpr_options(3, 0, 0, 0, 0, 0, 0, 0)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 9, 0, 0, 0, 0, 0)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 5, 0, 0, 0)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 2, 0, 0)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 3, 0)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 1)) == -1
     assert handle.value is None
 
 

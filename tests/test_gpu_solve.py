@@ -24,13 +24,13 @@ from paper_2411_06225_amd import workloads as W  # noqa: E402
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def gpu_solve(w, eps=None, corr=0, k_max=0, prec=0, seeded=False, u0=None):
+def gpu_solve(w, eps=None, corr=0, k_max=0, prec=0, seeded=False, u0=None, **opt):
     u0 = W.initial_condition(w) if u0 is None else u0
     A, z = W.random_weights(w)
     h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
     kw = {} if seeded else dict(A=A, zeta=z)
     plan = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps if eps is None else eps, M=w.M,
-                    activation=w.act, lam=w.lam, precision=prec, correction=corr, k_max=k_max, seed=77, **kw)
+                    activation=w.act, lam=w.lam, precision=prec, correction=corr, k_max=k_max, seed=77, **kw, **opt)
     U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device="cuda")
     status = plan.execute(torch.tensor(u0, dtype=torch.float64, device="cuda"), U)
     torch.cuda.synchronize()
@@ -166,6 +166,40 @@ def test_G_equal_F_converges_in_one_iteration(corr):
 def test_iteration_cap_reports_not_converged(orc):
     w = DR_SMALL
     Ug, ig = gpu_solve(w, k_max=2)
+    assert ig["status"] == rpr.RPR_NOT_CONVERGED and ig["K"] == 2 and ig["converged"] == 0
+    Uo, io = orc_solve(orc, w, k_max=2)
+    assert ig["L_hist"].tolist() == io["L_hist"].tolist()
+    assert np.abs(Ug - Uo).max() / np.abs(Uo).max() <= w.N * 1e-12
+
+
+@pytest.mark.parametrize("w,poll", [(DR_SMALL, 4), (DR_RAGGED, 3), (BURGERS_SMALL, 1)],
+                         ids=["diffreact_32x32", "diffreact_24x20", "burgers_small"])
+def test_graph_replay_matches_oracle(orc, w, poll):
+    """Captured iteration blocks: the block is replayed whole, so iterations
+    after the stop flag (and past k_max) must leave every buffer untouched;
+    repeated executes replay the same graph.  The chain inside the graph runs
+    on one work-group (DR_SMALL's plain chain spreads over many), so states
+    are compared to the oracle at the usual tolerance."""
+    Uo, io = orc_solve(orc, w)
+    A, z = W.random_weights(w)
+    plan = rpr.Plan(rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params), w.d, w.t0, w.tN, w.N, F=w.F, G=w.G,
+                    tol=w.eps, M=w.M, activation=w.act, lam=w.lam, A=A, zeta=z, poll_every=poll, graph=1)
+    try:
+        for rep in range(2):
+            U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device="cuda")
+            status = plan.execute(torch.tensor(W.initial_condition(w), dtype=torch.float64, device="cuda"), U)
+            torch.cuda.synchronize()
+            ig = plan.info()
+            ig["L_hist"], ig["chg_hist"] = plan.history()
+            assert status == rpr.RPR_OK
+            assert_same_run(U.cpu().numpy(), ig, Uo, io, w.N)
+    finally:
+        plan.close()
+
+
+def test_graph_respects_iteration_cap(orc):
+    w = DR_SMALL
+    Ug, ig = gpu_solve(w, k_max=2, poll_every=3, graph=1)  # the block holds 3 iterations, the cap is 2
     assert ig["status"] == rpr.RPR_NOT_CONVERGED and ig["K"] == 2 and ig["converged"] == 0
     Uo, io = orc_solve(orc, w, k_max=2)
     assert ig["L_hist"].tolist() == io["L_hist"].tolist()
