@@ -80,7 +80,11 @@ typedef enum { RPR_RK1 = 1, RPR_RK4 = 4 } rpr_method; /* forward Euler, classica
 
 typedef struct {
     int32_t method;            /* rpr_method */
-    int32_t reserved;          /* must be 0 */
+    int32_t threads;           /* work-group size of the slot kernel: 0 automatic
+                                  (the autotuner's choice, else 1024); 512 or 1024
+                                  to fix it (512 exists for the 64 x 64 grids only,
+                                  others give RPR_ERR_UNSUPPORTED).  Batch plans
+                                  choose their own and ignore it. */
     int64_t steps;             /* fixed steps per slice, >= 1 */
 } rpr_propagator;
 
@@ -230,6 +234,9 @@ rpr_status rpr_plan_destroy(rpr_plan *plan);
  *   in, out   : device pointers, n_states x d, doubles if precision = RPR_FP64,
  *               floats if RPR_MIXED; must not overlap.
  *   dt        : step length; P->steps steps are taken.
+ * Work-group size: P->threads, or when 0 the one the autotuner chose for this
+ * grid, precision and method in the same process (rpr_options.autotune), else
+ * 1024.
  */
 rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propagator *P, int32_t precision,
                          double dt, int32_t n_states, const void *in, void *out, void *stream);

@@ -50,7 +50,7 @@ class rpr_rhs(C.Structure):
 
 
 class rpr_propagator(C.Structure):
-    _fields_ = [("method", C.c_int32), ("reserved", C.c_int32), ("steps", C.c_int64)]
+    _fields_ = [("method", C.c_int32), ("threads", C.c_int32), ("steps", C.c_int64)]
 
 
 class rpr_randnet(C.Structure):
@@ -151,8 +151,8 @@ def nspecies(kind: int) -> int:
 
 # ---- building blocks ---------------------------------------------------------
 def rpr_propagate(h: rpr_rhs, d: int, method: int, steps: int, precision: int, dt: float, n_states: int, x_in,
-                  x_out, stream=None) -> int:
-    P = rpr_propagator(int(method), 0, int(steps))
+                  x_out, stream=None, threads: int = 0) -> int:
+    P = rpr_propagator(int(method), int(threads), int(steps))
     return check(lib().rpr_propagate(C.byref(h), int(d), C.byref(P), int(precision), float(dt), int(n_states),
                                      _ptr(x_in), _ptr(x_out), _stream(stream)))
 
@@ -193,8 +193,9 @@ class Plan:
                  features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0):
         import numpy as np
         self.d, self.N = int(d), int(N)
-        self._F = rpr_propagator(int(F[0]), 0, int(F[1]))
-        self._G = rpr_propagator(int(G[0]), 0, int(G[1]))
+        # F, G: (method, steps) or (method, steps, threads)
+        self._F = rpr_propagator(int(F[0]), int(F[2]) if len(F) > 2 else 0, int(F[1]))
+        self._G = rpr_propagator(int(G[0]), int(G[2]) if len(G) > 2 else 0, int(G[1]))
         self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale))
         self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features),
                                 int(autotune), int(graph), 0)

@@ -92,7 +92,8 @@ static rpr_status check_prop(const rpr_propagator *P, const char *name)
     if (!P) return fail(RPR_ERR_INVALID_ARG, std::string(name) + " is NULL");
     if (P->method != RPR_RK1 && P->method != RPR_RK4)
         return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".method must be RPR_RK1 or RPR_RK4");
-    if (P->reserved != 0) return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".reserved must be 0");
+    if (P->threads != 0 && P->threads != 512 && P->threads != 1024)
+        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".threads must be 0, 512 or 1024");
     if (P->steps < 1) return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".steps must be >= 1");
     return RPR_OK;
 }
@@ -372,6 +373,23 @@ static void tune_store()
     f << "\n}\n";
 }
 
+static std::string prop_key(const Geom &g, int esz, int method)
+{
+    std::ostringstream k;
+    k << "prop:" << g.kind << ":" << g.nx << "x" << g.ny << ":" << esz << ":" << method;
+    return k.str();
+}
+
+// Work-group size the autotuner chose for this propagator class (1024 when
+// it has not run for it).
+static int tuned_prop_threads(const Geom &g, int esz, int method)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    const auto it = g_tune.find(prop_key(g, esz, method));
+    return it == g_tune.end() ? 1024 : it->second;
+}
+
 template <typename T>
 static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
 {
@@ -379,11 +397,11 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
     tune_load();
     const Geom &g = p->g;
     const int N = p->N, d = g.d;
-    std::ostringstream kf, kc;
-    kf << "prop:" << g.kind << ":" << g.nx << "x" << g.ny << ":" << p->esz << ":" << p->F.method;
+    std::ostringstream kc;
+    const std::string kf = prop_key(g, p->esz, p->F.method);
     kc << "chain:" << g.kind << ":" << g.nx << "x" << g.ny << ":" << p->esz << ":M" << p->M << ":N" << N << ":"
        << p->corr << ":" << (p->feat_bf16 ? 1 : 0);
-    const bool haveF = g_tune.count(kf.str()) != 0, haveC = g_tune.count(kc.str()) != 0;
+    const bool haveF = g_tune.count(kf) != 0, haveC = g_tune.count(kc.str()) != 0;
     hipStream_t st;
     RPR_HIP(hipStreamCreate(&st));
     hipEvent_t e0, e1;
@@ -403,14 +421,13 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
     if (rc != RPR_OK) { done(); return rc; }
 
     // fine propagator: 1024-thread (short strips) or 512-thread (long strips) work-groups
-    if (!haveF) {
+    if (!haveF && p->F.threads == 0) {
         const int64_t steps = p->F.steps < 32 ? p->F.steps : 32;
         float best = 1e30f;
         int best_mt = p->shF.maxt;
         for (int mt : {1024, 512}) {
-            OnchipShape sh;
-            if (!onchip_shape(g, p->esz, &sh, mt)) continue;
-            if (launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt) != RPR_OK) continue;
+            if (check_threads(g, p->esz, mt) != RPR_OK) continue;
+            RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt));
             float ms = 0.f;
             RPR_HIP(hipEventRecord(e0, st));
             for (int r = 0; r < 3; ++r)
@@ -420,9 +437,9 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
             RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best) { best = ms; best_mt = mt; }
         }
-        g_tune[kf.str()] = best_mt;
+        g_tune[kf] = best_mt;
     }
-    const int mt = g_tune[kf.str()];
+    const int mt = p->F.threads ? p->F.threads : g_tune[kf];
     if (!onchip_shape(g, p->esz, &p->shF, mt)) { done(); return fail(RPR_ERR_HIP, "autotune: lost the F shape"); }
 
     // chain grid: one work-group, or a quarter, half or all of the CUs
@@ -542,10 +559,19 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     const double T = (tN - t0) / N;
     p->dtF = T / (double)F->steps;
     p->dtG = T / (double)G->steps;
-    if (!onchip_shape(g, p->esz, &p->shF, 1024) || !onchip_shape(g, p->esz, &p->shG, 1024)) {
+    if (!onchip_shape(g, p->esz, &p->shF, F->threads ? F->threads : 1024) ||
+        !onchip_shape(g, p->esz, &p->shG, G->threads ? G->threads : 1024)) {
         delete p;
         return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group's LDS in this build");
     }
+    for (const rpr_propagator *P : {F, G})
+        if (P->threads) {
+            const rpr_status st = check_threads(g, p->esz, P->threads);
+            if (st != RPR_OK) {
+                delete p;
+                return st;
+            }
+        }
     if (use_net && (size_t)p->M * 32 * sizeof(double) > kMaxLds) {
         delete p;
         return fail(RPR_ERR_UNSUPPORTED, "net.M too large for the ridge solve");
@@ -1059,13 +1085,16 @@ extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propa
     const size_t bytes = (size_t)n_states * d * (precision == RPR_FP64 ? 8 : 4);
     const char *a = static_cast<const char *>(in), *b = static_cast<const char *>(out);
     if (a < b + bytes && b < a + bytes) return fail(RPR_ERR_INVALID_ARG, "in and out must not overlap");
+    const int esz = precision == RPR_FP64 ? 8 : 4;
+    if (P->threads) RPR_TRY(check_threads(g, esz, P->threads));
     RPR_TRY(check_device());
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const int mt = P->threads ? P->threads : tuned_prop_threads(g, esz, P->method);
     if (precision == RPR_FP64)
         return launch_propagate<double>(g, P->method, P->steps, dt, n_states, static_cast<const double *>(in),
-                                        static_cast<double *>(out), nullptr, st);
+                                        static_cast<double *>(out), nullptr, st, mt);
     return launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
-                                   static_cast<float *>(out), nullptr, st);
+                                   static_cast<float *>(out), nullptr, st, mt);
 }
 
 extern "C" rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int32_t activation, double s,

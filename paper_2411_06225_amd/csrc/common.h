@@ -67,36 +67,36 @@ __device__ __forceinline__ void rhs_burgers(const T *c, const T *w, const T *e, 
     k[0] = nu * uxx - c[0] * ux;
 }
 
-// Five-point Laplacian.
+// D times the 5-point Laplacian plus r, from the sum xs of the two x
+// neighbours and the centre weight mx in x (-2 when both neighbours are in
+// xs), with the diffusion coefficient folded into the axis weights
+// (Dx = D / dx^2, Dy = D / dy^2).
 template <typename T>
-__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, T idx2, T idy2)
+__device__ __forceinline__ T diffuse5(T c, T xs, T mx, T s, T n, T Dx, T Dy, T r)
 {
-    return (w - T(2) * c + e) * idx2 + (s - T(2) * c + n) * idy2;
+    return Dx * (xs + mx * c) + (Dy * (s - T(2) * c + n) + r);
 }
 
-// FitzHugh-Nagumo diffusion-reaction (Sec. 5.2).
+// FitzHugh-Nagumo diffusion-reaction (Sec. 5.2).  D*: diffusion
+// coefficients over dx^2 and dy^2; xs, mx as in diffuse5.
 template <typename T>
-__device__ __forceinline__ void rhs_diffreact(const T *c, const T *w, const T *e, const T *s, const T *n,
-                                              T *k, T Du, T Dv, T cc, T idx2, T idy2)
+__device__ __forceinline__ void rhs_diffreact(const T *c, const T *xs, T mx, const T *s, const T *n, T *k, T Dux,
+                                              T Duy, T Dvx, T Dvy, T cc)
 {
     const T u = c[0], v = c[1];
-    const T lu = lap5(u, w[0], e[0], s[0], n[0], idx2, idy2);
-    const T lv = lap5(v, w[1], e[1], s[1], n[1], idx2, idy2);
-    k[0] = Du * lu + (u - u * u * u - cc - v);
-    k[1] = Dv * lv + (u - v);
+    k[0] = diffuse5(u, xs[0], mx, s[0], n[0], Dux, Duy, (u - u * u * u) - (cc + v));
+    k[1] = diffuse5(v, xs[1], mx, s[1], n[1], Dvx, Dvy, u - v);
 }
 
 // Brusselator (App. E).
 template <typename T>
-__device__ __forceinline__ void rhs_bruss(const T *c, const T *w, const T *e, const T *s, const T *n,
-                                          T *k, T A, T B, T Du, T Dv, T idx2, T idy2)
+__device__ __forceinline__ void rhs_bruss(const T *c, const T *xs, T mx, const T *s, const T *n, T *k, T A, T B,
+                                          T Dux, T Duy, T Dvx, T Dvy)
 {
     const T u = c[0], v = c[1];
-    const T lu = lap5(u, w[0], e[0], s[0], n[0], idx2, idy2);
-    const T lv = lap5(v, w[1], e[1], s[1], n[1], idx2, idy2);
     const T u2v = u * u * v;
-    k[0] = Du * lu + A - (B + T(1)) * u + u2v;
-    k[1] = Dv * lv + B * u - u2v;
+    k[0] = diffuse5(u, xs[0], mx, s[0], n[0], Dux, Duy, (A - (B + T(1)) * u) + u2v);
+    k[1] = diffuse5(v, xs[1], mx, s[1], n[1], Dvx, Dvy, B * u - u2v);
 }
 
 // Shallow water: Rusanov flux across one face; (h, m, n) = depth, momentum
@@ -147,6 +147,22 @@ constexpr int kind_ns()
     return KIND == RPR_BURGERS1D ? 1 : (KIND == RPR_SWE2D ? 3 : 2);
 }
 
+// Right-hand side of the Laplacian-coupled systems (diffusion-reaction,
+// Brusselator) at one cell from the sum xs of its x neighbours, the centre
+// weight mx in x and its y neighbours.
+template <int KIND, typename T>
+__device__ __forceinline__ void rhs_cell_xsum(const Geom &g, const T *c, const T *xs, T mx, const T *s, const T *n,
+                                              T *k)
+{
+    static_assert(KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D, "5-point Laplacian systems only");
+    if constexpr (KIND == RPR_DIFFREACT2D)
+        rhs_diffreact<T>(c, xs, mx, s, n, k, T(g.p[0] * g.idx2), T(g.p[0] * g.idy2), T(g.p[1] * g.idx2),
+                         T(g.p[1] * g.idy2), T(g.p[2]));
+    else
+        rhs_bruss<T>(c, xs, mx, s, n, k, T(g.p[0]), T(g.p[1]), T(g.p[2] * g.idx2), T(g.p[2] * g.idy2),
+                     T(g.p[3] * g.idx2), T(g.p[3] * g.idy2));
+}
+
 // Dispatch for a compile-time kind.
 template <int KIND, typename T>
 __device__ __forceinline__ void rhs_cell(const Geom &g, const T *c, const T *w, const T *e, const T *s,
@@ -154,10 +170,9 @@ __device__ __forceinline__ void rhs_cell(const Geom &g, const T *c, const T *w, 
 {
     if constexpr (KIND == RPR_BURGERS1D) {
         rhs_burgers<T>(c, w, e, k, T(g.p[0]), T(g.idx2), T(g.i2dx));
-    } else if constexpr (KIND == RPR_DIFFREACT2D) {
-        rhs_diffreact<T>(c, w, e, s, n, k, T(g.p[0]), T(g.p[1]), T(g.p[2]), T(g.idx2), T(g.idy2));
-    } else if constexpr (KIND == RPR_BRUSS2D) {
-        rhs_bruss<T>(c, w, e, s, n, k, T(g.p[0]), T(g.p[1]), T(g.p[2]), T(g.p[3]), T(g.idx2), T(g.idy2));
+    } else if constexpr (KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D) {
+        T xs[2] = {w[0] + e[0], w[1] + e[1]};
+        rhs_cell_xsum<KIND, T>(g, c, xs, T(-2), s, n, k);
     } else {
         rhs_swe<T>(c, w, e, s, n, ww, we, ws, wn, k, T(g.p[0]), T(g.idx), T(g.idy));
     }
@@ -195,6 +210,9 @@ struct OnchipShape {
 // max_threads (512 or 1024) bounds the work-group: with 512 threads each
 // strip is twice as long and a thread may hold 256 VGPRs instead of 128.
 bool onchip_shape(const Geom &g, size_t elem, OnchipShape *sh, int max_threads = 1024);
+// RPR_OK when a kernel instance with work-groups of `threads` (512 or 1024)
+// serves grid g at element size elem, else RPR_ERR_UNSUPPORTED.
+rpr_status check_threads(const Geom &g, size_t elem, int threads);
 
 // Per right-hand side instance (propagate.hip, one object per kind and precision).
 template <int KIND, typename T>

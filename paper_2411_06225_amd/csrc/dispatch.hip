@@ -38,6 +38,36 @@ bool onchip_shape(const Geom &g, size_t elem, OnchipShape *sh, int max_threads)
     return true;
 }
 
+namespace {
+struct NoLaunch {
+    template <int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
+    rpr_status run() { return RPR_OK; }
+};
+template <typename T>
+rpr_status has_instance_t(const Geom &g, const OnchipShape &sh)
+{
+    NoLaunch f;
+    switch (g.kind) {
+    case RPR_BURGERS1D: return visit_shape_kind<RPR_BURGERS1D, T>(g, sh, f);
+    case RPR_DIFFREACT2D: return visit_shape_kind<RPR_DIFFREACT2D, T>(g, sh, f);
+    case RPR_BRUSS2D: return visit_shape_kind<RPR_BRUSS2D, T>(g, sh, f);
+    case RPR_SWE2D: return visit_shape_kind<RPR_SWE2D, T>(g, sh, f);
+    default: return fail(RPR_ERR_INVALID_ARG, "unknown right-hand side");
+    }
+}
+}  // namespace
+
+rpr_status check_threads(const Geom &g, size_t elem, int threads)
+{
+    OnchipShape sh;
+    if (!onchip_shape(g, elem, &sh, threads))
+        return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group's LDS in this build");
+    const rpr_status st = elem == 8 ? has_instance_t<double>(g, sh) : has_instance_t<float>(g, sh);
+    if (st != RPR_OK)
+        return fail(RPR_ERR_UNSUPPORTED, "no " + std::to_string(threads) + "-thread kernel for this grid");
+    return RPR_OK;
+}
+
 template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
                             const int *ctrl, hipStream_t st, int max_threads)

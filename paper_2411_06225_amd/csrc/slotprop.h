@@ -22,6 +22,28 @@
 
 namespace rpr {
 
+// Value of the same register in the lane one to the west (WEST) or east of
+// this one, across the whole wavefront (DPP wavefront shift / rotate by one
+// lane: wave_shr / wave_ror give lane i the value of lane i-1, wave_shl /
+// wave_rol that of lane i+1).  With ROT the row wraps around; without it the
+// lane at the row end reads 0 (bound control), and the caller accounts for
+// the wall in the centre weight instead.
+template <bool WEST, bool ROT, typename T>
+__device__ __forceinline__ T lane_neighbour(T v)
+{
+    constexpr int CTRL = WEST ? (ROT ? 0x13C : 0x138) : (ROT ? 0x134 : 0x130);
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+        const int rlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
+        const int rhi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
+        return __longlong_as_double((long long)(((unsigned long long)(unsigned)rhi << 32) | (unsigned)rlo));
+    } else {
+        const int b = __float_as_int(v);
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, b, CTRL, 0xf, 0xf, true));
+    }
+}
+
 // Elements of one padded LDS stage buffer.
 __host__ __device__ inline int padded_elems(const Geom &g)
 {
@@ -40,6 +62,11 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
 {
     constexpr int NS = kind_ns<KIND>();
     constexpr bool ONE_D = KIND == RPR_BURGERS1D;
+    // a grid row of 64 cells is exactly one wavefront: east / west neighbours
+    // come from the adjacent lanes, and only the first and last row of each
+    // strip go through LDS (for the strips above and below)
+    constexpr bool XLANE = !ONE_D && NX == 64 && FULL && KIND != RPR_SWE2D;
+    constexpr bool XROT = KIND == RPR_BRUSS2D;  // periodic in x
     const int t = threadIdx.x;
     const int nx = NX ? NX : g.nx, ny = NY ? NY : g.ny;
     const int nc = (NX && NY) ? NX * NY : g.nc;
@@ -110,14 +137,15 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
     T u[CPT][NS], acc[CPT][NS], y[CPT][NS], cmp[KAHAN ? CPT : 1][NS];
     auto publish = [&](T *buf, const int c) {
         const int pi = pbase0 + c * pstride;
-        // in 1D only the strip ends are read by other threads
-        if (ONE_D && !(c == 0 || c == nv - 1)) return;
+        // in 1D, and with lane neighbours in x, only the strip ends are read
+        // by other threads
+        if ((ONE_D || XLANE) && !(c == 0 || c == nv - 1)) return;
 #pragma unroll
         for (int sp = 0; sp < NS; ++sp) {
             T *o = buf + sp * PQ + pi;
             o[0] = y[c][sp];
-            if (gx0) o[ox0] = y[c][sp];
-            if (gx1) o[ox1] = y[c][sp];
+            if (!XLANE && gx0) o[ox0] = y[c][sp];
+            if (!XLANE && gx1) o[ox1] = y[c][sp];
             if (c == 0 && gfirst) o[ofirst] = y[c][sp];
             if (c == nv - 1 && glast) o[olast] = y[c][sp];
         }
@@ -137,6 +165,10 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
         }
     }
 
+    // weight of the centre cell in the x part of the Laplacian when the x
+    // neighbours come from lanes: -2, or -1 beside a zero-flux wall, whose
+    // mirror ghost (the cell itself) the lane exchange leaves out
+    const T mx = XROT ? T(-2) : T(-2) + T(x == 0 ? 1 : 0) + T(x == nx - 1 ? 1 : 0);
     int cur = 0;
     // which: 1..3 RK4 stages producing k1..k3, 4 the last RK4 stage, 0 Euler
     auto stage = [&](const int which) {
@@ -156,15 +188,23 @@ __device__ __forceinline__ void slot_propagate(const Geom &g, int method, long l
                         w[sp] = c == 0 ? r[-1] : prev[sp];
                         e[sp] = c + 1 < nv ? y[c + 1][sp] : r[1];
                     } else {
-                        w[sp] = r[-1];
-                        e[sp] = r[1];
+                        if constexpr (XLANE) {
+                            // w holds the sum of both x neighbours (a wall's mirror ghost left out)
+                            w[sp] = lane_neighbour<true, XROT>(y[c][sp]) + lane_neighbour<false, XROT>(y[c][sp]);
+                        } else {
+                            w[sp] = r[-1];
+                            e[sp] = r[1];
+                        }
                         s[sp] = c == 0 ? r[-P] : prev[sp];
                         n[sp] = c + 1 < nv ? y[c + 1][sp] : r[P];
                     }
                 }
                 T k[NS];
-                rhs_cell<KIND, T>(g, y[c], w, e, s, n, wall_w, wall_e, c == 0 && wall_s,
-                                  c == nv - 1 && wall_n, k);
+                if constexpr (XLANE)
+                    rhs_cell_xsum<KIND, T>(g, y[c], w, mx, s, n, k);
+                else
+                    rhs_cell<KIND, T>(g, y[c], w, e, s, n, wall_w, wall_e, c == 0 && wall_s,
+                                      c == nv - 1 && wall_n, k);
 #pragma unroll
                 for (int sp = 0; sp < NS; ++sp) {
                     prev[sp] = y[c][sp];

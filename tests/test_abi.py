@@ -37,8 +37,8 @@ def test_version_string():
     assert rpr.lib().rpr_version().decode().startswith("rpr ")
 
 
-def _prop(method=4, steps=10):
-    return rpr.rpr_propagator(method, 0, steps)
+def _prop(method=4, steps=10, threads=0):
+    return rpr.rpr_propagator(method, threads, steps)
 
 
 @pytest.mark.parametrize("kind,nx,ny,d,msg", [
@@ -61,9 +61,20 @@ def test_propagate_rejects_bad_propagator_and_overlap():
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(method=2)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(steps=0)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 5, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(threads=256)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    assert "threads" in rpr.last_error()
     # in and out overlapping
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 0, 1e-3, 2, 4096, 4096 + 512, None) == -1
     assert "overlap" in rpr.last_error()
+
+
+@pytest.mark.parametrize("kind,nx,ny,prec", [(1, 13, 9, 0), (0, 128, 1, 0), (1, 32, 32, 1), (2, 128, 128, 0)])
+def test_propagate_rejects_work_group_size_without_kernel(kind, nx, ny, prec):
+    # 512-thread kernels exist for the 64 x 64 grids only; decided on the host
+    h = rpr.make_rhs(kind, nx, ny)
+    d = rpr.nspecies(kind) * nx * ny
+    st = rpr.lib().rpr_propagate(C.byref(h), d, C.byref(_prop(threads=512)), prec, 1e-3, 1, 1 << 20, 1 << 30, None)
+    assert st == rpr.RPR_ERR_UNSUPPORTED
 
 
 def test_plan_create_rejects_bad_options():

@@ -104,6 +104,29 @@ def test_propagate_fp32_states_close_to_fp64_oracle(orc, case):
     assert err <= 2e-5
 
 
+@pytest.mark.parametrize("case", [c for c in PROP_CASES if c[0] in ("diffreact_64x64", "bruss_64x64")],
+                         ids=lambda c: c[0])
+@pytest.mark.parametrize("threads", [512, 1024])
+@pytest.mark.parametrize("prec", [rpr.RPR_FP64, rpr.RPR_MIXED], ids=["fp64", "fp32"])
+def test_propagate_every_work_group_size(orc, case, threads, prec):
+    """Both kernel instances of the 64 x 64 grids (strips of 8 rows on 512
+    threads, of 4 rows on 1024), RK4 and forward Euler."""
+    name, kind, nx, ny, dom, params, steps, dt, method = case
+    rng = np.random.default_rng(11)
+    d = rpr.nspecies(kind) * nx * ny
+    X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(2)])
+    pb = orc.problem(kind, nx, ny, dom, params)
+    h = rpr.make_rhs(kind, nx, ny, dom, params)
+    dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
+    for meth, st in ((method, steps), (1, 20)):
+        ref = orc.propagate_many(pb, meth, st, dt, X)
+        xin, xout = dev(X, dtype), torch.empty((2, d), dtype=dtype, device="cuda")
+        rpr.rpr_propagate(h, d, meth, st, prec, dt, 2, xin, xout, threads=threads)
+        err = rel_err(host(xout), ref)
+        print(name, threads, meth, "rel err %.2e" % err)
+        assert err <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
+
+
 def test_propagate_many_states_is_batched_identically(orc):
     # every state of a batch goes through the same kernel: equal inputs give bitwise equal outputs
     kind, nx, ny = rpr.RPR_DIFFREACT2D, 64, 64
