@@ -572,7 +572,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
                 return st;
             }
         }
-    if (use_net && (size_t)p->M * 32 * sizeof(double) > kMaxLds) {
+    if (use_net && ((size_t)p->M * 32 + 32 * 33) * sizeof(double) > kMaxLds) {
         delete p;
         return fail(RPR_ERR_UNSUPPORTED, "net.M too large for the ridge solve");
     }

@@ -34,11 +34,10 @@ rpr_status launch_stats(int n, int M, int d, const double *Phi, const TY *Y, con
                         double *Bm, const int *nrows_dev, hipStream_t st);
 
 // L L^T = G + lambda I (L, Lt = L^T: M x M workspaces), then W = (L L^T)^{-1} B.
-// A failed factorisation sets *fail, increments *fail_count and zeroes W.
-// With `done` non-null and *done != 0 both kernels return at once.
-rpr_status launch_ridge_solve(int M, int d, const double *G, double lambda, double *L, double *Lt,
-                              double *W, const double *Bm, int *fail, int *fail_count, const int *done,
-                              hipStream_t st);
+// M <= 512.  A failed factorisation sets *fail, increments *fail_count and
+// zeroes W.  With `done` non-null and *done != 0 both kernels return at once.
+rpr_status launch_ridge_solve(int M, int d, const double *G, double lambda, double *L, double *Lt, double *W,
+                              const double *Bm, int *fail, int *fail_count, const int *done, hipStream_t st);
 
 // Yhat = Phi W (n x d).
 rpr_status launch_readout(int n, int M, int d, const double *W, const double *Phi, double *Y, hipStream_t st);

@@ -276,57 +276,131 @@ template rpr_status launch_stats<float>(int, int, int, const double *, const flo
                                         double *, double *, const int *, hipStream_t);
 
 // ------------------------------------------------------------- cholesky ---
-// Left-looking (Cholesky-Crout) factorisation of S = G + lambda I, one column
-// per step: the finished row j of L is broadcast through LDS, its diagonal is
-// a block reduction, and thread i computes L[i][j] from its own row.
-// Writes L (lower, row-major) and Lt = L^T; a non-positive or NaN pivot sets
-// *fail = 1 and counts in *fail_count (both may be null).
+// Blocked left-looking Cholesky factorisation S = G + lambda I = L L^T with
+// 32-column panels, one work-group of 32 x 32 threads (thread (j, rl): panel
+// column j, row lane rl).  For the panel of columns c0 .. c0+nb:
+//   1. P = S[c0:, c0:c0+nb] - L[c0:, :c0] L[c0:c0+nb, :c0]^T for rows
+//      c0+rl+32q; the panel's top rows L[c0:c0+nb, :c0] are staged in LDS
+//      once, the other factor is read from L directly;
+//   2. the nb x nb top block of P is factored by one wavefront, lane = row,
+//      each row in registers, the columns passed between lanes by shuffles;
+//   3. every row x below it solves x L_kk^T = P[row] by substitution along
+//      the 32 lanes of its half-wavefront.
+// Writes L (lower, row-major, zero above) and Lt = L^T.  A non-positive or
+// NaN pivot sets *fail = 1, counts in *fail_count (both may be null) and
+// continues with pivot 1.
+constexpr int CB = 32;
+constexpr int CB_MAX_M = 512;
+
 __global__ __launch_bounds__(1024) void k_cholesky(int M, const double *__restrict__ G, double lambda,
                                                    double *__restrict__ L, double *__restrict__ Lt,
                                                    int *__restrict__ fail, int *__restrict__ fail_count,
                                                    const int *__restrict__ done)
 {
     if (done && *done) return;
-    if (threadIdx.x == 0 && fail) *fail = 0;
-    extern __shared__ double srow[];  // M + 32
-    double *red = srow + M;
+    extern __shared__ double top[];  // top[p * 33 + j] = L[c0 + j][p], p < c0
+    __shared__ double D[CB][CB + 1]; // diagonal block of the panel
     __shared__ int bad;
-    const int t = threadIdx.x, B = blockDim.x;
-    if (t == 0) bad = 0;
-    for (int i = t; i < M * M; i += B) {
+    const int t = threadIdx.x, j = t % CB, rl = t / CB;
+    if (t == 0) {
+        bad = 0;
+        if (fail) *fail = 0;
+    }
+    for (int i = t; i < M * M; i += CB * CB) {
         L[i] = 0.0;
         Lt[i] = 0.0;
     }
+    const int nblk = (M + CB - 1) / CB;
     __syncthreads();
-    for (int j = 0; j < M; ++j) {
-        // row j of L (entries < j) into LDS
-        for (int p = t; p < j; p += B) srow[p] = L[(size_t)j * M + p];
-        __syncthreads();
-        // diagonal: G[j][j] + lambda - sum_p L[j][p]^2, reduced in a fixed order
-        double part = 0.0;
-        for (int p = t; p < j; p += B) part = fma(srow[p], srow[p], part);
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-        if ((t & 63) == 0) red[t >> 6] = part;
-        __syncthreads();
-        if (t == 0) {
-            double ssum = 0.0;
-            for (int w = 0; w < (B + 63) / 64; ++w) ssum += red[w];
-            const double piv = G[(size_t)j * M + j] + lambda - ssum;
-            if (!(piv > 0.0)) bad = 1;
-            const double ljj = sqrt(piv > 0.0 ? piv : 1.0);
-            red[32] = ljj;
-            L[(size_t)j * M + j] = ljj;
-            Lt[(size_t)j * M + j] = ljj;
+
+    for (int k = 0; k < nblk; ++k) {
+        const int c0 = k * CB, nb = min(CB, M - c0);
+        const int nq = rl < M - c0 ? (M - c0 - rl + CB - 1) / CB : 0;  // rows c0 + rl + 32 q < M
+
+        // 1. panel update against the finished columns 0 .. c0
+        for (int e = t; e < c0 * CB; e += CB * CB) {
+            const int jj = e / c0, p = e % c0;  // coalesced along each row of L
+            top[p * (CB + 1) + jj] = jj < nb ? L[(size_t)(c0 + jj) * M + p] : 0.0;
         }
         __syncthreads();
-        const double ljj = red[32];
-        for (int i = j + 1 + t; i < M; i += B) {
-            double s = G[(size_t)i * M + j];
-            const double *Li = L + (size_t)i * M;
-            for (int p = 0; p < j; ++p) s = fma(-Li[p], srow[p], s);
-            const double lij = s / ljj;
-            L[(size_t)i * M + j] = lij;
-            Lt[(size_t)j * M + i] = lij;
+        // P of the rows below the block goes to L (solved in place in step 3),
+        // the block's own rows to D
+        for (int q = 0; q < nq; ++q) {
+            const int r = c0 + rl + CB * q;
+            const double *X = L + (size_t)r * M;
+            double sacc = 0.0;
+            // c0 is a multiple of 32: batches of 16 independent loads
+            for (int p0 = 0; p0 < c0; p0 += 16) {
+                double xv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) xv[u] = X[p0 + u];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) sacc = fma(xv[u], top[(p0 + u) * (CB + 1) + j], sacc);
+            }
+            if (q == 0) {
+                if (j < nb && rl < nb) {
+                    double sv = rl >= j ? G[(size_t)r * M + c0 + j] : 0.0;
+                    if (rl == j) sv += lambda;
+                    D[rl][j] = sv - sacc;
+                }
+            } else if (j < nb) {
+                L[(size_t)r * M + c0 + j] = G[(size_t)r * M + c0 + j] - sacc;
+            }
+        }
+        __syncthreads();
+
+        // 2. factor the diagonal block: wavefront 0, lane r = row r
+        if (t < 64) {
+            const int r = t & (CB - 1);
+            double row[CB];
+#pragma unroll
+            for (int x = 0; x < CB; ++x) row[x] = (r < nb && x < nb) ? D[r][x] : 0.0;
+            bool badw = false;
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) {
+                if (jj < nb) {
+                    const double piv = __shfl(row[jj], jj, CB);
+                    badw = badw || !(piv > 0.0);
+                    const double djj = sqrt(piv > 0.0 ? piv : 1.0);
+                    const double lr = r > jj ? row[jj] / djj : (r == jj ? djj : 0.0);
+                    row[jj] = lr;
+#pragma unroll
+                    for (int j2 = jj + 1; j2 < CB; ++j2) {
+                        if (j2 < nb) {
+                            const double lj = __shfl(lr, j2, CB);  // L[j2][jj]
+                            if (r >= j2) row[j2] = fma(-lr, lj, row[j2]);
+                        }
+                    }
+                }
+            }
+            if (r < nb)
+#pragma unroll
+                for (int x = 0; x < CB; ++x) D[r][x] = x <= r ? row[x] : 0.0;
+            if (t == 0 && badw) bad = 1;
+        }
+        __syncthreads();
+
+        // 3. rows below the block
+        const double rinv = j < nb ? 1.0 / D[j][j] : 0.0;
+        auto solve_row = [&](double pv) {
+            for (int jj = 0; jj < nb; ++jj) {
+                if (j == jj) pv *= rinv;
+                const double xb = __shfl(pv, jj, CB);
+                if (j > jj && j < nb) pv = fma(-xb, D[j][jj], pv);
+            }
+            return pv;
+        };
+        for (int q = 1; q < nq; ++q) {
+            const int r = c0 + rl + CB * q;
+            const double x = solve_row(j < nb ? L[(size_t)r * M + c0 + j] : 0.0);
+            if (j < nb) {
+                L[(size_t)r * M + c0 + j] = x;
+                Lt[(size_t)(c0 + j) * M + r] = x;
+            }
+        }
+        if (rl < nb && j <= rl) {
+            L[(size_t)(c0 + rl) * M + c0 + j] = D[rl][j];
+            Lt[(size_t)(c0 + j) * M + c0 + rl] = D[rl][j];
         }
         __syncthreads();
     }
@@ -337,73 +411,141 @@ __global__ __launch_bounds__(1024) void k_cholesky(int M, const double *__restri
 }
 
 // ---------------------------------------------------------------- solve ---
-// W = (L L^T)^{-1} B for a block of SC columns of B: forward substitution with
-// L, then backward with L^T, the block kept in LDS (M x SC doubles).  Each
-// column is served by 8 threads that split the inner product and combine it
-// with shuffles.  If the factorisation failed (*fail), W is set to zero.
-constexpr int SC = 32;
-
+// W = (L L^T)^{-1} B = L^-T L^-1 B for a block of 32 columns of B per
+// work-group of 256 threads.  Block forward then backward substitution over
+// 32-row blocks: each block first subtracts the product with the rows already
+// solved (column c = t % 32, rows g + 8 i, i < 4, for g = t / 32; the rows
+// of L or L^T read from memory, shared by the 32 lanes of a column group),
+// then is solved against its
+// diagonal block by substitution along the 32 lanes of a half-wavefront
+// (lane = row; each half-wavefront takes 4 columns).  The M x 32 block of B
+// stays in LDS.  If the factorisation failed (*fail), W is set to zero.
 __global__ __launch_bounds__(256) void k_trsm(int M, int d, const double *__restrict__ L,
                                               const double *__restrict__ Lt, const double *__restrict__ Bm,
                                               double *__restrict__ W, const int *__restrict__ fail,
                                               const int *__restrict__ done)
 {
     if (done && *done) return;
-    extern __shared__ double sb[];  // M x SC
-    const int j0 = blockIdx.x * SC;
-    const int col = threadIdx.x / 8, q = threadIdx.x % 8;
-    const int j = j0 + col;
+    extern __shared__ double Y[];  // M x 32, then the 32 x 33 staging tile
+    double *T = Y + (size_t)M * CB;
+    const int t = threadIdx.x, c = t % CB, g = t / CB;
+    const int j0 = blockIdx.x * CB;
     const bool failed = fail && *fail;
-    for (int i = threadIdx.x; i < M * SC; i += 256) {
-        const int r = i / SC, c = i % SC;
-        sb[i] = (j0 + c < d && !failed) ? Bm[(size_t)r * d + j0 + c] : 0.0;
+    for (int i = t; i < M * CB; i += 256) {
+        const int r = i / CB, cc = i % CB;
+        Y[i] = (!failed && j0 + cc < d) ? Bm[(size_t)r * d + j0 + cc] : 0.0;
+    }
+    const int nblk = (M + CB - 1) / CB;
+    // T[rr][p] = src[(r0 + rr) M + pc + p] for rr < rows left, p < pw, else 0
+    auto stage = [&](const double *src, int r0, int pc, int pw) {
+        __syncthreads();
+        for (int e = t; e < CB * CB; e += 256) {
+            const int rr = e / CB, p = e % CB;
+            T[rr * (CB + 1) + p] = (r0 + rr < M && p < pw) ? src[(size_t)(r0 + rr) * M + pc + p] : 0.0;
+        }
+        __syncthreads();
+    };
+    if (!failed) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool fwd = pass == 0;
+            for (int bi = 0; bi < nblk; ++bi) {
+                const int b = fwd ? bi : nblk - 1 - bi;
+                const int r0 = b * CB, rb = min(CB, M - r0);
+                // rows already solved: forward rows 0 .. r0 of L, backward rows
+                // r0+32 .. M of L^T (the columns below the block)
+                __syncthreads();  // the previous block's rows of Y are final
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                const int p_lo = fwd ? 0 : r0 + CB, p_hi = fwd ? r0 : M;
+                const double *src = fwd ? L : Lt;
+                const double *Lr[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = min(r0 + g + 8 * i, M - 1);  // rows past M compute unused sums
+                    Lr[i] = src + (size_t)r * M;
+                }
+                // batches of 8 columns: 32 independent loads in flight per thread
+                int p = p_lo;
+                for (; p + 8 <= p_hi; p += 8) {
+                    double lv[4][8];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) lv[i][u] = Lr[i][p + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const double y = Y[(p + u) * CB + c];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[i] = fma(lv[i][u], y, acc[i]);
+                    }
+                }
+                for (; p < p_hi; ++p) {
+                    const double y = Y[p * CB + c];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[i] = fma(Lr[i][p], y, acc[i]);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + g + 8 * i;
+                    if (r < M) Y[r * CB + c] -= acc[i];
+                }
+                // the diagonal block of L (lower triangle)
+                stage(L, r0, r0, rb);
+                const int rr = c;  // lane within the half-wavefront = row of the block
+                const double rinv = rr < rb ? 1.0 / T[rr * (CB + 1) + rr] : 0.0;
+                double z[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) z[i] = rr < rb ? Y[(r0 + rr) * CB + g + 8 * i] : 0.0;
+                for (int s = 0; s < rb; ++s) {
+                    const int jj = fwd ? s : rb - 1 - s;
+                    // forward: x_jj = z_jj / L[jj][jj], then z_rr -= L[rr][jj] x_jj (rr > jj);
+                    // backward: z_rr -= L[jj][rr] x_jj (rr < jj)
+                    const bool upd = fwd ? (rr > jj && rr < rb) : rr < jj;
+                    const double lw = upd ? (fwd ? T[rr * (CB + 1) + jj] : T[jj * (CB + 1) + rr]) : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (rr == jj) z[i] *= rinv;
+                        const double xb = __shfl(z[i], jj, CB);
+                        if (upd) z[i] = fma(-lw, xb, z[i]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (rr < rb) Y[(r0 + rr) * CB + g + 8 * i] = z[i];
+            }
+        }
     }
     __syncthreads();
-    if (!failed) {
-        // forward: z_r = (b_r - sum_{p<r} L[r][p] z_p) / L[r][r]
-        for (int r = 0; r < M; ++r) {
-            double s = 0.0;
-            const double *Lr = L + (size_t)r * M;
-            for (int p = q; p < r; p += 8) s = fma(Lr[p], sb[p * SC + col], s);
-            s += __shfl_xor(s, 1, 8);
-            s += __shfl_xor(s, 2, 8);
-            s += __shfl_xor(s, 4, 8);
-            if (q == 0) sb[r * SC + col] = (sb[r * SC + col] - s) / Lr[r];
-            __syncthreads();
-        }
-        // backward: w_r = (z_r - sum_{p>r} L[p][r] w_p) / L[r][r]
-        for (int r = M - 1; r >= 0; --r) {
-            double s = 0.0;
-            const double *Ltr = Lt + (size_t)r * M;
-            for (int p = r + 1 + q; p < M; p += 8) s = fma(Ltr[p], sb[p * SC + col], s);
-            s += __shfl_xor(s, 1, 8);
-            s += __shfl_xor(s, 2, 8);
-            s += __shfl_xor(s, 4, 8);
-            if (q == 0) sb[r * SC + col] = (sb[r * SC + col] - s) / Ltr[r];
-            __syncthreads();
-        }
-    }
-    for (int i = threadIdx.x; i < M * SC; i += 256) {
-        const int r = i / SC, c = i % SC;
-        if (j0 + c < d) W[(size_t)r * d + j0 + c] = sb[i];
+    for (int i = t; i < M * CB; i += 256) {
+        const int r = i / CB, cc = i % CB;
+        if (j0 + cc < d) W[(size_t)r * d + j0 + cc] = Y[i];
     }
 }
 
-rpr_status launch_ridge_solve(int M, int d, const double *G, double lambda, double *L, double *Lt,
-                              double *W, const double *Bm, int *fail, int *fail_count, const int *done,
-                              hipStream_t st)
+rpr_status launch_ridge_solve(int M, int d, const double *G, double lambda, double *L, double *Lt, double *W,
+                              const double *Bm, int *fail, int *fail_count, const int *done, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), (M + 40) * sizeof(double), st, M, G, lambda, L, Lt,
-                       fail, fail_count, done);
+    if (M > CB_MAX_M) return rpr::fail(RPR_ERR_UNSUPPORTED, "ridge solve: M > 512");
+    static bool chol_attr = false;
+    if (!chol_attr) {
+        RPR_HIP(hipFuncSetAttribute((const void *)k_cholesky, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kMaxLds - sizeof(double) * CB * (CB + 1) - 64)));
+        chol_attr = true;
+    }
+    // the largest panel offset c0 = 32 (ceil(M / 32) - 1) sets the staged rows
+    const size_t c0_max = (size_t)CB * ((M + CB - 1) / CB - 1);
+    const size_t top_lds = sizeof(double) * (c0_max > 0 ? c0_max : 1) * (CB + 1);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CB * CB), top_lds, st, M, G, lambda, L, Lt, fail, fail_count,
+                       done);
     RPR_HIP(hipGetLastError());
-    const size_t lds = (size_t)M * SC * sizeof(double);
+    const size_t lds = ((size_t)M * CB + CB * (CB + 1)) * sizeof(double);
     if (lds > kMaxLds) return rpr::fail(RPR_ERR_UNSUPPORTED, "ridge solve: M too large for LDS block");
     static bool attr_set = false;
     if (!attr_set) {
         RPR_HIP(hipFuncSetAttribute((const void *)k_trsm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_trsm, dim3((d + SC - 1) / SC), dim3(256), lds, st, M, d, L, Lt, Bm, W, fail, done);
+    hipLaunchKernelGGL(k_trsm, dim3((d + CB - 1) / CB), dim3(256), lds, st, M, d, L, Lt, Bm, W, fail, done);
     RPR_HIP(hipGetLastError());
     return RPR_OK;
 }

@@ -165,7 +165,11 @@ def test_features_match_oracle(orc, n, M, d, act):
     assert err <= 1e-13
 
 
-@pytest.mark.parametrize("n,M,d", [(40, 30, 77), (12, 100, 128), (300, 200, 1000), (1, 5, 3)])
+# M around the 32-column panel size of the factorisation (one block, ragged
+# last block, several blocks, the largest M) and d around the 32-column
+# blocks of the solve
+@pytest.mark.parametrize("n,M,d", [(40, 30, 77), (12, 100, 128), (300, 200, 1000), (1, 5, 3), (50, 32, 32),
+                                   (70, 33, 65), (90, 64, 31), (150, 97, 200), (600, 512, 300)])
 def test_ridge_fit_matches_oracle(orc, n, M, d):
     rng = np.random.default_rng(n * M)
     Phi = np.tanh(rng.standard_normal((n, M)))
@@ -179,6 +183,20 @@ def test_ridge_fit_matches_oracle(orc, n, M, d):
     err = rel_err(host(W), ref)
     print("ridge", n, M, d, "kappa %.1e rel err %.2e tol %.1e" % (kappa, err, tol))
     assert err <= tol
+
+
+def test_ridge_fit_reports_non_positive_definite():
+    # a NaN feature makes every pivot after it NaN: the factorisation fails
+    # (reported, W zeroed) instead of returning garbage
+    rng = np.random.default_rng(5)
+    n, M, d = 20, 40, 50
+    Phi = np.tanh(rng.standard_normal((n, M)))
+    Phi[3, 7] = np.nan
+    W = torch.full((M, d), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(rpr.RprError) as e:
+        rpr.rpr_ridge_fit(M, d, n, dev(Phi), dev(rng.standard_normal((n, d))), 1e-3, W)
+    assert e.value.status == rpr.RPR_ERR_NOT_SPD
+    assert np.all(host(W) == 0.0)
 
 
 def test_readout_matches_oracle_formula():
