@@ -195,6 +195,8 @@ struct rpr_plan {
            *u0max = nullptr;
     int *ok = nullptr, *nrows = nullptr, *L_hist = nullptr, *cfail = nullptr, *u0bad = nullptr;
     uint16_t *Ab = nullptr;   // bf16 copy of A (reduced precision)
+    double *At = nullptr;     // A^T, d x M (the chain's hidden layer, plain precision)
+    uint16_t *Abt = nullptr;  // bf16 A^T, d x M (reduced precision)
     float *fpart32 = nullptr; // split-K partials of the bf16 feature GEMM
     Ctrl *ctrl = nullptr;
     Ctrl *ctrl_host = nullptr;  // pinned
@@ -208,6 +210,7 @@ struct rpr_plan {
     double graph_s = 0.0;               // input scale the captured block was built for
     hipStream_t cap_stream = nullptr;   // private stream the block is captured on
     void *gchain = nullptr;             // device ChainArgs<T> of the captured chain
+    double *hpart = nullptr;            // chain: per-work-group hidden-layer partial sums (grid x M)
     std::vector<double> bscale;         // batch: input scales the captured block was built for
     // batch plans: one sub-plan per instance plus the shared persistent fine solve
     std::vector<rpr_plan *> sub;
@@ -230,12 +233,12 @@ static void plan_free(rpr_plan *p)
 {
     for (rpr_plan *q : p->sub) plan_free(q);
     p->sub.clear();
-    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain};
+    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain, p->hpart};
     for (void *b : bb)
         if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
                     p->Lt, p->Bm, p->W, p->phi, p->part, p->chg_hist, p->u0max, p->ok, p->nrows, p->L_hist,
-                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32};
+                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At, p->Abt};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->ctrl_host) (void)hipHostFree(p->ctrl_host);
@@ -302,10 +305,16 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
             RPR_TRY(launch_uniform(seed, 0, (int64_t)M * d, p->A, nullptr));
             RPR_TRY(launch_uniform(seed, (uint64_t)M * d, M, p->zeta, nullptr));
         }
+        // the chain's hidden layer reads the weights column by column (A^T)
         if (p->feat_bf16) {
             RPR_TRY(dalloc(&p->Ab, (size_t)M * d));
+            RPR_TRY(dalloc(&p->Abt, (size_t)M * d));
             RPR_TRY(dalloc(&p->fpart32, (size_t)feat_bf16_splits(d) * N * M));
             RPR_TRY(launch_to_bf16(p->A, p->Ab, (size_t)M * d, nullptr));
+            RPR_TRY(launch_transpose<uint16_t>(p->Ab, p->Abt, M, d, nullptr));
+        } else {
+            RPR_TRY(dalloc(&p->At, (size_t)M * d));
+            RPR_TRY(launch_transpose<double>(p->A, p->At, M, d, nullptr));
         }
         RPR_HIP(hipDeviceSynchronize());
     }
@@ -461,10 +470,13 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
         a.Gc = Gc;
         a.gtmp = static_cast<T *>(p->gtmp);
         a.phi = p->phi;
+        a.hpart = p->hpart;
         a.A = p->A;
         a.zeta = p->zeta;
         a.W = p->W;
         a.Ab = p->Ab;
+        a.At = p->At;
+        a.Abt = p->Abt;
         a.part = p->part;
         a.ctrl = p->ctrl;
         float best = 1e30f;
@@ -611,6 +623,17 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     if (nwg > max_wg) nwg = max_wg;
     if (nwg > 4096) nwg = 4096;
     p->nwg = nwg < 1 ? 1 : nwg;
+    if (use_net) {
+        // the autotuner tries grids of up to one work-group per CU
+        const int hmax = p->autotune ? std::max(p->nwg, std::min(cus, max_wg)) : p->nwg;
+        st = dalloc(&p->hpart, (size_t)hmax * p->M);
+        if (st != RPR_OK) {
+            const std::string keep = g_err;
+            plan_free(p);
+            g_err = keep;
+            return st;
+        }
+    }
     if (p->autotune) {
         st = p->esz == 8 ? autotune_plan<double>(p, max_wg, cus) : autotune_plan<float>(p, max_wg, cus);
         if (st != RPR_OK) {
@@ -644,10 +667,13 @@ static ChainArgs<T> chain_args(rpr_plan *p, double s)
     a.Gc = static_cast<T *>(p->Gc);
     a.gtmp = static_cast<T *>(p->gtmp);
     a.phi = p->phi;
+    a.hpart = p->hpart;
     a.A = p->A;
     a.zeta = p->zeta;
     a.W = p->W;
     a.Ab = p->Ab;
+    a.At = p->At;
+    a.Abt = p->Abt;
     a.part = p->part;
     a.ctrl = p->ctrl;
     a.L_hist = p->L_hist;

@@ -25,8 +25,11 @@ struct ChainArgs {
     T *Gc;                     // (N+1) x d coarse values G(U_{i-1}) (row i)
     T *gtmp;                   // d: coarse value of the current slot
     double *phi;               // M: hidden layer of the current slot
+    double *hpart;             // grid x M: per-work-group partial sums of A x / s
     const double *A, *zeta, *W;
     const uint16_t *Ab;        // bf16 copy of A (reduced-precision plans), else null
+    const double *At;          // d x M: A^T (plain plans)
+    const uint16_t *Abt;       // d x M: bf16 A^T (reduced-precision plans)
     double *part;              // (N+1) x grid: per-work-group change maxima
     Ctrl *ctrl;
     int *L_hist;               // (N+1)

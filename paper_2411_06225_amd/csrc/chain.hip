@@ -11,11 +11,11 @@
 // (eq. "fpara").
 //
 // One cooperative launch runs a whole sweep.  Per slot, work-group 0 runs the
-// coarse propagator on chip while the other work-groups compute the hidden
-// layer sigma(A x / s + zeta), one neuron per work-group at a time (both need
-// only U_{i-1}); after a grid barrier every work-group applies the readout,
-// the update and the change norm to its own block of columns; a second grid
-// barrier publishes U_i.  The converged-slot counter L and the done flag live
+// coarse propagator on chip while the other work-groups finish the hidden
+// layer sigma(A x / s + zeta) of U_{i-1}; after a grid barrier every
+// work-group applies the readout, the update and the change norm to its own
+// block of columns of U_i and sums the hidden layer of U_i over those columns;
+// a second grid barrier publishes U_i and the partial sums.  The converged-slot counter L and the done flag live
 // in the device control block, so the host never waits on the sweep.
 #include <hip/hip_cooperative_groups.h>
 
@@ -63,7 +63,103 @@ __device__ __forceinline__ double nan_max(double a, double b)
     return a > b ? a : b;
 }
 
-// One sweep of one instance.  wg / nwg: this work-group and the number of
+// Hidden layer phi = sigma(A x / s + zeta), split over the work-groups by
+// columns: the work-group that owns columns j0 .. j1 of a slot state (it has
+// just written them) sums A[m][j] x_j / s over them for every neuron m
+// (hidden_partial), and after the grid barrier the owner of neuron m adds the
+// grid's partial sums in work-group order and applies sigma (hidden_finish).
+// No work-group reads another's columns of x.  Reduced precision: bf16
+// weights and inputs (products exact), sums in double, sigma in FP32, bf16
+// output.
+template <typename T>
+__device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
+                                               const int j1, const int wg, double *red)
+{
+    // whole wavefronts only (a block narrower than a wavefront is one partial
+    // wavefront of WL lanes); a trailing partial wavefront stays idle.
+    // Wavefront w takes columns j0 + w cpw .. j0 + (w+1) cpw, lane l the
+    // neurons l, l + WL, ...; the wavefronts' sums meet in LDS (red, nw x M
+    // doubles) and are added in wavefront order.
+    const int t = threadIdx.x, B = blockDim.x, d = a.g.d;
+    const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
+    const int lane = t & 63, wv = t >> 6;
+    if (wv < nw) {
+        const int cpw = (j1 - j0 + nw - 1) / nw;
+        const int c0 = j0 + wv * cpw, c1 = min(j1, c0 + cpw);
+        const bool bf = a.Ab != nullptr;
+        const float xsf = (float)a.inv_s;
+        constexpr int MPL = 4, CB4 = 4;  // neurons per lane and pass, columns per load batch
+        for (int mb = 0; mb < a.M; mb += WL * MPL) {
+            double p[MPL];
+#pragma unroll
+            for (int u = 0; u < MPL; ++u) p[u] = 0.0;
+            for (int cb = c0; cb < c1; cb += CB4) {
+                double xv[CB4], wv4[MPL][CB4];
+#pragma unroll
+                for (int k = 0; k < CB4; ++k) {
+                    const int j = cb + k;
+                    xv[k] = j < c1 ? (bf ? (double)from_bf16(to_bf16(float(x[j]) * xsf)) : double(x[j]) * a.inv_s)
+                                   : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < MPL; ++u) {
+                    const int m = mb + lane + WL * u;
+#pragma unroll
+                    for (int k = 0; k < CB4; ++k) {
+                        const int j = cb + k;
+                        wv4[u][k] = (m < a.M && j < c1) ? (bf ? (double)from_bf16(a.Abt[(size_t)j * a.M + m])
+                                                                : a.At[(size_t)j * a.M + m])
+                                                         : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < MPL; ++u)
+#pragma unroll
+                    for (int k = 0; k < CB4; ++k) p[u] = fma(wv4[u][k], xv[k], p[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < MPL; ++u) {
+                const int m = mb + lane + WL * u;
+                if (m < a.M) red[wv * a.M + m] = p[u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int m = t; m < a.M; m += B) {
+        double z = 0.0;
+        for (int w = 0; w < nw; ++w) z += red[w * a.M + m];
+        a.hpart[(size_t)wg * a.M + m] = z;
+    }
+}
+
+// Neurons m = hw, hw + nh, ... of this work-group: one wavefront per neuron.
+template <typename T>
+__device__ __forceinline__ void hidden_finish(const ChainArgs<T> &a, const int hw, const int nh, const int nwg)
+{
+    const int t = threadIdx.x, B = blockDim.x;
+    const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
+    const int lane = t & 63, wv = t >> 6;
+    for (int m = hw + nh * wv; wv < nw && m < a.M; m += nh * nw) {
+        double z = 0.0;
+        for (int w = lane; w < nwg; w += WL) z += a.hpart[(size_t)w * a.M + m];
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(z, off, 64);
+            if (lane + off < WL) z += o;
+        }
+        if (lane == 0) {
+            if (a.Ab != nullptr) {
+                const float zf = float(z) + (float)a.zeta[m];
+                const float sg = a.act == RPR_RELU ? (zf > 0.0f ? zf : 0.0f) : tanhf(zf);
+                a.phi[m] = (double)from_bf16(to_bf16(sg));
+            } else {
+                z += a.zeta[m];
+                a.phi[m] = a.act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
+            }
+        }
+    }
+}
+
+// One sweep of one instance.  wg / nwg: this work-group and the number of// One sweep of one instance.  wg / nwg: this work-group and the number of
 // work-groups sharing the instance; sync(): a barrier over those work-groups
 // (a grid barrier, or a work-group barrier when nwg == 1).
 template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, typename Sync>
@@ -97,11 +193,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     const int chunk = (d + nwg - 1) / nwg;
     const int j0 = wg * chunk, j1 = min(d, j0 + chunk);
 
-    // exact slot
+    const bool net = a.mode == CHAIN_RANDNET;
+    // exact slot, and the hidden-layer partial sums of its columns
     for (int j = j0 + t; j < j1; j += B) a.U[(size_t)(L + 1) * d + j] = a.Fv[(size_t)(L + 1) * d + j];
+    if (net && L + 2 <= N) {
+        __syncthreads();
+        hidden_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, scratch);
+    }
     sync();
 
-    const bool net = a.mode == CHAIN_RANDNET;
     for (int i = L + 2; i <= N; ++i) {
         const T *x = a.U + (size_t)(i - 1) * d;
         // ---- phase 1: coarse solve (work-group 0) and hidden layer (the others)
@@ -109,28 +209,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
             slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG, x, a.gtmp, lds);
             __syncthreads();
         }
-        if (net && (wg > 0 || nwg == 1)) {
-            const int first = nwg == 1 ? 0 : wg - 1, step = nwg == 1 ? 1 : nwg - 1;
-            for (int m = first; m < a.M; m += step) {
-                if (a.Ab != nullptr) {
-                    // reduced precision: bf16 weights and inputs, FP32 sums and sigma, bf16 output
-                    const uint16_t *Am = a.Ab + (size_t)m * d;
-                    const float xs = (float)a.inv_s;
-                    float part = 0.0f;
-                    for (int j = t; j < d; j += B)
-                        part = fmaf(from_bf16(Am[j]), from_bf16(to_bf16(float(x[j]) * xs)), part);
-                    const float z = block_sum_f(part, reinterpret_cast<float *>(scratch)) + (float)a.zeta[m];
-                    const float sg = a.act == RPR_RELU ? (z > 0.0f ? z : 0.0f) : tanhf(z);
-                    if (t == 0) a.phi[m] = (double)from_bf16(to_bf16(sg));
-                } else {
-                    const double *Am = a.A + (size_t)m * d;
-                    double part = 0.0;
-                    for (int j = t; j < d; j += B) part = fma(Am[j], double(x[j]) * a.inv_s, part);
-                    const double z = block_sum(part, scratch) + a.zeta[m];
-                    if (t == 0) a.phi[m] = a.act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
-                }
-            }
-        }
+        if (net && (wg > 0 || nwg == 1)) hidden_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg);
         sync();
 
         // ---- phase 2: readout, update and change norm on this block of columns
@@ -139,32 +218,61 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
         T *Ui = a.U + (size_t)i * d;
         T *Gci = a.Gc + (size_t)i * d;
         if (net) {
-            double *sphi = scratch;            // M
-            double *red = scratch + a.M;       // B
+            // readout W^T phi on columns j0 .. j1: wavefront w sums the neurons
+            // m = w, w + nw, ... for 2 tiles of 64 columns at a time, then
+            // wavefront q < 2 adds the nw partial sums of tile q in order
+            constexpr int TPT = 2;
+            const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;  // whole wavefronts, as above
+            const int lane = t & 63, wv = t >> 6;
+            double *sphi = scratch;                                        // M
+            double *red = scratch + ((a.M + 63) / 64) * 64;                // nw x TPT x WL
             for (int m = t; m < a.M; m += B) sphi[m] = a.phi[m];
             __syncthreads();
-            // width-cw column tiles; each column's sum split over B / cw neuron groups
-            const int cw = (j1 - j0) < 64 ? ((j1 - j0) > 0 ? (j1 - j0) : 1) : 64;
-            const int groups = B / cw;
-            const int jj = t % cw, mg = t / cw;
-            for (int jb = j0; jb < j1; jb += cw) {
-                const int j = jb + jj;
-                double acc = 0.0;
-                if (mg < groups && j < j1)
-                    for (int m = mg; m < a.M; m += groups) acc = fma(a.W[(size_t)m * d + j], sphi[m], acc);
-                if (mg < groups) red[mg * cw + jj] = acc;
+            for (int jb = j0; jb < j1; jb += WL * TPT) {
+                if (wv < nw) {
+                    double acc[TPT];
+#pragma unroll
+                    for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
+                    // batches of 8 neurons x TPT columns: 16 loads in flight
+                    for (int m0 = wv; m0 < a.M; m0 += 8 * nw) {
+                        double wr[8][TPT];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int m = m0 + u * nw;
+#pragma unroll
+                            for (int q = 0; q < TPT; ++q) {
+                                const int j = jb + WL * q + lane;
+                                wr[u][q] = (m < a.M && j < j1) ? a.W[(size_t)m * d + j] : 0.0;
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int m = m0 + u * nw;
+                            const double ph = m < a.M ? sphi[m] : 0.0;
+#pragma unroll
+                            for (int q = 0; q < TPT; ++q) acc[q] = fma(wr[u][q], ph, acc[q]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < TPT; ++q) red[(wv * TPT + q) * WL + lane] = acc[q];
+                }
                 __syncthreads();
-                if (mg == 0 && j < j1) {
-                    double c = 0.0;
-                    for (int q = 0; q < groups; ++q) c += red[q * cw + jj];
-                    const T gv = a.gtmp[j];
-                    const T unew = T(double(gv) + c);
-                    emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
-                    Ui[j] = unew;
-                    Gci[j] = gv;
+                for (int q = wv; q < TPT && wv < nw; q += nw) {
+                    const int j = jb + WL * q + lane;
+                    if (j < j1) {
+                        double c = 0.0;
+                        for (int w = 0; w < nw; ++w) c += red[(w * TPT + q) * WL + lane];
+                        const T gv = a.gtmp[j];
+                        const T unew = T(double(gv) + c);
+                        emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
+                        Ui[j] = unew;
+                        Gci[j] = gv;
+                    }
                 }
                 __syncthreads();
             }
+            // hidden-layer partial sums of the new state's columns, for slot i + 1
+            if (i < N) hidden_partial(a, Ui, j0, j1, wg, scratch);
         } else {
             for (int j = j0 + t; j < j1; j += B) {
                 const T gv = a.gtmp[j];
@@ -174,8 +282,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
                 Gci[j] = gv;
             }
         }
-        // work-group maximum (order-free, NaN already mapped to +inf)
-        for (int off = 32; off > 0; off >>= 1) emax = nan_max(emax, __shfl_down(emax, off, 64));
+        // work-group maximum (order-free, NaN already mapped to +inf); only
+        // lanes that exist in a partial wavefront take part
+        {
+            const int wl = min(64, B - (t & ~63));
+            for (int off = 32; off > 0; off >>= 1) {
+                const double o = __shfl_down(emax, off, 64);
+                if ((t & 63) + off < wl) emax = nan_max(emax, o);
+            }
+        }
         __syncthreads();
         if ((t & 63) == 0) scratch[t >> 6] = emax;
         __syncthreads();
@@ -250,8 +365,8 @@ struct ChainMultiLauncher {
 };
 
 template <int KIND, typename T>
-rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax, const OnchipShape &sh,
-                                   int M, hipStream_t st)
+rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax,
+                                   const OnchipShape &sh, int M, hipStream_t st)
 {
     ChainMultiLauncher<KIND, T> L{args_dev, n_inst, sh, M, st};
     return visit_shape_kind<KIND, T>(gmax, sh, L);

@@ -92,8 +92,10 @@ template rpr_status launch_propagate<float>(const Geom &, int, int64_t, double, 
 size_t chain_lds(const OnchipShape &sh, int M)
 {
     // the coarse solver's stage buffers, or the readout's neuron vector and
-    // partial sums, whichever is larger
-    const size_t red = (size_t)(M + 1024 + 64) * sizeof(double);
+    // partial sums (up to 16 wavefronts x 2 tiles x 64 columns), or the hidden
+    // layer's per-wavefront sums (16 x M), whichever is larger
+    size_t red = (size_t)(M + 2048 + 64) * sizeof(double);
+    if ((size_t)16 * M * sizeof(double) > red) red = (size_t)16 * M * sizeof(double);
     return sh.lds > red ? sh.lds : red;
 }
 

@@ -39,6 +39,10 @@ rpr_status launch_stats(int n, int M, int d, const double *Phi, const TY *Y, con
 rpr_status launch_ridge_solve(int M, int d, const double *G, double lambda, double *L, double *Lt, double *W,
                               const double *Bm, int *fail, int *fail_count, const int *done, hipStream_t st);
 
+// out (cols x rows) = in^T for a row-major rows x cols matrix.
+template <typename E>
+rpr_status launch_transpose(const E *in, E *out, int rows, int cols, hipStream_t st);
+
 // Yhat = Phi W (n x d).
 rpr_status launch_readout(int n, int M, int d, const double *W, const double *Phi, double *Y, hipStream_t st);
 

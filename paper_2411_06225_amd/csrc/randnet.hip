@@ -110,6 +110,33 @@ rpr_status launch_to_bf16(const double *in, uint16_t *out, size_t n, hipStream_t
     return RPR_OK;
 }
 
+// out (cols x rows) = in^T (in: rows x cols, row-major), through 32 x 32 LDS
+// tiles (padded against bank conflicts); 32 x 8 threads.
+template <typename E>
+__global__ __launch_bounds__(256) void k_transpose(const E *__restrict__ in, E *__restrict__ out, int rows, int cols)
+{
+    __shared__ E tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    for (int k = ty; k < 32; k += 8)
+        if (r0 + k < rows && c0 + tx < cols) tile[k][tx] = in[(size_t)(r0 + k) * cols + c0 + tx];
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8)
+        if (c0 + k < cols && r0 + tx < rows) out[(size_t)(c0 + k) * rows + r0 + tx] = tile[tx][k];
+}
+
+template <typename E>
+rpr_status launch_transpose(const E *in, E *out, int rows, int cols, hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0) return RPR_OK;
+    hipLaunchKernelGGL(k_transpose<E>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, in, out, rows,
+                       cols);
+    RPR_HIP(hipGetLastError());
+    return RPR_OK;
+}
+template rpr_status launch_transpose<double>(const double *, double *, int, int, hipStream_t);
+template rpr_status launch_transpose<uint16_t>(const uint16_t *, uint16_t *, int, int, hipStream_t);
+
 // Work-group tile: 64 rows of X x 64 neurons, 4 waves; wave w owns rows
 // 16w..16w+15 and all four 16-neuron tiles.  K advances 32 at a time through
 // LDS.  Operand layout of the 16x16x32 instruction: lane l holds A[l%16][8(l/16)..+7],
