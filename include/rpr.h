@@ -80,11 +80,17 @@ typedef enum { RPR_RK1 = 1, RPR_RK4 = 4 } rpr_method; /* forward Euler, classica
 
 typedef struct {
     int32_t method;            /* rpr_method */
-    int32_t threads;           /* work-group size of the slot kernel: 0 automatic
-                                  (the autotuner's choice, else 1024); 512 or 1024
-                                  to fix it (512 exists for the 64 x 64 grids only,
-                                  others give RPR_ERR_UNSUPPORTED).  Batch plans
-                                  choose their own and ignore it. */
+    int32_t threads;           /* kernel of the propagator: 0 automatic (on chip,
+                                  one work-group per slot state, with the
+                                  autotuner's work-group size, else 1024, when the
+                                  state fits one work-group; otherwise tiled);
+                                  512 or 1024 fix the on-chip work-group size (512
+                                  exists for the 64 x 64 grids only); 256 selects
+                                  the tiled form (2D grids: slot states in memory,
+                                  one pass over 64 x 16-cell tiles per RK stage).
+                                  Other sizes give RPR_ERR_INVALID_ARG, sizes
+                                  without a kernel RPR_ERR_UNSUPPORTED.  Batch
+                                  plans choose their own and ignore it. */
     int64_t steps;             /* fixed steps per slice, >= 1 */
 } rpr_propagator;
 

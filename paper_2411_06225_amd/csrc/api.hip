@@ -92,8 +92,8 @@ static rpr_status check_prop(const rpr_propagator *P, const char *name)
     if (!P) return fail(RPR_ERR_INVALID_ARG, std::string(name) + " is NULL");
     if (P->method != RPR_RK1 && P->method != RPR_RK4)
         return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".method must be RPR_RK1 or RPR_RK4");
-    if (P->threads != 0 && P->threads != 512 && P->threads != 1024)
-        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".threads must be 0, 512 or 1024");
+    if (P->threads != 0 && P->threads != TILED_THREADS && P->threads != 512 && P->threads != 1024)
+        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".threads must be 0, 256, 512 or 1024");
     if (P->steps < 1) return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".steps must be >= 1");
     return RPR_OK;
 }
@@ -211,6 +211,8 @@ struct rpr_plan {
     hipStream_t cap_stream = nullptr;   // private stream the block is captured on
     void *gchain = nullptr;             // device ChainArgs<T> of the captured chain
     double *hpart = nullptr;            // chain: per-work-group hidden-layer partial sums (grid x M)
+    void *fwork = nullptr;              // tiled F: u, acc, ya, yb, cmp (N x d each)
+    void *gwork = nullptr;              // tiled coarse solver: u, acc, ya, yb, cmp (d each)
     std::vector<double> bscale;         // batch: input scales the captured block was built for
     // batch plans: one sub-plan per instance plus the shared persistent fine solve
     std::vector<rpr_plan *> sub;
@@ -229,11 +231,20 @@ struct rpr_plan {
     std::vector<double> ch;
 };
 
+// Work arrays of the tiled propagator carved from one block of n x 5 values.
+template <typename T>
+static TiledWork<T> tiled_work(void *base, size_t n)
+{
+    if (!base) return TiledWork<T>{};
+    T *b = static_cast<T *>(base);
+    return TiledWork<T>{b, b + n, b + 2 * n, b + 3 * n, sizeof(T) == 4 ? b + 4 * n : nullptr};
+}
+
 static void plan_free(rpr_plan *p)
 {
     for (rpr_plan *q : p->sub) plan_free(q);
     p->sub.clear();
-    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain, p->hpart};
+    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain, p->hpart, p->fwork, p->gwork};
     for (void *b : bb)
         if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
@@ -276,6 +287,14 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
     RPR_TRY(dalloc(&c, sd * p->esz)); p->Fv = c;
     RPR_TRY(dalloc(&c, sd * p->esz)); p->Gc = c;
     RPR_TRY(dalloc(&c, (size_t)d * p->esz)); p->gtmp = c;
+    if (p->shF.maxt == TILED_THREADS) {
+        RPR_TRY(dalloc(&c, 5 * (size_t)N * d * p->esz));
+        p->fwork = c;
+    }
+    if (p->shG.maxt == TILED_THREADS) {
+        RPR_TRY(dalloc(&c, 5 * (size_t)d * p->esz));
+        p->gwork = c;
+    }
     RPR_TRY(dalloc(&p->part, (size_t)(N + 1) * 4096));
     RPR_TRY(dalloc(&p->ctrl, 1));
     RPR_TRY(dalloc(&p->L_hist, N + 1));
@@ -430,7 +449,8 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
     if (rc != RPR_OK) { done(); return rc; }
 
     // fine propagator: 1024-thread (short strips) or 512-thread (long strips) work-groups
-    if (!haveF && p->F.threads == 0) {
+    const bool tiledF = p->shF.maxt == TILED_THREADS;
+    if (!haveF && p->F.threads == 0 && !tiledF) {
         const int64_t steps = p->F.steps < 32 ? p->F.steps : 32;
         float best = 1e30f;
         int best_mt = p->shF.maxt;
@@ -448,8 +468,10 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
         }
         g_tune[kf] = best_mt;
     }
-    const int mt = p->F.threads ? p->F.threads : g_tune[kf];
-    if (!onchip_shape(g, p->esz, &p->shF, mt)) { done(); return fail(RPR_ERR_HIP, "autotune: lost the F shape"); }
+    if (!tiledF) {
+        const int mt = p->F.threads ? p->F.threads : g_tune[kf];
+        if (!onchip_shape(g, p->esz, &p->shF, mt)) { done(); return fail(RPR_ERR_HIP, "autotune: lost the F shape"); }
+    }
 
     // chain grid: one work-group, or a quarter, half or all of the CUs
     if (!haveC) {
@@ -471,6 +493,7 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
         a.gtmp = static_cast<T *>(p->gtmp);
         a.phi = p->phi;
         a.hpart = p->hpart;
+        a.gw = tiled_work<T>(p->gwork, (size_t)d);
         a.A = p->A;
         a.zeta = p->zeta;
         a.W = p->W;
@@ -571,19 +594,25 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     const double T = (tN - t0) / N;
     p->dtF = T / (double)F->steps;
     p->dtG = T / (double)G->steps;
-    if (!onchip_shape(g, p->esz, &p->shF, F->threads ? F->threads : 1024) ||
-        !onchip_shape(g, p->esz, &p->shG, G->threads ? G->threads : 1024)) {
-        delete p;
-        return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group's LDS in this build");
-    }
-    for (const rpr_propagator *P : {F, G})
-        if (P->threads) {
-            const rpr_status st = check_threads(g, p->esz, P->threads);
-            if (st != RPR_OK) {
+    // on chip when the slot state fits one work-group (or as F/G.threads say),
+    // else the tiled form
+    for (const rpr_propagator *P : {F, G}) {
+        OnchipShape &sh = P == F ? p->shF : p->shG;
+        bool tiled = P->threads == TILED_THREADS;
+        if (!tiled && !onchip_shape(g, p->esz, &sh, P->threads ? P->threads : 1024)) {
+            if (P->threads) {
                 delete p;
-                return st;
+                return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group of that size");
             }
+            tiled = true;
         }
+        const rpr_status st = check_threads(g, p->esz, tiled ? TILED_THREADS : (P->threads ? P->threads : 1024));
+        if (st != RPR_OK) {
+            delete p;
+            return st;
+        }
+        if (tiled) sh = tiled_shape(g, p->esz);
+    }
     if (use_net && ((size_t)p->M * 32 + 32 * 33) * sizeof(double) > kMaxLds) {
         delete p;
         return fail(RPR_ERR_UNSUPPORTED, "net.M too large for the ridge solve");
@@ -619,7 +648,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const double work = (double)g.d * (use_net ? p->M : 1);
-    int nwg = work < 65536.0 ? 1 : cus;
+    int nwg = (work < 65536.0 && p->shG.maxt != TILED_THREADS) ? 1 : cus;  // the tiled coarse solver needs the grid
     if (nwg > max_wg) nwg = max_wg;
     if (nwg > 4096) nwg = 4096;
     p->nwg = nwg < 1 ? 1 : nwg;
@@ -668,6 +697,7 @@ static ChainArgs<T> chain_args(rpr_plan *p, double s)
     a.gtmp = static_cast<T *>(p->gtmp);
     a.phi = p->phi;
     a.hpart = p->hpart;
+    a.gw = tiled_work<T>(p->gwork, (size_t)p->g.d);
     a.A = p->A;
     a.zeta = p->zeta;
     a.W = p->W;
@@ -804,7 +834,9 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     // capture stream); inside a graph the chain runs as one work-group with
     // plain barriers, so the graph holds no grid-wide barrier
     auto iteration = [&](hipStream_t s, bool graph) -> rpr_status {
-        RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, s, p->shF.maxt));
+        const TiledWork<T> fw = tiled_work<T>(p->fwork, (size_t)N * d);
+        RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, s, p->shF.maxt,
+                                    p->fwork ? &fw : nullptr));
         RPR_TRY(phase_model<T>(p, a.inv_s, s));
         if (graph)
             RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->gchain), 1, g, p->shG, p->M, s));
@@ -903,6 +935,9 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
     for (rpr_plan *q : p->sub)
         if (q->prec != p->prec || q->corr != p->corr)
             return bail(fail(RPR_ERR_INVALID_ARG, "all instances of a batch need the same precision and correction"));
+    for (rpr_plan *q : p->sub)
+        if (q->shF.maxt == TILED_THREADS || q->shG.maxt == TILED_THREADS)
+            return bail(fail(RPR_ERR_UNSUPPORTED, "batch instances must fit one work-group each"));
     // the kernel shape of the largest instance serves every instance
     int big = 0;
     for (int b = 1; b < n_inst; ++b)
@@ -1113,14 +1148,38 @@ extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propa
     if (a < b + bytes && b < a + bytes) return fail(RPR_ERR_INVALID_ARG, "in and out must not overlap");
     const int esz = precision == RPR_FP64 ? 8 : 4;
     if (P->threads) RPR_TRY(check_threads(g, esz, P->threads));
+    // automatic: on chip when the state fits one work-group, else tiled
+    OnchipShape probe;
+    const bool fits = onchip_shape(g, esz, &probe, 1024);
+    if (!P->threads && !fits) RPR_TRY(check_threads(g, esz, TILED_THREADS));
     RPR_TRY(check_device());
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int mt = P->threads ? P->threads : tuned_prop_threads(g, esz, P->method);
-    if (precision == RPR_FP64)
-        return launch_propagate<double>(g, P->method, P->steps, dt, n_states, static_cast<const double *>(in),
-                                        static_cast<double *>(out), nullptr, st, mt);
-    return launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
-                                   static_cast<float *>(out), nullptr, st, mt);
+    const int mt = P->threads ? P->threads : (fits ? tuned_prop_threads(g, esz, P->method) : TILED_THREADS);
+    if (mt != TILED_THREADS) {
+        if (precision == RPR_FP64)
+            return launch_propagate<double>(g, P->method, P->steps, dt, n_states, static_cast<const double *>(in),
+                                            static_cast<double *>(out), nullptr, st, mt);
+        return launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
+                                       static_cast<float *>(out), nullptr, st, mt);
+    }
+    // tiled: five work arrays of n_states x d values, released on the stream
+    const size_t nd = (size_t)n_states * d;
+    void *ws = nullptr;
+    RPR_HIP(hipMallocAsync(&ws, 5 * nd * esz, st));
+    rpr_status rc;
+    if (precision == RPR_FP64) {
+        double *b = static_cast<double *>(ws);
+        const TiledWork<double> w{b, b + nd, b + 2 * nd, b + 3 * nd, nullptr};
+        rc = launch_propagate<double>(g, P->method, P->steps, dt, n_states, static_cast<const double *>(in),
+                                      static_cast<double *>(out), nullptr, st, mt, &w);
+    } else {
+        float *b = static_cast<float *>(ws);
+        const TiledWork<float> w{b, b + nd, b + 2 * nd, b + 3 * nd, b + 4 * nd};
+        rc = launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
+                                     static_cast<float *>(out), nullptr, st, mt, &w);
+    }
+    RPR_HIP(hipFreeAsync(ws, st));
+    return rc;
 }
 
 extern "C" rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int32_t activation, double s,

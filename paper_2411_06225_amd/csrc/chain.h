@@ -26,6 +26,7 @@ struct ChainArgs {
     T *gtmp;                   // d: coarse value of the current slot
     double *phi;               // M: hidden layer of the current slot
     double *hpart;             // grid x M: per-work-group partial sums of A x / s
+    TiledWork<T> gw;           // work arrays of the tiled coarse solver (d values each)
     const double *A, *zeta, *W;
     const uint16_t *Ab;        // bf16 copy of A (reduced-precision plans), else null
     const double *At;          // d x M: A^T (plain plans)

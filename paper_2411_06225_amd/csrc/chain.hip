@@ -21,6 +21,7 @@
 
 #include "chain.h"
 #include "slotprop.h"
+#include "tiledprop.h"
 
 namespace cg = cooperative_groups;
 
@@ -159,10 +160,29 @@ __device__ __forceinline__ void hidden_finish(const ChainArgs<T> &a, const int h
     }
 }
 
+// Coarse propagation src -> dst (and dst2) of a state too large for one
+// work-group, by the whole grid: the tiles of each RK stage are spread over
+// the work-groups, a grid barrier separates the stages.
+template <int KIND, typename T, typename Sync>
+__device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src, T *dst, T *dst2, const int wg,
+                                             const int nwg, Sync sync, T *lds)
+{
+    const int nt = tiles_of(a.g);
+    for (long long s = 0; s < a.G_steps; ++s) {
+        for (int stage = a.G_method == RPR_RK4 ? 1 : 0; stage <= (a.G_method == RPR_RK4 ? 4 : 0); ++stage) {
+            const StageIO<T> io = stage_io<T>(a.G_method, stage, s, a.G_steps, src, dst, dst2, a.gw);
+            for (int tile = wg; tile < nt; tile += nwg) stage_tile<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
+            sync();
+        }
+    }
+}
+
 // One sweep of one instance.  wg / nwg: this work-group and the number of// One sweep of one instance.  wg / nwg: this work-group and the number of
 // work-groups sharing the instance; sync(): a barrier over those work-groups
 // (a grid barrier, or a work-group barrier when nwg == 1).
-template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, typename Sync>
+// TILED: the slot state does not fit one work-group; the coarse solver is
+// then run by the whole grid (tiled_coarse) instead of work-group 0.
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, bool TILED, typename Sync>
 __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, const int nwg, Sync sync,
                                            unsigned char *lds_raw)
 {
@@ -174,13 +194,20 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     Ctrl *ctrl = a.ctrl;
 
     if (a.mode == CHAIN_SWEEP) {
-        // k = 0 (single work-group): the state stays on chip from slot to slot
-        if (wg != 0) return;
-        for (int i = 1; i <= a.N; ++i) {
-            slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG,
-                                                             a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d,
-                                                             lds, a.Gc + (size_t)i * d);
-            __syncthreads();
+        if constexpr (TILED) {
+            // k = 0 by the whole grid
+            for (int i = 1; i <= a.N; ++i)
+                tiled_coarse<KIND, T>(a, a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d, a.Gc + (size_t)i * d, wg,
+                                      nwg, sync, lds);
+        } else {
+            // k = 0 (single work-group): the state stays on chip from slot to slot
+            if (wg != 0) return;
+            for (int i = 1; i <= a.N; ++i) {
+                slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG,
+                                                                 a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d,
+                                                                 lds, a.Gc + (size_t)i * d);
+                __syncthreads();
+            }
         }
         return;
     }
@@ -205,11 +232,16 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     for (int i = L + 2; i <= N; ++i) {
         const T *x = a.U + (size_t)(i - 1) * d;
         // ---- phase 1: coarse solve (work-group 0) and hidden layer (the others)
-        if (wg == 0) {
-            slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG, x, a.gtmp, lds);
-            __syncthreads();
+        if constexpr (TILED) {
+            tiled_coarse<KIND, T>(a, x, a.gtmp, (T *)nullptr, wg, nwg, sync, lds);
+            if (net) hidden_finish(a, wg, nwg, nwg);
+        } else {
+            if (wg == 0) {
+                slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG, x, a.gtmp, lds);
+                __syncthreads();
+            }
+            if (net && (wg > 0 || nwg == 1)) hidden_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg);
         }
-        if (net && (wg > 0 || nwg == 1)) hidden_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg);
         sync();
 
         // ---- phase 2: readout, update and change norm on this block of columns
@@ -328,7 +360,7 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cg::grid_group grid = cg::this_grid();
-    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
 }
 
 // Independent instances: work-group b runs the whole sweep of instance b.
@@ -337,7 +369,24 @@ __global__ __launch_bounds__(MAXT) void k_chain_multi(const ChainArgs<T> *__rest
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ChainArgs<T> a = args[blockIdx.x];
-    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+}
+
+// ---------------------------------------------------------- tiled form --
+template <int KIND, typename T>
+__global__ __launch_bounds__(TT_THREADS) void k_chain_tiled(ChainArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cg::grid_group grid = cg::this_grid();
+    chain_body<KIND, T, 1, false, false, 0, 0, true>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
+}
+
+template <int KIND, typename T>
+__global__ __launch_bounds__(TT_THREADS) void k_chain_multi_tiled(const ChainArgs<T> *__restrict__ args)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const ChainArgs<T> a = args[blockIdx.x];
+    chain_body<KIND, T, 1, false, false, 0, 0, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
 }
 
 template <int KIND, typename T>
@@ -368,6 +417,22 @@ template <int KIND, typename T>
 rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax,
                                    const OnchipShape &sh, int M, hipStream_t st)
 {
+    if (sh.maxt == TILED_THREADS) {
+        if constexpr (KIND == RPR_BURGERS1D) {
+            return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
+        } else {
+            auto kern = k_chain_multi_tiled<KIND, T>;
+            static bool attr_set = false;
+            if (!attr_set) {
+                RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)kMaxLds));
+                attr_set = true;
+            }
+            hipLaunchKernelGGL(kern, dim3(n_inst), dim3(TT_THREADS), chain_lds(sh, M), st, args_dev);
+            RPR_HIP(hipGetLastError());
+            return RPR_OK;
+        }
+    }
     ChainMultiLauncher<KIND, T> L{args_dev, n_inst, sh, M, st};
     return visit_shape_kind<KIND, T>(gmax, sh, L);
 }
@@ -412,6 +477,31 @@ template <int KIND, typename T>
 rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,
                              int *max_wg)
 {
+    if (sh.maxt == TILED_THREADS) {
+        if constexpr (KIND == RPR_BURGERS1D) {
+            return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
+        } else {
+            auto kern = k_chain_tiled<KIND, T>;
+            static bool attr_set = false;
+            if (!attr_set) {
+                RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)kMaxLds));
+                attr_set = true;
+            }
+            const size_t lds = chain_lds(sh, a.M);
+            if (max_wg) {
+                int per_cu = 0, dev = 0, cus = 0;
+                RPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, TT_THREADS, lds));
+                RPR_HIP(hipGetDevice(&dev));
+                RPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                *max_wg = per_cu * cus;
+                return RPR_OK;
+            }
+            void *args[] = {(void *)&a};
+            RPR_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(nwg), dim3(TT_THREADS), args, lds, st));
+            return RPR_OK;
+        }
+    }
     ChainLauncher<KIND, T> L{a, sh, nwg, st, max_wg};
     return visit_shape_kind<KIND, T>(a.g, sh, L);
 }

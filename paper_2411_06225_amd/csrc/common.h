@@ -210,8 +210,13 @@ struct OnchipShape {
 // max_threads (512 or 1024) bounds the work-group: with 512 threads each
 // strip is twice as long and a thread may hold 256 VGPRs instead of 128.
 bool onchip_shape(const Geom &g, size_t elem, OnchipShape *sh, int max_threads = 1024);
-// RPR_OK when a kernel instance with work-groups of `threads` (512 or 1024)
-// serves grid g at element size elem, else RPR_ERR_UNSUPPORTED.
+// Launch shape of the tiled propagator (block TT_THREADS, maxt TILED_THREADS,
+// LDS of one haloed tile).
+OnchipShape tiled_shape(const Geom &g, size_t elem);
+
+// RPR_OK when a kernel instance with work-groups of `threads` (512 or 1024
+// on chip, TILED_THREADS tiled) serves grid g at element size elem, else
+// RPR_ERR_UNSUPPORTED.
 rpr_status check_threads(const Geom &g, size_t elem, int threads);
 
 // Per right-hand side instance (propagate.hip, one object per kind and precision).
@@ -219,12 +224,31 @@ template <int KIND, typename T>
 rpr_status launch_propagate_kind(const Geom &g, const OnchipShape &sh, int method, int64_t steps, double dt,
                                  int n, const T *in, T *out, const int *ctrl, hipStream_t st);
 
-// Launch of the on-chip propagator: out[b] = P(in[b]) for b in [0, n), where
-// work-group b skips its state when ctrl != nullptr and b < ctrl[0] (slot
-// b + 1 is already final) or ctrl[2] != 0 (run finished).
+// Work arrays of the tiled propagator for n slot states (n x d values each,
+// slot b at b d): the work state u, the RK4 accumulator, two stage inputs and
+// the FP32 compensation (acc and yb unused by forward Euler, cmp by FP64).
+template <typename T>
+struct TiledWork {
+    T *u, *acc, *ya, *yb, *cmp;
+};
+
+// Work-group size that selects the tiled propagator (states in memory).
+constexpr int TILED_THREADS = 256;
+
+// Tiled propagation of n states, one launch per RK stage (2D grids).
+template <int KIND, typename T>
+rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
+                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st);
+
+// Launch of the propagator: out[b] = P(in[b]) for b in [0, n), where the
+// work of state b is skipped when ctrl != nullptr and b < ctrl[0] (slot b + 1
+// is already final) or ctrl[2] != 0 (run finished).  max_threads 512 / 1024
+// selects the on-chip kernel with that work-group size, TILED_THREADS the
+// tiled one, which needs the work arrays tw.
 template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in,
-                            T *out, const int *ctrl, hipStream_t st, int max_threads = 1024);
+                            T *out, const int *ctrl, hipStream_t st, int max_threads = 1024,
+                            const TiledWork<T> *tw = nullptr);
 
 // One instance of a batch, as the persistent fine-solve kernel sees it.
 template <typename T>

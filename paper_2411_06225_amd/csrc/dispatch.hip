@@ -2,6 +2,7 @@
 // right-hand-side kind to the per-kind kernel objects.
 #include "chain.h"
 #include "slotprop.h"
+#include "tiledprop.h"
 
 namespace rpr {
 
@@ -57,8 +58,20 @@ rpr_status has_instance_t(const Geom &g, const OnchipShape &sh)
 }
 }  // namespace
 
+OnchipShape tiled_shape(const Geom &g, size_t elem)
+{
+    OnchipShape sh{};
+    sh.block = TT_THREADS;
+    sh.maxt = TILED_THREADS;
+    sh.lds = tiled_lds(g, elem);
+    return sh;
+}
+
 rpr_status check_threads(const Geom &g, size_t elem, int threads)
 {
+    if (threads == TILED_THREADS)
+        return g.kind == RPR_BURGERS1D ? fail(RPR_ERR_UNSUPPORTED, "the tiled propagator serves 2D grids only")
+                                       : RPR_OK;
     OnchipShape sh;
     if (!onchip_shape(g, elem, &sh, threads))
         return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group's LDS in this build");
@@ -70,9 +83,18 @@ rpr_status check_threads(const Geom &g, size_t elem, int threads)
 
 template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
-                            const int *ctrl, hipStream_t st, int max_threads)
+                            const int *ctrl, hipStream_t st, int max_threads, const TiledWork<T> *tw)
 {
     if (n <= 0) return RPR_OK;
+    if (max_threads == TILED_THREADS) {
+        if (!tw) return fail(RPR_ERR_INVALID_ARG, "propagate: the tiled form needs work arrays");
+        switch (g.kind) {
+        case RPR_DIFFREACT2D: return launch_prop_tiled_kind<RPR_DIFFREACT2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_BRUSS2D: return launch_prop_tiled_kind<RPR_BRUSS2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_SWE2D: return launch_prop_tiled_kind<RPR_SWE2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        default: return fail(RPR_ERR_UNSUPPORTED, "propagate: the tiled form serves 2D grids only");
+        }
+    }
     OnchipShape sh;
     if (!onchip_shape(g, sizeof(T), &sh, max_threads))
         return fail(RPR_ERR_UNSUPPORTED, "propagate: the state does not fit one work-group's LDS");
@@ -85,9 +107,9 @@ rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt,
     }
 }
 template rpr_status launch_propagate<double>(const Geom &, int, int64_t, double, int, const double *, double *,
-                                             const int *, hipStream_t, int);
+                                             const int *, hipStream_t, int, const TiledWork<double> *);
 template rpr_status launch_propagate<float>(const Geom &, int, int64_t, double, int, const float *, float *,
-                                            const int *, hipStream_t, int);
+                                            const int *, hipStream_t, int, const TiledWork<float> *);
 
 size_t chain_lds(const OnchipShape &sh, int M)
 {

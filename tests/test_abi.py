@@ -61,19 +61,22 @@ def test_propagate_rejects_bad_propagator_and_overlap():
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(method=2)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(steps=0)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 5, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
-    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(threads=256)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(threads=128)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert "threads" in rpr.last_error()
     # in and out overlapping
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 0, 1e-3, 2, 4096, 4096 + 512, None) == -1
     assert "overlap" in rpr.last_error()
 
 
-@pytest.mark.parametrize("kind,nx,ny,prec", [(1, 13, 9, 0), (0, 128, 1, 0), (1, 32, 32, 1), (2, 128, 128, 0)])
-def test_propagate_rejects_work_group_size_without_kernel(kind, nx, ny, prec):
-    # 512-thread kernels exist for the 64 x 64 grids only; decided on the host
+@pytest.mark.parametrize("kind,nx,ny,prec,threads", [(1, 13, 9, 0, 512), (0, 128, 1, 0, 512), (1, 32, 32, 1, 512),
+                                                     (2, 128, 128, 0, 512), (0, 128, 1, 0, 256), (0, 4096, 1, 1, 256)])
+def test_propagate_rejects_work_group_size_without_kernel(kind, nx, ny, prec, threads):
+    # 512-thread kernels exist for the 64 x 64 grids only, the tiled form
+    # (256) for 2D grids only; decided on the host
     h = rpr.make_rhs(kind, nx, ny)
     d = rpr.nspecies(kind) * nx * ny
-    st = rpr.lib().rpr_propagate(C.byref(h), d, C.byref(_prop(threads=512)), prec, 1e-3, 1, 1 << 20, 1 << 30, None)
+    st = rpr.lib().rpr_propagate(C.byref(h), d, C.byref(_prop(threads=threads)), prec, 1e-3, 1, 1 << 20, 1 << 30,
+                                 None)
     assert st == rpr.RPR_ERR_UNSUPPORTED
 
 

@@ -127,6 +127,46 @@ def test_propagate_every_work_group_size(orc, case, threads, prec):
         assert err <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
 
 
+TILED_CASES = [c for c in PROP_CASES if c[1] != rpr.RPR_BURGERS1D] + [
+    ("swe_96x80", rpr.RPR_SWE2D, 96, 80, (0, 1, 0, 1), (9.81,), 30, 2e-4, 4),
+    ("diffreact_130x70", rpr.RPR_DIFFREACT2D, 130, 70, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 20, 2e-4, 4),
+    ("bruss_80x33_rk1", rpr.RPR_BRUSS2D, 80, 33, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 30, 1e-4, 1),
+]
+
+
+@pytest.mark.parametrize("case", TILED_CASES, ids=[c[0] for c in TILED_CASES])
+@pytest.mark.parametrize("prec", [rpr.RPR_FP64, rpr.RPR_MIXED], ids=["fp64", "fp32"])
+def test_tiled_propagate_matches_oracle(orc, case, prec):
+    """The tiled form (states in memory, one pass over 64 x 16-cell tiles
+    per RK stage) on grids with full and ragged tiles, walls and periodic
+    boundaries, several states per launch."""
+    name, kind, nx, ny, dom, params, steps, dt, method = case
+    rng = np.random.default_rng(abs(hash(name)) % 2 ** 32 + 1)
+    d = rpr.nspecies(kind) * nx * ny
+    X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(3)])
+    pb = orc.problem(kind, nx, ny, dom, params)
+    ref = orc.propagate_many(pb, method, steps, dt, X)
+    dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
+    xin, xout = dev(X, dtype), torch.empty((3, d), dtype=dtype, device="cuda")
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, dom, params), d, method, steps, prec, dt, 3, xin, xout, threads=256)
+    err = rel_err(host(xout), ref)
+    print(name, "tiled", "fp64" if prec == rpr.RPR_FP64 else "fp32", "rel err %.2e" % err)
+    assert np.all(np.isfinite(host(xout)))
+    assert err <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
+
+
+def test_large_state_takes_the_tiled_form_automatically(orc):
+    # 128 x 128 Brusselator in FP64 (256 KiB) does not fit one work-group
+    kind, nx, ny, params = rpr.RPR_BRUSS2D, 128, 128, (1.0, 3.0, 0.02, 0.01)
+    rng = np.random.default_rng(8)
+    X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(2)])
+    ref = orc.propagate_many(orc.problem(kind, nx, ny, (-1, 1, -1, 1), params), 4, 10, 1e-4, X)
+    xout = torch.empty((2, X.shape[1]), dtype=torch.float64, device="cuda")
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, params=params), X.shape[1], 4, 10, rpr.RPR_FP64, 1e-4, 2, dev(X),
+                      xout)
+    assert rel_err(host(xout), ref) <= 1e-12
+
+
 def test_propagate_many_states_is_batched_identically(orc):
     # every state of a batch goes through the same kernel: equal inputs give bitwise equal outputs
     kind, nx, ny = rpr.RPR_DIFFREACT2D, 64, 64

@@ -206,6 +206,41 @@ def test_graph_respects_iteration_cap(orc):
     assert np.abs(Ug - Uo).max() / np.abs(Uo).max() <= w.N * 1e-12
 
 
+def tiled(w, graph=0):
+    """The same workload with the tiled propagators forced (threads = 256)."""
+    return w.replace(F=(w.F[0], w.F[1], 256), G=(w.G[0], w.G[1], 256))
+
+
+TILED_SOLVES = [("diffreact_32x32", DR_SMALL, 0), ("swe_16x16", SWE_SMALL, 0),
+                ("diffreact_24x20_parareal", DR_RAGGED, 1), ("bruss_32x32", BRUSS_SMALL, 0)]
+
+
+@pytest.mark.parametrize("name,w,corr", TILED_SOLVES, ids=[c[0] for c in TILED_SOLVES])
+def test_tiled_plan_matches_oracle(orc, name, w, corr):
+    """Plans on the tiled form: fine solves one launch per RK stage over all
+    slots' tiles, the coarse solver spread over the chain's grid."""
+    Ug, ig = gpu_solve(tiled(w), corr=corr)
+    Uo, io = orc_solve(orc, w, corr=corr)
+    assert_same_run(Ug, ig, Uo, io, w.N)
+
+
+def test_tiled_plan_in_a_captured_graph(orc):
+    # graph mode runs the tiled chain on one work-group
+    w = SWE_SMALL
+    Ug, ig = gpu_solve(tiled(w), poll_every=3, graph=1)
+    Uo, io = orc_solve(orc, w)
+    assert_same_run(Ug, ig, Uo, io, w.N)
+
+
+def test_state_too_large_for_one_work_group_is_solved_tiled(orc):
+    # 128 x 128 Brusselator in FP64: 256 KiB per state, more than one
+    # work-group's LDS, so the plan takes the tiled form by itself
+    w = W.small(W.BRUSS_128, N=4, tN=0.4, F=(4, 100), G=(1, 50), M=30, precision="fp64")
+    Ug, ig = gpu_solve(w)
+    Uo, io = orc_solve(orc, w)
+    assert_same_run(Ug, ig, Uo, io, w.N)
+
+
 def test_repeated_execute_is_bitwise_reproducible():
     w = DR_RAGGED
     a, _ = gpu_solve(w)
