@@ -18,7 +18,14 @@ timed live with HIP events on its launch stream), the same solve in mixed
 precision (FP32 states) with its accuracy, and the CPU oracle timed on the
 host cores on the same workload.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline] [--no-mixed]
+                    [--extra] [--copy-calibration]
+
+--extra adds one FP64 and one mixed-precision solve of the other workloads
+(Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems;
+shallow water 192 x 192), which takes minutes.  --copy-calibration runs a
+device copy of 256 MiB, the reference a hardware-counter run uses to scale
+its byte counters.
 """
 from __future__ import annotations
 
@@ -49,6 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
 
@@ -168,21 +177,102 @@ def main():
         mplan.close()
     plan.close()
 
+    if args.copy_calibration:
+        # a plain copy of known size: a counter run scales FETCH_SIZE / WRITE_SIZE by it
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 8
+
+    if args.extra:
+        out["extra"] = extra_workloads(torch, rpr, W, dev)
+
     if not args.no_cpu_baseline:
+        # bounded sample: the fine solves of 4 x threads slots (the part of a
+        # solve that dominates it), by the oracle
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
+        n_sample = 4 * threads
         pb = oracle.problem(w.kind, w.nx, w.ny, w.domain, w.params)
-        net = oracle.Net(A, zeta, w.act, w.lam, 0.0)
+        X = np.tile(u0h, (n_sample, 1))
         t0 = time.perf_counter()
-        _, oi = oracle.parareal(pb, u0h, N=w.N, t0=w.t0, tN=w.tN, F=w.F, G=w.G, eps=w.eps, net=net, nthreads=threads)
+        oracle.propagate_many(pb, w.F[0], w.F[1], T / w.F[1], X, nthreads=threads)
         csec = time.perf_counter() - t0
-        o_active = [w.N - int(oi["L_hist"][k - 1]) for k in range(1, oi["K"] + 1)]
-        out["cpu_baseline"] = {"value": sum(o_active) * w.F[1] / csec, "unit": "fine state-steps/s",
+        out["cpu_baseline"] = {"value": n_sample * w.F[1] / csec, "unit": "fine state-steps/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": f"the full solve of the same workload by the FP64 C oracle "
-                                         f"(K={oi['K']}, {sum(o_active)} fine slot solves), fine solves on "
-                                         f"{threads} threads, {csec:.1f} s"}
+                               "sample": f"{n_sample} fine slot solves (RK4 x {w.F[1]} on d = {w.d}) of the same "
+                                         f"workload by the FP64 C oracle on {threads} threads, {csec:.1f} s; the "
+                                         f"fine solves are the bulk of an oracle solve, so the rate bounds its "
+                                         f"whole-solve rate from above"}
     print(json.dumps(out))
+
+
+def extra_workloads(torch, rpr, W, dev):
+    """One FP64 and one mixed-precision solve of each of the other workloads:
+    time to tolerance, fine state-steps per second and the accuracy of the
+    mixed solve against the FP64 one (per slot max |U_mixed - U_fp64|,
+    averaged over slots).  Progress goes to stderr."""
+    res = {}
+
+    def fine_rate(plan, w, sec):
+        Lh, _ = plan.history()
+        K = plan.info()["K"]
+        return sum(w.N - int(Lh[k - 1]) for k in range(1, K + 1)) * w.F[1] / sec
+
+    def single(w):
+        h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+        A, z = W.random_weights(w)
+        u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
+        r = {"d": w.d, "N": w.N}
+        Us = {}
+        for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
+            plan = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
+                            A=A, zeta=z, precision=prec, autotune=1)
+            U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.execute(u0, U)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            Us[name] = U
+            r[name] = {"s": sec, "K": plan.info()["K"], "fine_state_steps_per_s": fine_rate(plan, w, sec)}
+            plan.close()
+            print(f"extra {w.name} {name}: {sec:.3f} s, K = {r[name]['K']}", file=sys.stderr, flush=True)
+        r["mixed"]["E_vs_fp64"] = float((Us["mixed"][1:] - Us["fp64"][1:]).abs().amax(dim=1).mean())
+        return r
+
+    res["burgers_d128"] = single(W.BURGERS_D128)
+    res["bruss_128x128"] = single(W.BRUSS_128)
+    res["swe_192x192"] = single(W.SWE_192)
+
+    bw = W.burgers_batch()
+    problems = []
+    for w in bw.instances:
+        A, z = W.random_weights(w)
+        problems.append(dict(h=rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params), d=w.d, t0=w.t0, tN=w.tN,
+                             N=w.N, F=w.F, G=w.G, M=w.M, activation=w.act, lam=w.lam, A=A, zeta=z))
+    u0s = [torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev) for w in bw.instances]
+    r = {"instances": len(problems), "slots": sum(w.N for w in bw.instances)}
+    for name, prec, graph in (("fp64", rpr.RPR_FP64, 0), ("mixed_graph", rpr.RPR_MIXED, 1)):
+        plan = rpr.BatchPlan(problems, tol=[w.eps for w in bw.instances], precision=prec, graph=graph)
+        outs = [torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev) for w in bw.instances]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status = plan.execute(u0s, outs)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        steps = 0
+        for b, w in enumerate(bw.instances):
+            inst = plan.instance(b)
+            Lh, _ = inst.history()
+            steps += sum(w.N - int(Lh[k - 1]) for k in range(1, inst.info()["K"] + 1)) * w.F[1]
+        r[name] = {"s": sec, "status": status, "fine_state_steps_per_s": steps / sec}
+        plan.close()
+        print(f"extra burgers_batch64 {name}: {sec:.3f} s", file=sys.stderr, flush=True)
+    res["burgers_batch64"] = r
+    return res
 
 
 if __name__ == "__main__":

@@ -121,10 +121,12 @@ typedef enum {
 } rpr_correction;
 
 typedef enum {
-    RPR_FEAT_AUTO = 0,         /* FP64 for RPR_FP64 plans, bfloat16 for RPR_MIXED plans */
-    RPR_FEAT_FP64 = 1,         /* hidden layer in double precision */
-    RPR_FEAT_BF16 = 2          /* bf16 inputs and weights, single-precision sums on the
-                                  matrix cores, bf16 result (see rpr_randnet_features_bf16) */
+    RPR_FEAT_AUTO = 0,         /* FP64 for RPR_FP64 plans, split bfloat16 for RPR_MIXED
+                                  plans (training features; the predictor-corrector
+                                  sweep evaluates the hidden layer in double) */
+    RPR_FEAT_FP64 = 1,         /* training features in double precision */
+    RPR_FEAT_BF16 = 2          /* split-bfloat16 products, single-precision sums on the
+                                  matrix cores (see rpr_randnet_features_bf16) */
 } rpr_feature_precision;
 
 typedef struct {
@@ -256,10 +258,12 @@ rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int32_t activat
                                 void *stream);
 
 /*
- * Reduced-precision features, the recipe of RPR_MIXED plans: x/s and A rounded
- * to bfloat16 (round to nearest even), products summed in single precision on
- * the matrix cores, zeta added and sigma applied in single precision, result
- * rounded to bfloat16 and returned as doubles.
+ * Split-bfloat16 features, the training features of RPR_MIXED plans: x/s and
+ * A are each split into three bfloat16 pieces (each the bfloat16 rounding of
+ * what the previous pieces leave), the six products of the pieces down to
+ * 2^-16 relative are summed in single precision on the matrix cores, the
+ * partial sums, zeta and sigma are taken in double.  The pre-activation is
+ * within 2^-16 sum_j |A_mj x_j / s| of the exact one.
  *   A (M x d, doubles), zeta (M, doubles), X (n x d, floats), Phi (n x M,
  *   doubles): device pointers.  Allocates and frees its own workspace.
  */

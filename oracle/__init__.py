@@ -86,10 +86,6 @@ def lib():
                                       C.c_int32, dp, dp]
         L.orc_features.restype = None
         L.orc_features.argtypes = [C.POINTER(RandNet), C.c_int32, C.c_int32, dp, dp]
-        L.orc_bf16_rne.restype = C.c_float
-        L.orc_bf16_rne.argtypes = [C.c_float]
-        L.orc_features_bf16.restype = None
-        L.orc_features_bf16.argtypes = [C.POINTER(RandNet), C.c_int32, C.c_int32, C.POINTER(C.c_float), dp]
         L.orc_ridge_fit.restype = C.c_int32
         L.orc_ridge_fit.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, C.c_double, dp]
         L.orc_ridge_fit_dual.restype = C.c_int32
@@ -177,19 +173,6 @@ def features(net: Net, X) -> np.ndarray:
     X = np.atleast_2d(_f64(X))
     out = np.empty((X.shape[0], net.A.shape[0]))
     lib().orc_features(C.byref(net.st), X.shape[1], X.shape[0], _dp(X), _dp(out))
-    return out
-
-
-def bf16_rne(f: float) -> float:
-    return float(lib().orc_bf16_rne(float(f)))
-
-
-def features_bf16(net: Net, X) -> np.ndarray:
-    """Reduced-precision hidden layer (bf16 inputs/weights/outputs, float sums)."""
-    X = np.atleast_2d(np.ascontiguousarray(X, dtype=np.float32))
-    out = np.empty((X.shape[0], net.A.shape[0]))
-    lib().orc_features_bf16(C.byref(net.st), X.shape[1], X.shape[0], X.ctypes.data_as(C.POINTER(C.c_float)),
-                            _dp(out))
     return out
 
 

@@ -81,13 +81,6 @@ typedef struct {
 /* Phi (n x M) = sigma(A (X_r / s) + zeta) for each row X_r of X (n x d). */
 void orc_features(const orc_randnet *net, int32_t d, int32_t n, const double *X, double *Phi);
 
-/* bfloat16 round-to-nearest-even of a float (returned as a float). */
-float orc_bf16_rne(float f);
-
-/* Reduced-precision features: bf16 inputs and weights, float accumulation in
- * index order, float activation, bf16 result.  X: n x d floats. */
-void orc_features_bf16(const orc_randnet *net, int32_t d, int32_t n, const float *X, double *Phi);
-
 /* Ridge readout from explicit rows: W (M x d) = (Phi^T Phi + lambda I)^{-1} Phi^T Y,
  * by Cholesky.  Returns 0, or -6 if the matrix is not numerically positive definite. */
 int32_t orc_ridge_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y,

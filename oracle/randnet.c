@@ -25,43 +25,6 @@ void orc_features(const orc_randnet *net, int32_t d, int32_t n, const double *X,
         }
 }
 
-/* Round a float to bfloat16 (the upper 16 bits of the IEEE single) with
- * round-to-nearest-even, returned as a float.  NaN stays NaN. */
-float orc_bf16_rne(float f)
-{
-    uint32_t u;
-    memcpy(&u, &f, 4);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return f;  /* NaN */
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    u &= 0xFFFF0000u;
-    float r;
-    memcpy(&r, &u, 4);
-    return r;
-}
-
-/*
- * Reduced-precision hidden layer: the same map as orc_features with the
- * input x/s and the weights A rounded to bfloat16, the sum accumulated in
- * single precision in index order, zeta added and sigma applied in single
- * precision, and the result rounded to bfloat16.  X holds the single
- * precision states of the reduced-precision path.
- */
-void orc_features_bf16(const orc_randnet *net, int32_t d, int32_t n, const float *X, double *Phi)
-{
-    for (int r = 0; r < n; ++r)
-        for (int m = 0; m < net->M; ++m) {
-            float z = 0.0f;
-            for (int j = 0; j < d; ++j) {
-                const float a = orc_bf16_rne((float)net->A[(size_t)m * d + j]);
-                const float x = orc_bf16_rne((float)((double)X[(size_t)r * d + j] / net->scale));
-                z += a * x;
-            }
-            z += (float)net->zeta[m];
-            const float s = net->act == ORC_RELU ? (z > 0.0f ? z : 0.0f) : tanhf(z);
-            Phi[(size_t)r * net->M + m] = (double)orc_bf16_rne(s);
-        }
-}
-
 /* Textbook Cholesky-Crout: S = L L^T, column by column. */
 int32_t orc_cholesky(int32_t s, const double *S, double *L)
 {

@@ -195,8 +195,7 @@ struct rpr_plan {
            *u0max = nullptr;
     int *ok = nullptr, *nrows = nullptr, *L_hist = nullptr, *cfail = nullptr, *u0bad = nullptr;
     uint16_t *Ab = nullptr;   // bf16 copy of A (reduced precision)
-    double *At = nullptr;     // A^T, d x M (the chain's hidden layer, plain precision)
-    uint16_t *Abt = nullptr;  // bf16 A^T, d x M (reduced precision)
+    double *At = nullptr;     // A^T, d x M (the chain's hidden layer)
     float *fpart32 = nullptr; // split-K partials of the bf16 feature GEMM
     Ctrl *ctrl = nullptr;
     Ctrl *ctrl_host = nullptr;  // pinned
@@ -249,7 +248,7 @@ static void plan_free(rpr_plan *p)
         if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
                     p->Lt, p->Bm, p->W, p->phi, p->part, p->chg_hist, p->u0max, p->ok, p->nrows, p->L_hist,
-                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At, p->Abt};
+                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->ctrl_host) (void)hipHostFree(p->ctrl_host);
@@ -325,15 +324,12 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
             RPR_TRY(launch_uniform(seed, (uint64_t)M * d, M, p->zeta, nullptr));
         }
         // the chain's hidden layer reads the weights column by column (A^T)
+        RPR_TRY(dalloc(&p->At, (size_t)M * d));
+        RPR_TRY(launch_transpose<double>(p->A, p->At, M, d, nullptr));
         if (p->feat_bf16) {
-            RPR_TRY(dalloc(&p->Ab, (size_t)M * d));
-            RPR_TRY(dalloc(&p->Abt, (size_t)M * d));
+            RPR_TRY(dalloc(&p->Ab, 3 * (size_t)M * d));
             RPR_TRY(dalloc(&p->fpart32, (size_t)feat_bf16_splits(d) * N * M));
             RPR_TRY(launch_to_bf16(p->A, p->Ab, (size_t)M * d, nullptr));
-            RPR_TRY(launch_transpose<uint16_t>(p->Ab, p->Abt, M, d, nullptr));
-        } else {
-            RPR_TRY(dalloc(&p->At, (size_t)M * d));
-            RPR_TRY(launch_transpose<double>(p->A, p->At, M, d, nullptr));
         }
         RPR_HIP(hipDeviceSynchronize());
     }
@@ -497,9 +493,7 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
         a.A = p->A;
         a.zeta = p->zeta;
         a.W = p->W;
-        a.Ab = p->Ab;
         a.At = p->At;
-        a.Abt = p->Abt;
         a.part = p->part;
         a.ctrl = p->ctrl;
         float best = 1e30f;
@@ -701,9 +695,7 @@ static ChainArgs<T> chain_args(rpr_plan *p, double s)
     a.A = p->A;
     a.zeta = p->zeta;
     a.W = p->W;
-    a.Ab = p->Ab;
     a.At = p->At;
-    a.Abt = p->Abt;
     a.part = p->part;
     a.ctrl = p->ctrl;
     a.L_hist = p->L_hist;
@@ -1213,7 +1205,7 @@ extern "C" rpr_status rpr_randnet_features_bf16(int32_t M, int32_t d, int32_t n,
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint16_t *Ab = nullptr;
     float *part = nullptr;
-    RPR_HIP(hipMallocAsync((void **)&Ab, sizeof(uint16_t) * (size_t)M * d, st));
+    RPR_HIP(hipMallocAsync((void **)&Ab, 3 * sizeof(uint16_t) * (size_t)M * d, st));
     RPR_HIP(hipMallocAsync((void **)&part, sizeof(float) * feat_bf16_splits(d) * n * M, st));
     rpr_status rc = launch_to_bf16(A, Ab, (size_t)M * d, st);
     if (rc == RPR_OK) rc = launch_features_bf16<float>(n, M, d, activation, 1.0 / s, Ab, zeta, X, Phi, part, nullptr, st);

@@ -28,9 +28,7 @@ struct ChainArgs {
     double *hpart;             // grid x M: per-work-group partial sums of A x / s
     TiledWork<T> gw;           // work arrays of the tiled coarse solver (d values each)
     const double *A, *zeta, *W;
-    const uint16_t *Ab;        // bf16 copy of A (reduced-precision plans), else null
-    const double *At;          // d x M: A^T (plain plans)
-    const uint16_t *Abt;       // d x M: bf16 A^T (reduced-precision plans)
+    const double *At;          // d x M: A^T
     double *part;              // (N+1) x grid: per-work-group change maxima
     Ctrl *ctrl;
     int *L_hist;               // (N+1)

@@ -69,9 +69,9 @@ __device__ __forceinline__ double nan_max(double a, double b)
 // just written them) sums A[m][j] x_j / s over them for every neuron m
 // (hidden_partial), and after the grid barrier the owner of neuron m adds the
 // grid's partial sums in work-group order and applies sigma (hidden_finish).
-// No work-group reads another's columns of x.  Reduced precision: bf16
-// weights and inputs (products exact), sums in double, sigma in FP32, bf16
-// output.
+// No work-group reads another's columns of x.  Sums and sigma in double in
+// both precisions (the training features of reduced-precision plans come
+// from the split-bfloat16 GEMM, accurate to the same order as FP32 states).
 template <typename T>
 __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
                                                const int j1, const int wg, double *red)
@@ -87,8 +87,6 @@ __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *_
     if (wv < nw) {
         const int cpw = (j1 - j0 + nw - 1) / nw;
         const int c0 = j0 + wv * cpw, c1 = min(j1, c0 + cpw);
-        const bool bf = a.Ab != nullptr;
-        const float xsf = (float)a.inv_s;
         constexpr int MPL = 4, CB4 = 4;  // neurons per lane and pass, columns per load batch
         for (int mb = 0; mb < a.M; mb += WL * MPL) {
             double p[MPL];
@@ -99,8 +97,7 @@ __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *_
 #pragma unroll
                 for (int k = 0; k < CB4; ++k) {
                     const int j = cb + k;
-                    xv[k] = j < c1 ? (bf ? (double)from_bf16(to_bf16(float(x[j]) * xsf)) : double(x[j]) * a.inv_s)
-                                   : 0.0;
+                    xv[k] = j < c1 ? double(x[j]) * a.inv_s : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < MPL; ++u) {
@@ -108,9 +105,7 @@ __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *_
 #pragma unroll
                     for (int k = 0; k < CB4; ++k) {
                         const int j = cb + k;
-                        wv4[u][k] = (m < a.M && j < c1) ? (bf ? (double)from_bf16(a.Abt[(size_t)j * a.M + m])
-                                                                : a.At[(size_t)j * a.M + m])
-                                                         : 0.0;
+                        wv4[u][k] = (m < a.M && j < c1) ? a.At[(size_t)j * a.M + m] : 0.0;
                     }
                 }
 #pragma unroll
@@ -148,14 +143,8 @@ __device__ __forceinline__ void hidden_finish(const ChainArgs<T> &a, const int h
             if (lane + off < WL) z += o;
         }
         if (lane == 0) {
-            if (a.Ab != nullptr) {
-                const float zf = float(z) + (float)a.zeta[m];
-                const float sg = a.act == RPR_RELU ? (zf > 0.0f ? zf : 0.0f) : tanhf(zf);
-                a.phi[m] = (double)from_bf16(to_bf16(sg));
-            } else {
-                z += a.zeta[m];
-                a.phi[m] = a.act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
-            }
+            z += a.zeta[m];
+            a.phi[m] = a.act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
         }
     }
 }

@@ -16,16 +16,18 @@ template <typename TX>
 rpr_status launch_features(int n, int M, int d, int act, double inv_s, const double *A, const double *zeta,
                            const TX *X, double *Phi, double *part, const int *nrows_dev, hipStream_t st);
 
-// Reduced-precision features (bf16 inputs and weights Ab, FP32 accumulation
-// on the matrix cores, FP32 sigma, bf16 result stored as double).  part holds
-// feat_bf16_splits(d) x n x M floats.
+// Split-bfloat16 features: inputs and weights (Ab, three pieces of M x d,
+// from launch_to_bf16) split in three bfloat16 pieces, the six leading
+// products of the pieces accumulated in FP32 on the matrix cores, the K-split
+// partials and sigma in double.  part holds feat_bf16_splits(d) x n x M floats.
 int feat_bf16_splits(int d);
 template <typename TX>
 rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, const uint16_t *Ab,
                                 const double *zeta, const TX *X, double *Phi, float *part,
                                 const int *nrows_dev, hipStream_t st);
 
-// out = bf16(float(in)), round to nearest even.
+// The three bfloat16 pieces of in (round to nearest even each): out holds
+// 3 n values, piece p at out + p n.
 rpr_status launch_to_bf16(const double *in, uint16_t *out, size_t n, hipStream_t st);
 
 // G += Phi^T Phi and B += Phi^T Y over the rows r with ok[r] != 0 (ok may be null).

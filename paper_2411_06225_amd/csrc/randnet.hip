@@ -96,10 +96,23 @@ template rpr_status launch_features<float>(int, int, int, int, double, const dou
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+// Three-piece bfloat16 split of v: v ~ p0 + p1 + p2, each piece the
+// bfloat16 rounding of what the previous ones leave (24 significant bits in
+// all; |v - p0 - p1 - p2| <= 2^-27 |v|).
+__device__ __forceinline__ void split_bf16(double v, uint16_t &p0, uint16_t &p1, uint16_t &p2)
+{
+    p0 = to_bf16((float)v);
+    const double r1 = v - (double)from_bf16(p0);
+    p1 = to_bf16((float)r1);
+    const double r2 = r1 - (double)from_bf16(p1);
+    p2 = to_bf16((float)r2);
+}
+
+// out = the three pieces of in, piece p at out + p n.
 __global__ void k_to_bf16(const double *__restrict__ in, uint16_t *__restrict__ out, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = to_bf16((float)in[i]);
+    if (i < n) split_bf16(in[i], out[i], out[n + i], out[2 * n + i]);
 }
 
 rpr_status launch_to_bf16(const double *in, uint16_t *out, size_t n, hipStream_t st)
@@ -137,6 +150,11 @@ rpr_status launch_transpose(const E *in, E *out, int rows, int cols, hipStream_t
 template rpr_status launch_transpose<double>(const double *, double *, int, int, hipStream_t);
 template rpr_status launch_transpose<uint16_t>(const uint16_t *, uint16_t *, int, int, hipStream_t);
 
+// Split-bfloat16 feature GEMM Z = (X / s) A^T on MFMA: both operands are
+// split in three bfloat16 pieces (X on the fly, A beforehand) and the six
+// products of the pieces down to 2^-16 relative, x0 a0, x0 a1, x1 a0, x0 a2,
+// x2 a0, x1 a1, are accumulated in FP32 (bfloat16 products are exact in
+// FP32).  The dropped products are below 2^-24 |x a|.
 // Work-group tile: 64 rows of X x 64 neurons, 4 waves; wave w owns rows
 // 16w..16w+15 and all four 16-neuron tiles.  K advances 32 at a time through
 // LDS.  Operand layout of the 16x16x32 instruction: lane l holds A[l%16][8(l/16)..+7],
@@ -146,7 +164,7 @@ constexpr int BT = 64, BK = 32, BKP = 40;  // LDS row pitch 80 B keeps 16-byte a
 template <typename TX>
 __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, int kchunk,
                                                            const TX *__restrict__ X,
-                                                           const uint16_t *__restrict__ Ab, float xs,
+                                                           const uint16_t *__restrict__ Ab, double xs,
                                                            float *__restrict__ part,
                                                            const int *__restrict__ nrows_dev)
 {
@@ -154,7 +172,8 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
     const int r0 = blockIdx.x * BT, m0 = blockIdx.y * BT;
     if (r0 >= nr) return;
     const int k0 = blockIdx.z * kchunk, k1 = min(d, k0 + kchunk);
-    __shared__ __align__(16) uint16_t Xs[BT][BKP], As[BT][BKP];
+    const size_t md = (size_t)M * d;
+    __shared__ __align__(16) uint16_t Xs[3][BT][BKP], As[3][BT][BKP];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int lr = t >> 2, lk = (t & 3) * 8;  // loader: row, first k of 8
     f32x4_t acc[4];
@@ -163,27 +182,40 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
     for (int kb = k0; kb < k1; kb += BK) {
         {
             const int r = r0 + lr, m = m0 + lr;
-            uint16_t xv[8], av[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int k = kb + lk + e;
                 const bool kin = k < k1;
-                xv[e] = (r < nr && kin) ? to_bf16(float(X[(size_t)r * d + k]) * xs) : (uint16_t)0;
-                av[e] = (m < M && kin) ? Ab[(size_t)m * d + k] : (uint16_t)0;
-            }
+                uint16_t x0 = 0, x1 = 0, x2 = 0;
+                if (r < nr && kin) split_bf16(double(X[(size_t)r * d + k]) * xs, x0, x1, x2);
+                Xs[0][lr][lk + e] = x0;
+                Xs[1][lr][lk + e] = x1;
+                Xs[2][lr][lk + e] = x2;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                Xs[lr][lk + e] = xv[e];
-                As[lr][lk + e] = av[e];
+                for (int p = 0; p < 3; ++p)
+                    As[p][lr][lk + e] = (m < M && kin) ? Ab[p * md + (size_t)m * d + k] : (uint16_t)0;
             }
         }
         __syncthreads();
-        const uint4 a4 = *reinterpret_cast<const uint4 *>(&Xs[w * 16 + (lane & 15)][8 * (lane >> 4)]);
-        const bf16x8_t a = __builtin_bit_cast(bf16x8_t, a4);
+        bf16x8_t xa[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+            xa[p] = __builtin_bit_cast(bf16x8_t,
+                                       *reinterpret_cast<const uint4 *>(&Xs[p][w * 16 + (lane & 15)][8 * (lane >> 4)]));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint4 b4 = *reinterpret_cast<const uint4 *>(&As[j * 16 + (lane & 15)][8 * (lane >> 4)]);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8_t, b4), acc[j], 0, 0, 0);
+            bf16x8_t ab[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                ab[p] = __builtin_bit_cast(bf16x8_t,
+                                           *reinterpret_cast<const uint4 *>(&As[p][j * 16 + (lane & 15)][8 * (lane >> 4)]));
+            // smallest products first
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[1], acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[2], ab[0], acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[2], acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[0], acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[1], acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[0], acc[j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -196,6 +228,7 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
         }
 }
 
+// Phi = sigma(sum of the K-split partials + zeta), in double.
 __global__ void k_feat_bf16_finish(int n, int M, int nsplit, const float *__restrict__ part,
                                    const double *__restrict__ zeta, int act, double *__restrict__ Phi,
                                    const int *__restrict__ nrows_dev)
@@ -203,11 +236,10 @@ __global__ void k_feat_bf16_finish(int n, int M, int nsplit, const float *__rest
     const int nr = nrows_dev ? *nrows_dev : n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nr * M) return;
-    float z = 0.0f;
-    for (int s = 0; s < nsplit; ++s) z += part[(size_t)s * n * M + i];
-    z += (float)zeta[i % M];
-    const float sg = act == RPR_RELU ? (z > 0.0f ? z : 0.0f) : tanhf(z);
-    Phi[i] = (double)from_bf16(to_bf16(sg));
+    double z = 0.0;
+    for (int s = 0; s < nsplit; ++s) z += (double)part[(size_t)s * n * M + i];
+    z += zeta[i % M];
+    Phi[i] = act == RPR_RELU ? (z > 0.0 ? z : 0.0) : tanh(z);
 }
 
 int feat_bf16_splits(int d)
@@ -225,8 +257,8 @@ rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, cons
     const int ns = feat_bf16_splits(d);
     const int kchunk = ((d + ns - 1) / ns + BK - 1) / BK * BK;
     dim3 grid((n + BT - 1) / BT, (M + BT - 1) / BT, ns);
-    hipLaunchKernelGGL(k_feat_bf16_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, (float)inv_s,
-                       part, nrows_dev);
+    hipLaunchKernelGGL(k_feat_bf16_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, inv_s, part,
+                       nrows_dev);
     RPR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_feat_bf16_finish, dim3((n * M + 255) / 256), dim3(256), 0, st, n, M, ns, part, zeta,
                        act, Phi, nrows_dev);

@@ -263,36 +263,6 @@ def test_features_symmetries(orc):
     np.testing.assert_array_equal(orc.features(r4, 4 * X), orc.features(r, X))
 
 
-def test_bf16_rounding_reference_values(orc):
-    # bfloat16 keeps 8 significant bits: 1 + 2^-7 is representable, 1 + 2^-8 is
-    # the midpoint between 1 and 1 + 2^-7 and rounds to the even neighbour 1,
-    # 1 + 3 * 2^-8 rounds up to the even neighbour 1 + 2^-6.
-    assert orc.bf16_rne(1.0 + 2 ** -7) == 1.0 + 2 ** -7
-    assert orc.bf16_rne(1.0 + 2 ** -8) == 1.0
-    assert orc.bf16_rne(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6
-    assert orc.bf16_rne(1.0 + 2 ** -8 + 2 ** -20) == 1.0 + 2 ** -7
-    assert orc.bf16_rne(-3.0) == -3.0
-    assert orc.bf16_rne(0.1) == 0.10009765625  # 0x3DCD
-    assert math.isnan(orc.bf16_rne(float("nan")))
-
-
-def test_bf16_features_within_bf16_precision_of_fp64(orc):
-    # rounding inputs and weights to 8 bits perturbs each product by <= 2^-8
-    # relative; the activations differ by about sqrt(d) 2^-8 |a||x| at most.
-    rng = np.random.default_rng(12)
-    M, d = 20, 64
-    A = rng.uniform(-1, 1, (M, d))
-    zeta = rng.uniform(-1, 1, M)
-    X = rng.uniform(-2, 2, (5, d)).astype(np.float32)
-    for act in (orc.TANH, orc.RELU):
-        net = orc.Net(A, zeta, act, 0.0, 2.0)
-        lo = orc.features_bf16(net, X)
-        hi = orc.features(net, X.astype(np.float64))
-        # outputs are bf16 numbers
-        np.testing.assert_array_equal(lo, np.vectorize(orc.bf16_rne)(lo))
-        assert np.abs(lo - hi).max() <= 4 * math.sqrt(d) * 2 ** -8
-
-
 def svd_ridge(Phi, Y, lam):
     U, s, Vt = np.linalg.svd(Phi, full_matrices=False)
     return Vt.T @ np.diag(s / (s ** 2 + lam)) @ U.T @ Y
