@@ -48,6 +48,30 @@ FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (AMD specification)
 # average over the four stages = 34.5 per cell-stage = 17.25 per DOF-stage.
 FLOPS_PER_DOF_STEP = {"diffreact": 4 * 17.25}
 
+# HBM bytes per 64-slot launch of the fine propagator, from one FETCH_SIZE and
+# one WRITE_SIZE hardware-counter run (KiB per dispatch), each scaled by what
+# the counter reads for a device copy of known size (FETCH x 2, WRITE x 1).
+# Valid only for the kernel sources they were taken on (hash below); any
+# change to them makes the field null until the counters are taken again.
+PROP_SOURCES = ("paper_2411_06225_amd/csrc/slotprop.h", "paper_2411_06225_amd/csrc/propagate.hip",
+                "paper_2411_06225_amd/csrc/common.h")
+PROP_TRAFFIC = {"sources": "48220047cc3f96e7", "fetch_kib": 2359.3, "fetch_scale": 2.0, "write_kib": 4608.0,
+                "write_scale": 1.0}
+
+
+def sources_hash(paths):
+    """First 16 hex digits of the SHA-1 of the files' SHA-1 digests in order."""
+    import hashlib
+    digests = "".join(hashlib.sha1(open(os.path.join(ROOT, p), "rb").read()).hexdigest() for p in paths)
+    return hashlib.sha1(digests.encode()).hexdigest()[:16]
+
+
+def measured_traffic():
+    if sources_hash(PROP_SOURCES) != PROP_TRAFFIC["sources"]:
+        return None
+    t = PROP_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -136,7 +160,7 @@ def main():
     f_flops = w.N * w.F[1] * w.d * FLOPS_PER_DOF_STEP["diffreact"]
     achieved = f_flops / f_sec
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
+                "frac": achieved / FP64_VECTOR_PEAK, "traffic": measured_traffic(),
                 "kernel": "k_prop_onchip (fine RK4, diffusion-reaction 64x64, FP64)",
                 "launch": {"slots": w.N, "steps": w.F[1], "flops_per_dof_step": FLOPS_PER_DOF_STEP["diffreact"],
                            "ms": f_sec * 1e3, "active_cu_fraction": w.N / 256}}
