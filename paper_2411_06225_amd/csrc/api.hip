@@ -414,11 +414,20 @@ static int tuned_prop_threads(const Geom &g, int esz, int method)
     return it == g_tune.end() ? 1024 : it->second;
 }
 
+// Device memory released when it goes out of scope.
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Trials of the autotuner on its own stream; the caller holds the tuning
+// table's lock.
 template <typename T>
-static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
+static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    tune_load();
     const Geom &g = p->g;
     const int N = p->N, d = g.d;
     std::ostringstream kc;
@@ -426,37 +435,37 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
     kc << "chain:" << g.kind << ":" << g.nx << "x" << g.ny << ":" << p->esz << ":M" << p->M << ":N" << N << ":"
        << p->corr << ":" << (p->feat_bf16 ? 1 : 0);
     const bool haveF = g_tune.count(kf) != 0, haveC = g_tune.count(kc.str()) != 0;
-    hipStream_t st;
-    RPR_HIP(hipStreamCreate(&st));
-    hipEvent_t e0, e1;
-    RPR_HIP(hipEventCreate(&e0));
-    RPR_HIP(hipEventCreate(&e1));
     T *U = static_cast<T *>(p->U), *Fv = static_cast<T *>(p->Fv), *Gc = static_cast<T *>(p->Gc);
-    rpr_status rc = RPR_OK;
-    auto done = [&]() {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        (void)hipStreamDestroy(st);
-    };
-    rc = zero(U, (size_t)(N + 1) * d, st);
-    if (rc == RPR_OK) rc = zero(Fv, (size_t)(N + 1) * d, st);
-    if (rc == RPR_OK) rc = zero(Gc, (size_t)(N + 1) * d, st);
-    if (rc == RPR_OK && p->W) rc = zero(p->W, (size_t)p->M * d, st);
-    if (rc != RPR_OK) { done(); return rc; }
+    RPR_TRY(zero(U, (size_t)(N + 1) * d, st));
+    RPR_TRY(zero(Fv, (size_t)(N + 1) * d, st));
+    RPR_TRY(zero(Gc, (size_t)(N + 1) * d, st));
+    if (p->W) RPR_TRY(zero(p->W, (size_t)p->M * d, st));
 
-    // fine propagator: 1024-thread (short strips) or 512-thread (long strips) work-groups
-    const bool tiledF = p->shF.maxt == TILED_THREADS;
-    if (!haveF && p->F.threads == 0 && !tiledF) {
+    // fine propagator: on chip with 1024-thread (short strips) or 512-thread
+    // (long strips) work-groups, or tiled through memory (2D grids)
+    const bool forced_tiled = p->shF.maxt == TILED_THREADS;
+    if (!haveF && p->F.threads == 0 && !forced_tiled) {
         const int64_t steps = p->F.steps < 32 ? p->F.steps : 32;
         float best = 1e30f;
         int best_mt = p->shF.maxt;
-        for (int mt : {1024, 512}) {
+        DevBuf trial;  // work arrays of the tiled candidate
+        for (int mt : {1024, 512, TILED_THREADS}) {
             if (check_threads(g, p->esz, mt) != RPR_OK) continue;
-            RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt));
+            TiledWork<T> w{};
+            if (mt == TILED_THREADS) {
+                if (hipMalloc(&trial.p, 5 * (size_t)N * d * p->esz) != hipSuccess) {
+                    (void)hipGetLastError();
+                    trial.p = nullptr;
+                    continue;
+                }
+                w = tiled_work<T>(trial.p, (size_t)N * d);
+            }
+            const TiledWork<T> *wp = mt == TILED_THREADS ? &w : nullptr;
+            RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp));
             float ms = 0.f;
             RPR_HIP(hipEventRecord(e0, st));
             for (int r = 0; r < 3; ++r)
-                RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt));
+                RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp));
             RPR_HIP(hipEventRecord(e1, st));
             RPR_HIP(hipEventSynchronize(e1));
             RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -464,9 +473,18 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
         }
         g_tune[kf] = best_mt;
     }
-    if (!tiledF) {
+    if (!forced_tiled) {
         const int mt = p->F.threads ? p->F.threads : g_tune[kf];
-        if (!onchip_shape(g, p->esz, &p->shF, mt)) { done(); return fail(RPR_ERR_HIP, "autotune: lost the F shape"); }
+        if (mt == TILED_THREADS) {
+            p->shF = tiled_shape(g, p->esz);
+            if (!p->fwork) {
+                char *c = nullptr;
+                RPR_TRY(dalloc(&c, 5 * (size_t)N * d * p->esz));
+                p->fwork = c;
+            }
+        } else if (!onchip_shape(g, p->esz, &p->shF, mt)) {
+            return fail(RPR_ERR_HIP, "autotune: lost the F shape");
+        }
     }
 
     // chain grid: one work-group, or a quarter, half or all of the CUs
@@ -517,8 +535,25 @@ static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
     }
     p->nwg = g_tune[kc.str()] < max_wg ? g_tune[kc.str()] : max_wg;
     if (!haveF || !haveC) tune_store();
-    done();
     return RPR_OK;
+}
+
+template <typename T>
+static rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rpr_status rc = RPR_OK;
+    if (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(RPR_ERR_HIP, "autotune: cannot create a stream or events");
+    if (rc == RPR_OK) rc = autotune_run<T>(p, max_wg, cus, st, e0, e1);
+    if (st) (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    return rc;
 }
 
 extern "C" const char *rpr_last_error(void) { return g_err.c_str(); }
