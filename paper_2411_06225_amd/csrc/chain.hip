@@ -160,13 +160,13 @@ __device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src
     for (long long s = 0; s < a.G_steps; ++s) {
         for (int stage = a.G_method == RPR_RK4 ? 1 : 0; stage <= (a.G_method == RPR_RK4 ? 4 : 0); ++stage) {
             const StageIO<T> io = stage_io<T>(a.G_method, stage, s, a.G_steps, src, dst, dst2, a.gw);
-            for (int tile = wg; tile < nt; tile += nwg) stage_tile<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
+            for (int tile = wg; tile < nt; tile += nwg) stage_tile_any<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
             sync();
         }
     }
 }
 
-// One sweep of one instance.  wg / nwg: this work-group and the number of// One sweep of one instance.  wg / nwg: this work-group and the number of
+// One sweep of one instance.  wg / nwg: this work-group and the number of
 // work-groups sharing the instance; sync(): a barrier over those work-groups
 // (a grid barrier, or a work-group barrier when nwg == 1).
 // TILED: the slot state does not fit one work-group; the coarse solver is

@@ -63,11 +63,10 @@ rpr_status launch_propagate_kind(const Geom &g, const OnchipShape &sh, int metho
 // One stage of the propagation of n slot states too large for one
 // work-group: block (tile, b) updates one tile of slot b (in + b d ->
 // out + b d, work arrays at b d).  Blocks of final slots exit at once.
-template <int KIND, typename T>
-__global__ __launch_bounds__(TT_THREADS) void k_prop_tiled(Geom g, int method, int stage, long long step,
-                                                           long long steps, double dt, const T *__restrict__ in,
-                                                           T *__restrict__ out, TiledWork<T> w,
-                                                           const int *__restrict__ ctrl)
+template <int KIND, typename T, int STAGE>
+__global__ __launch_bounds__(TT_THREADS) void k_prop_tiled(Geom g, int method, long long step, long long steps,
+                                                           double dt, const T *__restrict__ in, T *__restrict__ out,
+                                                           TiledWork<T> w, const int *__restrict__ ctrl)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int b = blockIdx.y;
@@ -75,8 +74,8 @@ __global__ __launch_bounds__(TT_THREADS) void k_prop_tiled(Geom g, int method, i
     const size_t off = (size_t)b * g.d;
     const TiledWork<T> wb{w.u + off, w.acc ? w.acc + off : nullptr, w.ya + off, w.yb ? w.yb + off : nullptr,
                           w.cmp ? w.cmp + off : nullptr};
-    const StageIO<T> io = stage_io<T>(method, stage, step, steps, in + off, out + off, nullptr, wb);
-    stage_tile<KIND, T>(g, blockIdx.x, stage, dt, io, reinterpret_cast<T *>(lds_raw));
+    const StageIO<T> io = stage_io<T>(method, STAGE, step, steps, in + off, out + off, nullptr, wb);
+    stage_tile<KIND, T, STAGE>(g, blockIdx.x, dt, io, reinterpret_cast<T *>(lds_raw));
 }
 
 template <int KIND, typename T>
@@ -90,12 +89,22 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
         if (n > 65535) return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 65535 states per launch");
         const dim3 grid((unsigned)tiles_of(g), (unsigned)n);
         const size_t lds = tiled_lds(g, sizeof(T));
-        for (long long s = 0; s < (long long)steps; ++s) {
-            for (int stage = method == RPR_RK4 ? 1 : 0; stage <= (method == RPR_RK4 ? 4 : 0); ++stage) {
-                hipLaunchKernelGGL((k_prop_tiled<KIND, T>), grid, dim3(TT_THREADS), lds, st, g, method, stage, s,
-                                   (long long)steps, dt, in, out, w, ctrl);
-                RPR_HIP(hipGetLastError());
+        const long long ns = (long long)steps;
+        for (long long s = 0; s < ns; ++s) {
+            if (method == RPR_RK4) {
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 1>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   in, out, w, ctrl);
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 2>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   in, out, w, ctrl);
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 3>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   in, out, w, ctrl);
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 4>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   in, out, w, ctrl);
+            } else {
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 0>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   in, out, w, ctrl);
             }
+            RPR_HIP(hipGetLastError());
         }
         return RPR_OK;
     }

@@ -5,8 +5,9 @@
 // over 64 x 16-cell tiles of the state in memory: a work-group of 256
 // threads copies the tile of the stage input with a one-cell halo into LDS
 // (the boundary rule applied while copying: wrap when periodic, the cell
-// itself at a wall), evaluates the right-hand side of its cells (4 rows per
-// thread) and applies the stage update to the RK arrays in memory.  The
+// itself at a wall), evaluates the right-hand side of its cells (a column of
+// 4 rows per thread, lane = column) and applies the stage update to the RK
+// arrays in memory.  The
 // update formulas, their order and the FP32 compensation are those of the
 // on-chip propagator, so both agree to rounding.
 #pragma once
@@ -21,10 +22,11 @@ constexpr int TT_RPT = TT_X * TT_Y / TT_THREADS;  // rows per thread
 __host__ __device__ inline int tiles_x(const Geom &g) { return (g.nx + TT_X - 1) / TT_X; }
 __host__ __device__ inline int tiles_of(const Geom &g) { return tiles_x(g) * ((g.ny + TT_Y - 1) / TT_Y); }
 
-// LDS of one haloed tile.
+// LDS of one haloed tile (shallow water: twice, for the per-cell flux
+// quantities).
 __host__ __device__ inline size_t tiled_lds(const Geom &g, size_t elem)
 {
-    return (size_t)g.ns * (TT_Y + 2) * (TT_X + 2) * elem;
+    return (size_t)g.ns * (TT_Y + 2) * (TT_X + 2) * elem * (g.kind == RPR_SWE2D ? 2 : 1);
 }
 
 // The arrays one stage touches in one slot state (d values each).
@@ -45,83 +47,338 @@ struct StageIO {
     int cmp_zero;
 };
 
-template <int KIND, typename T>
-__device__ __forceinline__ void stage_tile(const Geom &g, const int tile, const int stage, const double dt,
-                                           const StageIO<T> &io, T *__restrict__ lds)
+// Indices into one slot state are 32-bit (d < 2^31).
+// Load from global memory.  The stage arrays reach the tile code through a
+// struct, where the compiler no longer sees that they are global; a flat
+// load also counts against the scalar-load counter, so every wait for a
+// kernel argument would drain the tile's loads too.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// Shallow-water fluxes of one tile (Rusanov, as in the on-chip form), with
+// the per-cell quantities evaluated once per cell and each interface flux
+// once per interface:
+//   per cell  u = hu/h, v = hv/h, c = sqrt(g h), P = g h^2 / 2,
+//             x: (hu u + P, hv u, |u| + c),  y: (hv v + P, hu v, |v| + c);
+//   per face  a = max of the two speeds,
+//             F = (f_L + f_R)/2 - a (q_R - q_L)/2 component by component.
+// The stage input sits in lds[0 .. 3 PY PX) with wall ghosts already
+// mirrored; lds[3 PY PX .. 6 PY PX) holds the x quantities, then the y
+// quantities.  Threads: lane = column, TT_RPT rows per thread from cy0;
+// waves 0 and 1 also evaluate the halo rows, wave 2 the halo columns.
+template <typename T, typename Update>
+__device__ __forceinline__ void swe_tile(const Geom &g, const int x0, const int y0, const int lane, const int wv,
+                                         const int cy0, T *__restrict__ lds, const T (&uv)[TT_RPT][3],
+                                         Update &update)
+{
+    constexpr int PX = TT_X + 2, PY = TT_Y + 2, SP = PY * PX, R = TT_RPT;
+    const T gg = T(g.p[0]), idx = T(g.idx), idy = T(g.idy), half = T(0.5);
+    const int nx = g.nx, ny = g.ny, nc = g.nc;
+    const T *qb = lds;
+    T *db = lds + 3 * SP;
+    const int lx = lane + 1;
+
+    // own cells: state, x quantities to LDS, y quantities kept
+    T h[R], m[R], n[R], ym[R], yn[R], ys[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int o = (cy0 + q + 1) * PX + lx;
+        h[q] = qb[o];
+        m[q] = qb[SP + o];
+        n[q] = qb[2 * SP + o];
+        const T u = m[q] / h[q], v = n[q] / h[q], c = sqrt(gg * h[q]), P = half * gg * h[q] * h[q];
+        db[o] = m[q] * u + P;
+        db[SP + o] = n[q] * u;
+        db[2 * SP + o] = fabs(u) + c;
+        ym[q] = n[q] * v + P;
+        yn[q] = m[q] * v;
+        ys[q] = fabs(v) + c;
+    }
+    // halo rows (waves 0, 1: y quantities kept) and columns (wave 2: x quantities)
+    T hym = T(0), hyn = T(0), hys = T(0);
+    if (wv <= 1) {
+        const int o = (wv == 0 ? 0 : PY - 1) * PX + lx;
+        const T hh = qb[o], hm = qb[SP + o], hn = qb[2 * SP + o];
+        const T v = hn / hh, c = sqrt(gg * hh), P = half * gg * hh * hh;
+        hym = hn * v + P;
+        hyn = hm * v;
+        hys = fabs(v) + c;
+    } else if (wv == 2 && lane < 2 * TT_Y) {
+        const int o = (1 + (lane >> 1)) * PX + ((lane & 1) ? PX - 1 : 0);
+        const T hh = qb[o], hm = qb[SP + o], hn = qb[2 * SP + o];
+        const T u = hm / hh, c = sqrt(gg * hh), P = half * gg * hh * hh;
+        db[o] = hm * u + P;
+        db[SP + o] = hn * u;
+        db[2 * SP + o] = fabs(u) + c;
+    }
+    __syncthreads();
+
+    // x faces west and east of each own cell
+    T dh[R], dm[R], dn[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int o = (cy0 + q + 1) * PX + lx;
+        const T cm = db[o], cn = db[SP + o], cs = db[2 * SP + o];
+        T Fh[2], Fm[2], Fn[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int on = side ? o + 1 : o - 1;
+            const T oh = qb[on], om = qb[SP + on], onn = qb[2 * SP + on];
+            const T fm = db[on], fn = db[SP + on], fs = db[2 * SP + on];
+            // left and right states of the face
+            const T hL = side ? h[q] : oh, hR = side ? oh : h[q];
+            const T mL = side ? m[q] : om, mR = side ? om : m[q];
+            const T nL = side ? n[q] : onn, nR = side ? onn : n[q];
+            const T fmL = side ? cm : fm, fmR = side ? fm : cm;
+            const T fnL = side ? cn : fn, fnR = side ? fn : cn;
+            const T sL = side ? cs : fs, sR = side ? fs : cs;
+            const T a = sL > sR ? sL : sR;
+            Fh[side] = half * (mL + mR) - half * a * (hR - hL);
+            Fm[side] = half * (fmL + fmR) - half * a * (mR - mL);
+            Fn[side] = half * (fnL + fnR) - half * a * (nR - nL);
+        }
+        dh[q] = Fh[1] - Fh[0];
+        dm[q] = Fm[1] - Fm[0];
+        dn[q] = Fn[1] - Fn[0];
+    }
+    __syncthreads();
+
+    // y quantities replace the x quantities
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int o = (cy0 + q + 1) * PX + lx;
+        db[o] = ym[q];
+        db[SP + o] = yn[q];
+        db[2 * SP + o] = ys[q];
+    }
+    if (wv <= 1) {
+        const int o = (wv == 0 ? 0 : PY - 1) * PX + lx;
+        db[o] = hym;
+        db[SP + o] = hyn;
+        db[2 * SP + o] = hys;
+    }
+    __syncthreads();
+
+    // y faces of the strip: face f lies below own row f (f = 0 .. R)
+    T Gh[R + 1], Gm[R + 1], Gn[R + 1];
+#pragma unroll
+    for (int f = 0; f <= R; ++f) {
+        T hL, nL, mL, gmL, gnL, sL, hR, nR, mR, gmR, gnR, sR;
+        if (f == 0) {
+            const int o = cy0 * PX + lx;
+            hL = qb[o]; mL = qb[SP + o]; nL = qb[2 * SP + o];
+            gmL = db[o]; gnL = db[SP + o]; sL = db[2 * SP + o];
+        } else {
+            hL = h[f - 1]; mL = m[f - 1]; nL = n[f - 1];
+            gmL = ym[f - 1]; gnL = yn[f - 1]; sL = ys[f - 1];
+        }
+        if (f == R) {
+            const int o = (cy0 + R + 1) * PX + lx;
+            hR = qb[o]; mR = qb[SP + o]; nR = qb[2 * SP + o];
+            gmR = db[o]; gnR = db[SP + o]; sR = db[2 * SP + o];
+        } else {
+            hR = h[f]; mR = m[f]; nR = n[f];
+            gmR = ym[f]; gnR = yn[f]; sR = ys[f];
+        }
+        const T a = sL > sR ? sL : sR;
+        Gh[f] = half * (nL + nR) - half * a * (hR - hL);
+        Gm[f] = half * (gmL + gmR) - half * a * (nR - nL);  // normal (hv) component
+        Gn[f] = half * (gnL + gnR) - half * a * (mR - mL);  // tangential (hu) component
+    }
+
+    const int gx = x0 + lane;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int gy = y0 + cy0 + q;
+        if (gx < nx && gy < ny) {
+            const int c0 = gy * nx + gx;
+            const T k0 = -dh[q] * idx - (Gh[q + 1] - Gh[q]) * idy;
+            const T k1 = -dm[q] * idx - (Gn[q + 1] - Gn[q]) * idy;
+            const T k2 = -dn[q] * idx - (Gm[q + 1] - Gm[q]) * idy;
+            update(q, 0, c0, uv[q][0], k0, h[q]);
+            update(q, 1, nc + c0, uv[q][1], k1, m[q]);
+            update(q, 2, 2 * nc + c0, uv[q][2], k2, n[q]);
+        }
+    }
+}
+
+// The tile of the stage input with its one-cell halo goes to LDS; each wave
+// copies whole rows (one cell per lane, the boundary rule applied to the
+// row index), the two halo columns follow in one pass.  Every load of the
+// tile is issued before the first LDS write, and the operands of the stage
+// update are fetched before the right-hand side is evaluated, so a
+// work-group waits for memory once per stage instead of once per access.
+template <int KIND, typename T, int STAGE>
+__device__ __forceinline__ void stage_tile(const Geom &g, const int tile, const double dt, const StageIO<T> &io,
+                                           T *__restrict__ lds)
 {
     constexpr int NS = kind_ns<KIND>();
     constexpr int PX = TT_X + 2, PY = TT_Y + 2;
+    constexpr int NW = TT_THREADS / 64;                // waves
+    constexpr int NR = (NS * PY + NW - 1) / NW;        // rows per wave
+    constexpr int NH = NS * PY * 2;                    // halo-column cells
     constexpr bool KAHAN = sizeof(T) == 4;
+    constexpr bool Y_IS_U = STAGE <= 1;                // Euler and the first RK4 stage read u itself
+    static_assert(TT_X == 64 && NH <= TT_THREADS, "tile shape");
     const int nx = g.nx, ny = g.ny, nc = g.nc;
     const bool per = g.periodic != 0;
     const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
-    for (int e = t; e < NS * PY * PX; e += blockDim.x) {
-        const int sp = e / (PY * PX), r = e % (PY * PX), ly = r / PX, lx = r % PX;
-        int gx = x0 + lx - 1, gy = y0 + ly - 1;
-        if (per) {
-            gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-            gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-        } else {
-            gx = gx < 0 ? 0 : (gx >= nx ? nx - 1 : gx);
-            gy = gy < 0 ? 0 : (gy >= ny ? ny - 1 : gy);
+    // Every load below is unconditional, with indices clamped into the
+    // state (values of cells outside it are loaded but never used), so no
+    // control flow separates a load from its use.
+    // rows of the tile: lane = interior column
+    int gxi = x0 + lane;
+    gxi = gxi < nx ? gxi : (per ? gxi - nx : nx - 1);
+    gxi = gxi < nx ? gxi : nx - 1;
+    T rowv[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int r0 = wv + j * NW;  // species-major row index
+        const int r = r0 < NS * PY ? r0 : NS * PY - 1;
+        const int sp = r / PY, ly = r % PY;
+        const int gy0 = y0 + ly - 1;
+        const int gyw = gy0 < 0 ? gy0 + ny : (gy0 >= ny ? gy0 - ny : gy0);
+        const int gyc = gy0 < 0 ? 0 : (gy0 >= ny ? ny - 1 : gy0);
+        int gy = per ? gyw : gyc;
+        gy = gy < ny ? gy : ny - 1;
+        rowv[j] = gload(io.y + (sp * nc + gy * nx + gxi));
+        if constexpr (KIND == RPR_SWE2D) {
+            // a wall ghost is the mirror image: normal momentum negated
+            const bool xg = !per && x0 + lane >= nx, yg = !per && (gy0 < 0 || gy0 >= ny);
+            if ((sp == 1 && xg) || (sp == 2 && yg)) rowv[j] = -rowv[j];
         }
-        lds[e] = io.y[sp * nc + gy * nx + gx];
+    }
+    // halo columns x0 - 1 and x0 + TT_X
+    T halov;
+    {
+        const int th = t < NH ? t : NH - 1;
+        const int sp = th / (2 * PY), r = th % (2 * PY), ly = r >> 1, side = r & 1;
+        const int gx0 = side ? x0 + TT_X : x0 - 1, gy0 = y0 + ly - 1;
+        const int gxw = gx0 < 0 ? gx0 + nx : (gx0 >= nx ? gx0 - nx : gx0);
+        const int gxc = gx0 < 0 ? 0 : (gx0 >= nx ? nx - 1 : gx0);
+        const int gyw = gy0 < 0 ? gy0 + ny : (gy0 >= ny ? gy0 - ny : gy0);
+        const int gyc = gy0 < 0 ? 0 : (gy0 >= ny ? ny - 1 : gy0);
+        int gx = per ? gxw : gxc, gy = per ? gyw : gyc;
+        gx = gx < nx ? gx : nx - 1;
+        gy = gy < ny ? gy : ny - 1;
+        halov = gload(io.y + (sp * nc + gy * nx + gx));
+        if constexpr (KIND == RPR_SWE2D) {
+            const bool xg = !per && (gx0 < 0 || gx0 >= nx), yg = !per && (gy0 < 0 || gy0 >= ny);
+            if ((sp == 1 && xg) || (sp == 2 && yg)) halov = -halov;
+        }
+    }
+
+    // operands of the stage update of this thread's cells
+    const int cy0 = wv * TT_RPT;
+    const int gx = x0 + lane;
+    const int gxs = gx < nx ? gx : nx - 1;
+    T uv[TT_RPT][NS], av[TT_RPT][NS], cv[TT_RPT][NS];
+#pragma unroll
+    for (int q = 0; q < TT_RPT; ++q) {
+        const int gy = y0 + cy0 + q;
+        const int gys = gy < ny ? gy : ny - 1;
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const int idx = sp * nc + gys * nx + gxs;
+            uv[q][sp] = Y_IS_U ? T(0) : gload(io.u + idx);
+            av[q][sp] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? gload(io.acc + idx) : T(0);
+            if constexpr (KAHAN && (STAGE == 0 || STAGE == 4)) {
+                const T cm = gload(io.cmp + idx);
+                cv[q][sp] = io.cmp_zero ? T(0) : cm;
+            } else {
+                cv[q][sp] = T(0);
+            }
+        }
+    }
+
+    // keep every load above in flight before the first LDS write
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int r = wv + j * NW;
+        if (r < NS * PY) lds[r * PX + 1 + lane] = rowv[j];
+    }
+    if (t < NH) {
+        const int sp = t / (2 * PY), r = t % (2 * PY), ly = r >> 1, side = r & 1;
+        lds[(sp * PY + ly) * PX + (side ? PX - 1 : 0)] = halov;
     }
     __syncthreads();
 
     const T dtT = T(dt), hdt = T(0.5 * dt), dt6 = T(dt / 6.0);
-    const int cx = t % TT_X, cy0 = (t / TT_X) * TT_RPT;
-    const int gx = x0 + cx;
-#pragma unroll
-    for (int q = 0; q < TT_RPT; ++q) {
-        const int gy = y0 + cy0 + q;
-        if (t < TT_THREADS && gx < nx && gy < ny) {
-            const int lx = cx + 1, ly = cy0 + q + 1;
-            T c[NS], w[NS], e[NS], s[NS], n[NS], k[NS];
-#pragma unroll
-            for (int sp = 0; sp < NS; ++sp) {
-                const T *b = lds + sp * PY * PX;
-                c[sp] = b[ly * PX + lx];
-                w[sp] = b[ly * PX + lx - 1];
-                e[sp] = b[ly * PX + lx + 1];
-                s[sp] = b[(ly - 1) * PX + lx];
-                n[sp] = b[(ly + 1) * PX + lx];
+    // stage update of cell (q, sp) at idx with slope k: the RK base value is
+    // uu, or the stage input yy where the stage reads u itself
+    auto update = [&](const int q, const int sp, const int idx, const T uu, const T k, const T yy) {
+        const T u = Y_IS_U ? yy : uu;
+        if constexpr (STAGE == 1) {
+            io.acc[idx] = k;
+            io.y_out[idx] = u + hdt * k;
+        } else if constexpr (STAGE == 2) {
+            io.acc[idx] = av[q][sp] + T(2) * k;
+            io.y_out[idx] = u + hdt * k;
+        } else if constexpr (STAGE == 3) {
+            io.acc[idx] = av[q][sp] + T(2) * k;
+            io.y_out[idx] = u + dtT * k;
+        } else {
+            const T inc = STAGE == 4 ? dt6 * (av[q][sp] + k) : dtT * k;
+            if constexpr (KAHAN) {
+                const T yk = inc - cv[q][sp];
+                const T un = u + yk;
+                io.cmp[idx] = (un - u) - yk;
+                io.u_out[idx] = un;
+                if (io.u_out2) io.u_out2[idx] = un;
+            } else {
+                io.u_out[idx] = u + inc;
+                if (io.u_out2) io.u_out2[idx] = u + inc;
             }
-            rhs_cell<KIND, T>(g, c, w, e, s, n, !per && gx == 0, !per && gx == nx - 1, !per && gy == 0,
-                              !per && gy == ny - 1, k);
+        }
+    };
+
+    if constexpr (KIND == RPR_SWE2D) {
+        swe_tile<T>(g, x0, y0, lane, wv, cy0, lds, uv, update);
+    } else {
 #pragma unroll
-            for (int sp = 0; sp < NS; ++sp) {
-                const size_t idx = (size_t)sp * nc + (size_t)gy * nx + gx;
-                if (stage == 1) {
-                    io.acc[idx] = k[sp];
-                    io.y_out[idx] = io.u[idx] + hdt * k[sp];
-                } else if (stage == 2) {
-                    io.acc[idx] = io.acc[idx] + T(2) * k[sp];
-                    io.y_out[idx] = io.u[idx] + hdt * k[sp];
-                } else if (stage == 3) {
-                    io.acc[idx] = io.acc[idx] + T(2) * k[sp];
-                    io.y_out[idx] = io.u[idx] + dtT * k[sp];
-                } else {
-                    const T inc = stage == 4 ? dt6 * (io.acc[idx] + k[sp]) : dtT * k[sp];
-                    const T u = io.u[idx];
-                    if constexpr (KAHAN) {
-                        const T cm = io.cmp_zero ? T(0) : io.cmp[idx];
-                        const T yk = inc - cm;
-                        const T un = u + yk;
-                        io.cmp[idx] = (un - u) - yk;
-                        io.u_out[idx] = un;
-                        if (io.u_out2) io.u_out2[idx] = un;
-                    } else {
-                        io.u_out[idx] = u + inc;
-                        if (io.u_out2) io.u_out2[idx] = u + inc;
-                    }
+        for (int q = 0; q < TT_RPT; ++q) {
+            const int gy = y0 + cy0 + q;
+            if (gx < nx && gy < ny) {
+                const int lx = lane + 1, ly = cy0 + q + 1;
+                T c[NS], w[NS], e[NS], s[NS], n[NS], k[NS];
+#pragma unroll
+                for (int sp = 0; sp < NS; ++sp) {
+                    const T *b = lds + sp * PY * PX;
+                    c[sp] = b[ly * PX + lx];
+                    w[sp] = b[ly * PX + lx - 1];
+                    e[sp] = b[ly * PX + lx + 1];
+                    s[sp] = b[(ly - 1) * PX + lx];
+                    n[sp] = b[(ly + 1) * PX + lx];
                 }
+                rhs_cell<KIND, T>(g, c, w, e, s, n, !per && gx == 0, !per && gx == nx - 1, !per && gy == 0,
+                                  !per && gy == ny - 1, k);
+#pragma unroll
+                for (int sp = 0; sp < NS; ++sp)
+                    update(q, sp, sp * nc + gy * nx + gx, uv[q][sp], k[sp], c[sp]);
             }
         }
     }
     __syncthreads();  // the tile buffer is reused by the next tile
+}
+
+// stage_tile with the stage chosen at run time.
+template <int KIND, typename T>
+__device__ __forceinline__ void stage_tile_any(const Geom &g, const int tile, const int stage, const double dt,
+                                               const StageIO<T> &io, T *__restrict__ lds)
+{
+    switch (stage) {
+        case 0: stage_tile<KIND, T, 0>(g, tile, dt, io, lds); break;
+        case 1: stage_tile<KIND, T, 1>(g, tile, dt, io, lds); break;
+        case 2: stage_tile<KIND, T, 2>(g, tile, dt, io, lds); break;
+        case 3: stage_tile<KIND, T, 3>(g, tile, dt, io, lds); break;
+        default: stage_tile<KIND, T, 4>(g, tile, dt, io, lds); break;
+    }
 }
 
 // The arrays of stage `stage` (0 Euler, 1..4 RK4) of step `step` of a
