@@ -15,17 +15,22 @@ unfinished slots times 4000, divided by the wall time of the solve.
 
 Also reported: the roofline of the dominant kernel (the fine propagator,
 timed live with HIP events on its launch stream), the same solve in mixed
-precision (FP32 states) with its accuracy, and the CPU oracle timed on the
-host cores on the same workload.
+precision (FP32 states) with its accuracy, the time each precision takes to
+reach a common accuracy tau = 10 x the error of an FP32 serial fine solve
+(solves stopped after k iterations, k increased until the mean slot error
+against the FP64 serial fine solution is <= tau), and the CPU oracle timed
+on the host cores on the same workload.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline] [--no-mixed]
-                    [--extra] [--copy-calibration]
+                    [--extra] [--copy-calibration] [--f-only swe_192x192]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
 (Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems;
 shallow water 192 x 192), which takes minutes.  --copy-calibration runs a
 device copy of 256 MiB, the reference a hardware-counter run uses to scale
-its byte counters.
+its byte counters.  --f-only times only the fine propagator of the named
+workload (all N slot states, --steps RK4 steps, FP64 and FP32) and prints
+its roofline, for counter runs.
 """
 from __future__ import annotations
 
@@ -55,7 +60,7 @@ FLOPS_PER_DOF_STEP = {"diffreact": 4 * 17.25}
 # change to them makes the field null until the counters are taken again.
 PROP_SOURCES = ("paper_2411_06225_amd/csrc/slotprop.h", "paper_2411_06225_amd/csrc/propagate.hip",
                 "paper_2411_06225_amd/csrc/common.h")
-PROP_TRAFFIC = {"sources": "48220047cc3f96e7", "fetch_kib": 2359.3, "fetch_scale": 2.0, "write_kib": 4608.0,
+PROP_TRAFFIC = {"sources": "3bce6799c68047c1", "fetch_kib": 2359.5, "fetch_scale": 2.0, "write_kib": 4608.0,
                 "write_scale": 1.0}
 
 
@@ -82,6 +87,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--f-only", choices=["swe_192x192"], default=None,
+                    help="only time the fine propagator of this workload in FP64 and FP32 (for counter runs)")
     return ap.parse_args()
 
 
@@ -98,15 +105,25 @@ def main():
     w = W.DIFFREACT_64
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.f_only:
+        wf = W.SWE_192
+        cb = copy_bandwidth(torch, dev)
+        res = {"workload": wf.name, "F_roofline": {
+            "fp64": f_roofline(torch, rpr, wf, rpr.RPR_FP64, dev, steps=args.steps, copy_bw=cb),
+            "fp32": f_roofline(torch, rpr, wf, rpr.RPR_MIXED, dev, steps=args.steps, copy_bw=cb)}}
+        if args.copy_calibration:
+            res["copy_calibration_bytes"] = copy_calibration(torch, dev)
+        print(json.dumps(res))
+        return
     h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
     u0h = W.initial_condition(w)
     A, zeta = W.random_weights(w)
     u0 = torch.tensor(u0h, dtype=torch.float64, device=dev)
     T = (w.tN - w.t0) / w.N
 
-    def make_plan(prec):
+    def make_plan(prec, k_max=0):
         return rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
-                        A=A, zeta=zeta, precision=prec, correction=rpr.RPR_CORR_RANDNET, autotune=1)
+                        A=A, zeta=zeta, precision=prec, correction=rpr.RPR_CORR_RANDNET, autotune=1, k_max=k_max)
 
     def timed_solves(plan, steps, warmup):
         U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
@@ -189,6 +206,20 @@ def main():
         "roofline": roofline,
     }
 
+    def time_to_tau(prec, tau, k_stop):
+        """First iteration k whose U^k is within tau of the FP64 serial fine
+        solution (E as above), and the time of a solve stopped after k
+        iterations: the solve runs with k_max = k, so it does exactly the
+        work of the first k iterations; E is taken outside the timed part."""
+        for k in range(1, k_stop + 1):
+            p = make_plan(prec, k_max=k)
+            t, Uk = timed_solves(p, 2, 1)
+            p.close()
+            Ek = float((Uk[1:] - Uf[1:]).abs().amax(dim=1).mean())
+            if Ek <= tau:
+                return {"k": k, "s": t, "E": Ek}
+        return {"k": None, "s": None, "E": None}
+
     if not args.no_mixed:
         mplan = make_plan(rpr.RPR_MIXED)
         msec, Um = timed_solves(mplan, args.steps, 1)
@@ -199,26 +230,26 @@ def main():
         out["mixed"] = {"ms_per_solve": msec * 1e3, "K": minfo["K"], "E_vs_fp64_serial_fine": Em,
                         "fp32_serial_fine_error_floor": E32floor, "fp64_over_mixed_time": sec / msec}
         mplan.close()
+        # time to the common accuracy tau = 10 x the FP32 serial fine error
+        tau = 10.0 * E32floor
+        t64 = time_to_tau(rpr.RPR_FP64, tau, K)
+        t32 = time_to_tau(rpr.RPR_MIXED, tau, minfo["K"])
+        out["time_to_tau"] = {"tau": tau, "fp64": t64, "mixed": t32,
+                              "fp64_over_mixed": (t64["s"] / t32["s"]) if t64["s"] and t32["s"] else None}
     plan.close()
 
     if args.copy_calibration:
-        # a plain copy of known size: a counter run scales FETCH_SIZE / WRITE_SIZE by it
-        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = a.numel() * 8
+        out["copy_calibration_bytes"] = copy_calibration(torch, dev)
 
     if args.extra:
         out["extra"] = extra_workloads(torch, rpr, W, dev)
 
     if not args.no_cpu_baseline:
-        # bounded sample: the fine solves of 4 x threads slots (the part of a
-        # solve that dominates it), by the oracle
+        # bounded sample: the fine solves of 32 x threads slots (the part of
+        # a solve that dominates it, about 10 s), by the oracle
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
-        n_sample = 4 * threads
+        n_sample = 32 * threads
         pb = oracle.problem(w.kind, w.nx, w.ny, w.domain, w.params)
         X = np.tile(u0h, (n_sample, 1))
         t0 = time.perf_counter()
@@ -231,6 +262,73 @@ def main():
                                          f"fine solves are the bulk of an oracle solve, so the rate bounds its "
                                          f"whole-solve rate from above"}
     print(json.dumps(out))
+
+
+def copy_calibration(torch, dev):
+    """A plain device copy of 256 MiB: a counter run scales FETCH_SIZE and
+    WRITE_SIZE by what they read for it."""
+    a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return a.numel() * 8
+
+
+def copy_bandwidth(torch, dev, mib=1024, reps=5):
+    """Device-to-device copy rate (bytes read + bytes written per second) of
+    a mib-MiB buffer, HIP events: the measured HBM ceiling beside the
+    specification's."""
+    a = torch.ones(mib * 1024 * 1024 // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    torch.cuda.synchronize()
+    return 2 * a.numel() * 8 * reps / (ev[0].elapsed_time(ev[1]) / 1e3)
+
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s (AMD specification)
+# Array accesses per degree of freedom and classical RK4 step of the tiled
+# (through-memory) propagator, one pass per stage:
+#   stage 1: read y (= u), write acc, write y_out            3
+#   stage 2, 3: read y, u, acc, write acc, write y_out       5 + 5
+#   stage 4: read y, u, acc, write u_out (+ read and write
+#            the FP32 compensation)                          4 (FP32: 6)
+# The one-cell halo rows and columns a tile re-reads are not counted.
+TILED_ACCESSES_PER_DOF_STEP = {8: 17, 4: 19}
+
+
+def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
+    """Time one launch of the fine propagator over all N slot states of
+    workload w (steps RK4 steps) with HIP events on its stream and relate the
+    algorithmic bytes of the tiled form to the HBM peak."""
+    h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+    from paper_2411_06225_amd import workloads as W
+    dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
+    esz = 8 if prec == rpr.RPR_FP64 else 4
+    X = torch.tensor(W.initial_condition(w), dtype=dtype, device=dev)[None].repeat(w.N, 1).contiguous()
+    Y = torch.empty_like(X)
+    dt = (w.tN - w.t0) / w.N / w.F[1]
+    stream = torch.cuda.current_stream()
+    rpr.rpr_propagate(h, w.d, w.F[0], 2, prec, dt, w.N, X, Y, stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    rpr.rpr_propagate(h, w.d, w.F[0], steps, prec, dt, w.N, X, Y, stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    sec = ev[0].elapsed_time(ev[1]) / 1e3
+    bytes_ = w.N * w.d * steps * TILED_ACCESSES_PER_DOF_STEP[esz] * esz
+    achieved = bytes_ / sec
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "kernel": "k_prop_tiled (fine RK4, one launch per stage)",
+            "measured_copy_GBps": copy_bw / 1e9 if copy_bw else None,
+            "frac_of_copy": achieved / copy_bw if copy_bw else None,
+            "launch": {"slots": w.N, "steps": steps, "ms_per_step": sec * 1e3 / steps,
+                       "bytes_per_dof_step": TILED_ACCESSES_PER_DOF_STEP[esz] * esz}}
 
 
 def extra_workloads(torch, rpr, W, dev):
@@ -270,6 +368,9 @@ def extra_workloads(torch, rpr, W, dev):
     res["burgers_d128"] = single(W.BURGERS_D128)
     res["bruss_128x128"] = single(W.BRUSS_128)
     res["swe_192x192"] = single(W.SWE_192)
+    cb = copy_bandwidth(torch, dev)
+    res["swe_192x192"]["F_roofline"] = {"fp64": f_roofline(torch, rpr, W.SWE_192, rpr.RPR_FP64, dev, copy_bw=cb),
+                                        "fp32": f_roofline(torch, rpr, W.SWE_192, rpr.RPR_MIXED, dev, copy_bw=cb)}
 
     bw = W.burgers_batch()
     problems = []

@@ -103,6 +103,10 @@ typedef struct {
     double lambda;             /* ridge penalty of eq. "ridgeless" (> 0) */
     double input_scale;        /* the network sees x / s; <= 0 selects the default:
                                   the smallest power of two s >= max(1, ||u0||_inf) */
+    int32_t m_nn;              /* RPR_CORR_RANDNET_NN only: nearest stored pairs each
+                                  prediction is fitted on, 1 <= m_nn <= 32 (the paper
+                                  uses 3 or 4, App. G tables); ignored otherwise */
+    int32_t reserved;          /* must be 0 */
 } rpr_randnet;
 
 typedef enum {
@@ -117,7 +121,17 @@ typedef enum {
 typedef enum {
     RPR_CORR_RANDNET = 0,      /* eq. "HA" with the readout of eq. "ridgeless" fitted on
                                   every pair of eq. "Dk" collected so far */
-    RPR_CORR_PARAREAL = 1      /* eq. "fpara": (F - G)(U_{i-1}^{k-1}) */
+    RPR_CORR_PARAREAL = 1,     /* eq. "fpara": (F - G)(U_{i-1}^{k-1}) */
+    RPR_CORR_RANDNET_NN = 2    /* eq. "randnet": every prediction refits the readout
+                                  of eq. "ridgeless" on the m_nn stored pairs whose
+                                  inputs are nearest (Euclidean) to the slot input
+                                  (Alg. "RandNets training procedure"; App. B), in
+                                  the dual form W = Phi~^T (Phi~ Phi~^T + lambda I)^-1 Y~
+                                  (identical to the primal form); ties between
+                                  equal distances go to the earlier pair.  The plan
+                                  stores every finite pair: 2 N k_max d states plus
+                                  N k_max M doubles of features.  Single plans only
+                                  (a batch gives RPR_ERR_UNSUPPORTED). */
 } rpr_correction;
 
 typedef enum {
@@ -189,7 +203,9 @@ typedef struct {
     int32_t converged;         /* 1 if L reached N */
     int32_t rows_used;         /* finite training pairs accumulated in the readout */
     int32_t nonfinite_rows;    /* pairs dropped because of a non-finite entry */
-    int32_t chol_fail;         /* iterations whose ridge matrix failed Cholesky */
+    int32_t chol_fail;         /* ridge matrices that failed Cholesky: iterations of
+                                  RPR_CORR_RANDNET, predictions of RPR_CORR_RANDNET_NN
+                                  (such a prediction adds no correction) */
     double input_scale;        /* s actually used */
     double t_total;            /* seconds of device time of the last execute */
 } rpr_info;

@@ -28,7 +28,7 @@ RPR_BURGERS1D, RPR_DIFFREACT2D, RPR_BRUSS2D, RPR_SWE2D = 0, 1, 2, 3
 RPR_RK1, RPR_RK4 = 1, 4
 RPR_TANH, RPR_RELU = 0, 1
 RPR_FP64, RPR_MIXED = 0, 1
-RPR_CORR_RANDNET, RPR_CORR_PARAREAL = 0, 1
+RPR_CORR_RANDNET, RPR_CORR_PARAREAL, RPR_CORR_RANDNET_NN = 0, 1, 2
 RPR_FEAT_AUTO, RPR_FEAT_FP64, RPR_FEAT_BF16 = 0, 1, 2
 
 EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
@@ -54,7 +54,8 @@ class rpr_propagator(C.Structure):
 
 
 class rpr_randnet(C.Structure):
-    _fields_ = [("M", C.c_int32), ("activation", C.c_int32), ("lam", C.c_double), ("input_scale", C.c_double)]
+    _fields_ = [("M", C.c_int32), ("activation", C.c_int32), ("lam", C.c_double), ("input_scale", C.c_double),
+                ("m_nn", C.c_int32), ("reserved", C.c_int32)]
 
 
 class rpr_options(C.Structure):
@@ -190,13 +191,13 @@ class Plan:
                  tol: float = 1e-6, M: int = 100, activation: int = RPR_TANH, lam: float = 1e-6,
                  input_scale: float = 0.0, A=None, zeta=None, seed: int = 0, precision: int = RPR_FP64,
                  correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0,
-                 features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0):
+                 features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0, m_nn: int = 4):
         import numpy as np
         self.d, self.N = int(d), int(N)
         # F, G: (method, steps) or (method, steps, threads)
         self._F = rpr_propagator(int(F[0]), int(F[2]) if len(F) > 2 else 0, int(F[1]))
         self._G = rpr_propagator(int(G[0]), int(G[2]) if len(G) > 2 else 0, int(G[1]))
-        self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale))
+        self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale), int(m_nn), 0)
         self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features),
                                 int(autotune), int(graph), 0)
         self._h = h

@@ -27,7 +27,7 @@ REALS = ("double", "float")
 
 def _units():
     units = []
-    for src in ("propagate", "chain"):
+    for src in ("propagate", "tiled", "chain"):
         for k, kname in KINDS.items():
             for real in REALS:
                 obj = os.path.join(BUILD, f"{src}_{kname}_{real}.o")

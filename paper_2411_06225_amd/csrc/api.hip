@@ -157,6 +157,8 @@ __global__ void k_init_ctrl(Ctrl *c, int *L_hist, double *chg_hist)
     c->rows_used = 0;
     c->nonfinite = 0;
     c->chol_fail = 0;
+    c->nn_rows = 0;
+    c->pad = 0;
     L_hist[0] = 0;
     chg_hist[0] = 0.0;
 }
@@ -210,6 +212,14 @@ struct rpr_plan {
     hipStream_t cap_stream = nullptr;   // private stream the block is captured on
     void *gchain = nullptr;             // device ChainArgs<T> of the captured chain
     double *hpart = nullptr;            // chain: per-work-group hidden-layer partial sums (grid x M)
+    // nearest-neighbour correction: the store of every pair (n_cap rows)
+    bool nn = false;
+    int m_nn = 0, n_cap = 0;
+    void *Xs = nullptr, *Ys = nullptr;  // n_cap x d states
+    double *Ps = nullptr;               // n_cap x M features
+    int *oks = nullptr;                 // n_cap finite flags
+    double *dist = nullptr;             // n_cap squared distances of the current slot input
+    double *dpart = nullptr;            // chain grid x n_cap partial distances
     void *fwork = nullptr;              // tiled F: u, acc, ya, yb, cmp (N x d each)
     void *gwork = nullptr;              // tiled coarse solver: u, acc, ya, yb, cmp (d each)
     std::vector<double> bscale;         // batch: input scales the captured block was built for
@@ -243,7 +253,8 @@ static void plan_free(rpr_plan *p)
 {
     for (rpr_plan *q : p->sub) plan_free(q);
     p->sub.clear();
-    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain, p->hpart, p->fwork, p->gwork};
+    void *bb[] = {p->binsts, p->bitems, p->bcounter, p->bchain, p->hpart, p->fwork, p->gwork,
+                  p->Xs, p->Ys, p->Ps, p->oks, p->dist, p->dpart};
     for (void *b : bb)
         if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
@@ -300,18 +311,28 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
     RPR_TRY(dalloc(&p->chg_hist, N + 1));
     RPR_TRY(dalloc(&p->u0max, 1));
     RPR_TRY(dalloc(&p->u0bad, 1));
-    if (p->corr == RPR_CORR_RANDNET) {
+    if (p->corr == RPR_CORR_RANDNET || p->nn) {
         RPR_TRY(dalloc(&c, (size_t)N * d * p->esz)); p->X = c;
         RPR_TRY(dalloc(&c, (size_t)N * d * p->esz)); p->Y = c;
         RPR_TRY(dalloc(&p->A, (size_t)M * d));
         RPR_TRY(dalloc(&p->zeta, M));
         RPR_TRY(dalloc(&p->Phi, (size_t)N * M));
         RPR_TRY(dalloc(&p->fpart, (size_t)feat_splits(d) * N * M));
-        RPR_TRY(dalloc(&p->Gm, (size_t)M * M));
-        RPR_TRY(dalloc(&p->Lf, (size_t)M * M));
-        RPR_TRY(dalloc(&p->Lt, (size_t)M * M));
-        RPR_TRY(dalloc(&p->Bm, (size_t)M * d));
-        RPR_TRY(dalloc(&p->W, (size_t)M * d));
+        if (p->nn) {
+            // every pair of the run: at most N per iteration
+            p->n_cap = N * p->k_max;
+            RPR_TRY(dalloc(&c, (size_t)p->n_cap * d * p->esz)); p->Xs = c;
+            RPR_TRY(dalloc(&c, (size_t)p->n_cap * d * p->esz)); p->Ys = c;
+            RPR_TRY(dalloc(&p->Ps, (size_t)p->n_cap * M));
+            RPR_TRY(dalloc(&p->oks, p->n_cap));
+            RPR_TRY(dalloc(&p->dist, p->n_cap));
+        } else {
+            RPR_TRY(dalloc(&p->Gm, (size_t)M * M));
+            RPR_TRY(dalloc(&p->Lf, (size_t)M * M));
+            RPR_TRY(dalloc(&p->Lt, (size_t)M * M));
+            RPR_TRY(dalloc(&p->Bm, (size_t)M * d));
+            RPR_TRY(dalloc(&p->W, (size_t)M * d));
+        }
         RPR_TRY(dalloc(&p->phi, M));
         RPR_TRY(dalloc(&p->ok, N));
         RPR_TRY(dalloc(&p->nrows, 1));
@@ -343,6 +364,29 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
         RPR_HIP(hipMalloc(&p->gchain, sizeof(ChainArgs<double>)));
     }
     return RPR_OK;
+}
+
+// Chain mode of a plan's iterations.
+static int chain_mode(const rpr_plan *p)
+{
+    if (p->nn) return CHAIN_RANDNET_NN;
+    return p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+}
+
+// The nearest-neighbour store in the chain's arguments.
+template <typename T>
+static void nn_args(const rpr_plan *p, ChainArgs<T> &a)
+{
+    a.m_nn = p->m_nn;
+    a.lambda = p->lambda;
+    a.Xs = static_cast<const T *>(p->Xs);
+    a.Ys = static_cast<const T *>(p->Ys);
+    a.Ps = p->Ps;
+    a.oks = p->oks;
+    a.nrows = p->nrows;
+    a.n_cap = p->n_cap;
+    a.dpart = p->dpart;
+    a.dist = p->dist;
 }
 
 // --------------------------------------------------------------- autotuner --
@@ -491,7 +535,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
     if (!haveC) {
         ChainArgs<T> a{};
         a.g = g;
-        a.mode = p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+        a.mode = chain_mode(p);
         a.N = N;
         a.M = p->M;
         a.act = p->act;
@@ -514,12 +558,14 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         a.At = p->At;
         a.part = p->part;
         a.ctrl = p->ctrl;
+        nn_args<T>(p, a);
+        if (p->nn) RPR_TRY(zero(p->nrows, 1, st));  // the trials run with an empty store
         float best = 1e30f;
         int best_n = p->nwg;
         const int cands[] = {1, cus / 4, cus / 2, cus};
         for (int c : cands) {
             if (c < 1 || c > max_wg) continue;
-            if (p->corr == RPR_CORR_RANDNET && c > 1 && c - 1 > p->M && c != cus) continue;
+            if (p->M > 0 && c > 1 && c - 1 > p->M && c != cus) continue;
             float ms = 0.f;
             hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
             RPR_TRY(launch_chain<T>(a, p->shG, c, st));
@@ -577,8 +623,10 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     if (!opt) return fail(RPR_ERR_INVALID_ARG, "opt is NULL");
     if (opt->precision != RPR_FP64 && opt->precision != RPR_MIXED)
         return fail(RPR_ERR_INVALID_ARG, "opt.precision must be RPR_FP64 or RPR_MIXED");
-    if (opt->correction != RPR_CORR_RANDNET && opt->correction != RPR_CORR_PARAREAL)
-        return fail(RPR_ERR_INVALID_ARG, "opt.correction must be RPR_CORR_RANDNET or RPR_CORR_PARAREAL");
+    if (opt->correction != RPR_CORR_RANDNET && opt->correction != RPR_CORR_PARAREAL &&
+        opt->correction != RPR_CORR_RANDNET_NN)
+        return fail(RPR_ERR_INVALID_ARG,
+                    "opt.correction must be RPR_CORR_RANDNET, RPR_CORR_PARAREAL or RPR_CORR_RANDNET_NN");
     if (opt->k_max < 0 || opt->k_max > N) return fail(RPR_ERR_INVALID_ARG, "opt.k_max must be in [0, N]");
     if (opt->poll_every < 0) return fail(RPR_ERR_INVALID_ARG, "opt.poll_every must be >= 0");
     if (opt->features < RPR_FEAT_AUTO || opt->features > RPR_FEAT_BF16)
@@ -586,7 +634,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     if (opt->autotune != 0 && opt->autotune != 1) return fail(RPR_ERR_INVALID_ARG, "opt.autotune must be 0 or 1");
     if (opt->graph != 0 && opt->graph != 1) return fail(RPR_ERR_INVALID_ARG, "opt.graph must be 0 or 1");
     if (opt->reserved != 0) return fail(RPR_ERR_INVALID_ARG, "opt.reserved must be 0");
-    const bool use_net = opt->correction == RPR_CORR_RANDNET;
+    const bool use_net = opt->correction == RPR_CORR_RANDNET || opt->correction == RPR_CORR_RANDNET_NN;
     if (use_net) {
         if (!net) return fail(RPR_ERR_INVALID_ARG, "net is NULL");
         if (net->M < 1 || net->M > 512) return fail(RPR_ERR_INVALID_ARG, "net.M must be in [1, 512]");
@@ -595,6 +643,9 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         if (!(net->lambda > 0) || !is_finite(net->lambda)) return fail(RPR_ERR_INVALID_ARG, "net.lambda must be > 0");
         if (!is_finite(net->input_scale)) return fail(RPR_ERR_INVALID_ARG, "net.input_scale must be finite");
         if ((A == nullptr) != (zeta == nullptr)) return fail(RPR_ERR_INVALID_ARG, "pass both A and zeta, or neither");
+        if (net->reserved != 0) return fail(RPR_ERR_INVALID_ARG, "net.reserved must be 0");
+        if (opt->correction == RPR_CORR_RANDNET_NN && (net->m_nn < 1 || net->m_nn > NN_MAX))
+            return fail(RPR_ERR_INVALID_ARG, "net.m_nn must be in [1, 32]");
     }
     RPR_TRY(check_device());
 
@@ -619,6 +670,8 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         p->act = net->activation;
         p->lambda = net->lambda;
         p->scale_opt = net->input_scale;
+        p->nn = opt->correction == RPR_CORR_RANDNET_NN;
+        p->m_nn = p->nn ? net->m_nn : 0;
     }
     const double T = (tN - t0) / N;
     p->dtF = T / (double)F->steps;
@@ -642,7 +695,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         }
         if (tiled) sh = tiled_shape(g, p->esz);
     }
-    if (use_net && ((size_t)p->M * 32 + 32 * 33) * sizeof(double) > kMaxLds) {
+    if (p->corr == RPR_CORR_RANDNET && ((size_t)p->M * 32 + 32 * 33) * sizeof(double) > kMaxLds) {
         delete p;
         return fail(RPR_ERR_UNSUPPORTED, "net.M too large for the ridge solve");
     }
@@ -685,6 +738,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         // the autotuner tries grids of up to one work-group per CU
         const int hmax = p->autotune ? std::max(p->nwg, std::min(cus, max_wg)) : p->nwg;
         st = dalloc(&p->hpart, (size_t)hmax * p->M);
+        if (st == RPR_OK && p->nn) st = dalloc(&p->dpart, (size_t)hmax * p->n_cap);
         if (st != RPR_OK) {
             const std::string keep = g_err;
             plan_free(p);
@@ -735,7 +789,8 @@ static ChainArgs<T> chain_args(rpr_plan *p, double s)
     a.ctrl = p->ctrl;
     a.L_hist = p->L_hist;
     a.chg_hist = p->chg_hist;
-    a.mode = p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+    a.mode = chain_mode(p);
+    nn_args<T>(p, a);
     return a;
 }
 
@@ -769,7 +824,7 @@ static rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStr
     ChainArgs<T> a = chain_args<T>(p, s);
     a.mode = CHAIN_SWEEP;
     RPR_TRY(launch_chain<T>(a, p->shG, 1, st));
-    a.mode = p->corr == RPR_CORR_RANDNET ? CHAIN_RANDNET : CHAIN_PARAREAL;
+    a.mode = chain_mode(p);
     *out = a;
     return RPR_OK;
 }
@@ -778,7 +833,7 @@ static rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStr
 template <typename T>
 static rpr_status phase_model(rpr_plan *p, double inv_s, hipStream_t st)
 {
-    if (p->corr != RPR_CORR_RANDNET) return RPR_OK;
+    if (p->corr != RPR_CORR_RANDNET && !p->nn) return RPR_OK;
     const int N = p->N, d = p->g.d, M = p->M;
     T *U = static_cast<T *>(p->U), *Fv = static_cast<T *>(p->Fv), *Gc = static_cast<T *>(p->Gc);
     T *X = static_cast<T *>(p->X), *Y = static_cast<T *>(p->Y);
@@ -787,6 +842,9 @@ static rpr_status phase_model(rpr_plan *p, double inv_s, hipStream_t st)
         RPR_TRY(launch_features_bf16<T>(N, M, d, p->act, inv_s, p->Ab, p->zeta, X, p->Phi, p->fpart32, p->nrows, st));
     else
         RPR_TRY(launch_features<T>(N, M, d, p->act, inv_s, p->A, p->zeta, X, p->Phi, p->fpart, p->nrows, st));
+    if (p->nn)
+        return launch_nn_append<T>(N, d, M, X, Y, p->Phi, p->ok, p->nrows, p->ctrl, static_cast<T *>(p->Xs),
+                                   static_cast<T *>(p->Ys), p->Ps, p->oks, p->n_cap, st);
     RPR_TRY(launch_stats<T>(N, M, d, p->Phi, Y, p->ok, p->Gm, p->Bm, p->nrows, st));
     RPR_TRY(launch_ridge_solve(M, d, p->Gm, p->lambda, p->Lf, p->Lt, p->W, p->Bm, p->cfail, &p->ctrl->chol_fail,
                                &p->ctrl->done, st));
@@ -931,6 +989,8 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
     if (n_inst < 1) return fail(RPR_ERR_INVALID_ARG, "n_inst must be >= 1");
     if (!h || !d || !t0 || !tN || !N || !F || !G || !tol || !opt)
         return fail(RPR_ERR_INVALID_ARG, "batch arrays must not be NULL");
+    if (opt->correction == RPR_CORR_RANDNET_NN)
+        return fail(RPR_ERR_UNSUPPORTED, "the nearest-neighbour correction serves single plans only");
     for (int b = 1; b < n_inst; ++b)
         if (h[b].kind != h[0].kind) return fail(RPR_ERR_INVALID_ARG, "all instances of a batch need the same rhs kind");
     rpr_plan *p = new rpr_plan();

@@ -7,7 +7,10 @@
 
 namespace rpr {
 
-enum { CHAIN_SWEEP = 0, CHAIN_RANDNET = 1, CHAIN_PARAREAL = 2 };
+enum { CHAIN_SWEEP = 0, CHAIN_RANDNET = 1, CHAIN_PARAREAL = 2, CHAIN_RANDNET_NN = 3 };
+
+// Largest number of nearest neighbours of the refit-per-prediction mode.
+constexpr int NN_MAX = 32;
 
 template <typename T>
 struct ChainArgs {
@@ -29,6 +32,17 @@ struct ChainArgs {
     TiledWork<T> gw;           // work arrays of the tiled coarse solver (d values each)
     const double *A, *zeta, *W;
     const double *At;          // d x M: A^T
+    // nearest-neighbour mode: the store of every pair so far (rows 0 ..
+    // ctrl->nn_rows + *nrows; the last *nrows are this iteration's)
+    int m_nn;                  // neighbours per prediction
+    double lambda;             // ridge penalty
+    const T *Xs, *Ys;          // n_cap x d: inputs and targets
+    const double *Ps;          // n_cap x M: features of the inputs
+    const int *oks;            // n_cap: 1 if the pair is finite
+    const int *nrows;          // pairs added this iteration
+    int n_cap;                 // rows of the store
+    double *dpart;             // grid x n_cap: per-work-group partial squared distances
+    double *dist;              // n_cap: squared distances of the current slot input
     double *part;              // (N+1) x grid: per-work-group change maxima
     Ctrl *ctrl;
     int *L_hist;               // (N+1)

@@ -149,6 +149,192 @@ __device__ __forceinline__ void hidden_finish(const ChainArgs<T> &a, const int h
     }
 }
 
+// Nearest-neighbour mode (eq. "randnet"; App. B): squared Euclidean
+// distances of a slot state x to the n stored inputs, split over the
+// work-groups by columns like the hidden layer.  dist_partial: the owner of
+// columns j0 .. j1 sums (Xs[l][j] - x[j])^2 over them for every stored row l;
+// after the grid barrier dist_finish: the owner of row l adds the partial
+// sums in work-group order.  Doubles in both precisions.
+template <typename T>
+__device__ __forceinline__ void dist_partial(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
+                                             const int j1, const int wg, const int n)
+{
+    const int t = threadIdx.x, B = blockDim.x, d = a.g.d;
+    const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
+    const int lane = t & 63, wv = t >> 6;
+    if (wv >= nw) return;
+    constexpr int RB = 8, JB = 2;  // rows per wavefront and pass, columns per lane and load batch
+    for (int l0 = wv * RB; l0 < n; l0 += nw * RB) {
+        double acc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+        for (int jb = j0; jb < j1; jb += WL * JB) {
+            double xv[JB], v[RB][JB];
+#pragma unroll
+            for (int q = 0; q < JB; ++q) {
+                const int j = jb + q * WL + lane;
+                xv[q] = j < j1 ? double(x[j]) : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int q = 0; q < JB; ++q) {
+                    const int j = jb + q * WL + lane, l = l0 + r;
+                    v[r][q] = (l < n && j < j1) ? double(a.Xs[(size_t)l * d + j]) : xv[q];
+                }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int q = 0; q < JB; ++q) {
+                    const double e = v[r][q] - xv[q];
+                    acc[r] = fma(e, e, acc[r]);
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            double z = acc[r];
+            for (int off = 32; off > 0; off >>= 1) {
+                const double o = __shfl_down(z, off, 64);
+                if (lane + off < WL) z += o;
+            }
+            if (lane == 0 && l0 + r < n) a.dpart[(size_t)wg * a.n_cap + l0 + r] = z;
+        }
+    }
+}
+
+// Rows l = hw, hw + nh, ... of the distance vector: one wavefront per row.
+template <typename T>
+__device__ __forceinline__ void dist_finish(const ChainArgs<T> &a, const int hw, const int nh, const int nwg,
+                                            const int n)
+{
+    const int t = threadIdx.x, B = blockDim.x;
+    const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
+    const int lane = t & 63, wv = t >> 6;
+    for (int l = hw + nh * wv; wv < nw && l < n; l += nh * nw) {
+        double z = 0.0;
+        for (int w = lane; w < nwg; w += WL) z += a.dpart[(size_t)w * a.n_cap + l];
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(z, off, 64);
+            if (lane + off < WL) z += o;
+        }
+        if (lane == 0) a.dist[l] = z;
+    }
+}
+
+// (distance, row) of the lesser of two candidates; equal distances go to the
+// lower row.
+__device__ __forceinline__ void nn_min(double &bd, int &bi, const double od, const int oi)
+{
+    if (od < bd || (od == bd && oi < bi)) {
+        bd = od;
+        bi = oi;
+    }
+}
+
+// The refit of one prediction (eq. "randnet", Alg. "RandNets training
+// procedure"), by wavefront 0 of every work-group (the same result in each,
+// so no barrier is needed): the m nearest finite stored pairs of the current
+// slot input (distances from dist_finish, NaN read as +inf, ties to the lower
+// row), then the dual ridge readout on them,
+//   K = Phi~ Phi~^T + lambda I (m x m),  alpha = K^-1 Phi~ phi(x),
+// so that the correction W^T phi(x) = Y~^T alpha.  sel / alpha (LDS, m
+// entries, and sel[NN_MAX] the count) receive the rows and weights; K is LDS
+// scratch of NN_MAX^2 doubles.  Returns m, or 0 when there is no pair or K
+// is not positive definite (no correction; work-group 0 counts the failure).
+template <typename T>
+__device__ __forceinline__ int nn_refit(const ChainArgs<T> &a, const int n, const int wg, int *sel, double *alpha,
+                                        double *K)
+{
+    int &m_sh = sel[NN_MAX];
+    const int t = threadIdx.x, B = blockDim.x;
+    const int WL = B >= 64 ? 64 : B;
+    const int lane = t & 63;
+    if (t < 64) {
+        int m = a.m_nn < a.ctrl->rows_used ? a.m_nn : a.ctrl->rows_used;
+        // selection in (distance, row) order, one pair per round
+        double pd = -INFINITY;
+        int pi = -1;
+        for (int r = 0; r < m; ++r) {
+            double bd = INFINITY;
+            int bi = 0x7fffffff;
+            for (int l = lane; l < n; l += WL) {
+                if (!a.oks[l]) continue;
+                double dl = a.dist[l];
+                if (dl != dl) dl = INFINITY;
+                if (dl > pd || (dl == pd && l > pi)) nn_min(bd, bi, dl, l);
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double od = __shfl_xor(bd, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if ((lane ^ off) < WL) nn_min(bd, bi, od, oi);
+            }
+            if (bi == 0x7fffffff) {  // fewer finite pairs than counted: cannot happen
+                m = r;
+                break;
+            }
+            if (lane == 0) sel[r] = bi;
+            pd = bd;
+            pi = bi;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // K (upper triangle) and the right-hand side Phi~ phi
+        for (int p = 0; p < m; ++p) {
+            const double *Pp = a.Ps + (size_t)sel[p] * a.M;
+            for (int q = p; q <= m; ++q) {
+                const double *Pq = q < m ? a.Ps + (size_t)sel[q] * a.M : a.phi;
+                double z = 0.0;
+                for (int c = lane; c < a.M; c += WL) z = fma(Pp[c], Pq[c], z);
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double o = __shfl_xor(z, off, 64);
+                    if ((lane ^ off) < WL) z += o;
+                }
+                if (lane == 0) {
+                    if (q < m) K[p * NN_MAX + q] = z + (p == q ? a.lambda : 0.0);
+                    else alpha[p] = z;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // Cholesky K = L L^T (lower triangle, in place) and alpha = K^-1 b
+        if (lane == 0) {
+            bool spd = true;
+            for (int j = 0; j < m && spd; ++j) {
+                double s = K[j * NN_MAX + j];
+                for (int k = 0; k < j; ++k) s -= K[j * NN_MAX + k] * K[j * NN_MAX + k];
+                if (!(s > 0.0)) {
+                    spd = false;
+                    break;
+                }
+                const double ljj = sqrt(s);
+                K[j * NN_MAX + j] = ljj;
+                for (int i = j + 1; i < m; ++i) {
+                    double v = K[j * NN_MAX + i];  // upper triangle holds K[j][i] = K[i][j]
+                    for (int k = 0; k < j; ++k) v -= K[i * NN_MAX + k] * K[j * NN_MAX + k];
+                    K[i * NN_MAX + j] = v / ljj;
+                }
+            }
+            if (spd) {
+                for (int i = 0; i < m; ++i) {
+                    double v = alpha[i];
+                    for (int k = 0; k < i; ++k) v -= K[i * NN_MAX + k] * alpha[k];
+                    alpha[i] = v / K[i * NN_MAX + i];
+                }
+                for (int i = m - 1; i >= 0; --i) {
+                    double v = alpha[i];
+                    for (int k = i + 1; k < m; ++k) v -= K[k * NN_MAX + i] * alpha[k];
+                    alpha[i] = v / K[i * NN_MAX + i];
+                }
+            } else {
+                if (wg == 0) atomicAdd(&a.ctrl->chol_fail, 1);
+                m = 0;
+            }
+            m_sh = m;
+        }
+    }
+    __syncthreads();
+    return m_sh;
+}
+
 // Coarse propagation src -> dst (and dst2) of a state too large for one
 // work-group, by the whole grid: the tiles of each RK stage are spread over
 // the work-groups, a grid barrier separates the stages.
@@ -209,12 +395,16 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     const int chunk = (d + nwg - 1) / nwg;
     const int j0 = wg * chunk, j1 = min(d, j0 + chunk);
 
-    const bool net = a.mode == CHAIN_RANDNET;
+    const bool nn = a.mode == CHAIN_RANDNET_NN;
+    const bool net = a.mode == CHAIN_RANDNET || nn;
+    // stored pairs (this iteration's included)
+    const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
     // exact slot, and the hidden-layer partial sums of its columns
     for (int j = j0 + t; j < j1; j += B) a.U[(size_t)(L + 1) * d + j] = a.Fv[(size_t)(L + 1) * d + j];
     if (net && L + 2 <= N) {
         __syncthreads();
         hidden_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, scratch);
+        if (nn) dist_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, n_store);
     }
     sync();
 
@@ -224,12 +414,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
         if constexpr (TILED) {
             tiled_coarse<KIND, T>(a, x, a.gtmp, (T *)nullptr, wg, nwg, sync, lds);
             if (net) hidden_finish(a, wg, nwg, nwg);
+            if (nn) dist_finish(a, wg, nwg, nwg, n_store);
         } else {
             if (wg == 0) {
                 slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG, x, a.gtmp, lds);
                 __syncthreads();
             }
             if (net && (wg > 0 || nwg == 1)) hidden_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg);
+            if (nn && (wg > 0 || nwg == 1))
+                dist_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg, n_store);
         }
         sync();
 
@@ -238,7 +431,28 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
         const T *Fvi = a.Fv + (size_t)i * d;
         T *Ui = a.U + (size_t)i * d;
         T *Gci = a.Gc + (size_t)i * d;
-        if (net) {
+        if (nn) {
+            // refit on the nearest stored pairs, then U_i = G + Y~^T alpha on
+            // columns j0 .. j1
+            double *K = scratch;                          // NN_MAX x NN_MAX
+            double *alpha = scratch + NN_MAX * NN_MAX;    // NN_MAX
+            int *sel = reinterpret_cast<int *>(alpha + NN_MAX);
+            const int m = nn_refit(a, n_store, wg, sel, alpha, K);
+            for (int j = j0 + t; j < j1; j += B) {
+                double c = 0.0;
+                for (int r = 0; r < m; ++r) c = fma(alpha[r], double(a.Ys[(size_t)sel[r] * d + j]), c);
+                const T gv = a.gtmp[j];
+                const T unew = T(double(gv) + c);
+                emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
+                Ui[j] = unew;
+                Gci[j] = gv;
+            }
+            if (i < N) {
+                __syncthreads();
+                hidden_partial(a, Ui, j0, j1, wg, scratch);
+                dist_partial(a, Ui, j0, j1, wg, n_store);
+            }
+        } else if (net) {
             // readout W^T phi on columns j0 .. j1: wavefront w sums the neurons
             // m = w, w + nw, ... for 2 tiles of 64 columns at a time, then
             // wavefront q < 2 adds the nw partial sums of tile q in order
@@ -338,6 +552,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
         const int k = ctrl->k + 1;
         ctrl->k = k;
         ctrl->L = Lnew;
+        if (nn) ctrl->nn_rows = n_store;
         if (Lnew >= N || k >= a.k_max) ctrl->done = 1;  // converged, or iteration cap reached
         if (a.L_hist) a.L_hist[k] = Lnew;
         if (a.chg_hist) a.chg_hist[k] = chg;

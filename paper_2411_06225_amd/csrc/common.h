@@ -281,7 +281,8 @@ struct Ctrl {
     int rows_used;   // finite pairs in the readout
     int nonfinite;   // dropped pairs
     int chol_fail;   // failed ridge factorisations
-    int pad[2];
+    int nn_rows;     // pairs in the nearest-neighbour store (finite or not)
+    int pad;
 };
 
 }  // namespace rpr

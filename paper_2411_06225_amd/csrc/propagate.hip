@@ -4,7 +4,6 @@
 // indexed by slot; with a control block the work-groups of final slots exit
 // at once, so the same launch serves every Parareal iteration.
 #include "slotprop.h"
-#include "tiledprop.h"
 
 namespace rpr {
 
@@ -58,62 +57,6 @@ rpr_status launch_propagate_kind(const Geom &g, const OnchipShape &sh, int metho
     PropLauncher<KIND, T> L{g, sh, method, steps, dt, n, in, out, ctrl, st};
     return visit_shape_kind<KIND, T>(g, sh, L);
 }
-
-// ------------------------------------------------------------ tiled form --
-// One stage of the propagation of n slot states too large for one
-// work-group: block (tile, b) updates one tile of slot b (in + b d ->
-// out + b d, work arrays at b d).  Blocks of final slots exit at once.
-template <int KIND, typename T, int STAGE>
-__global__ __launch_bounds__(TT_THREADS) void k_prop_tiled(Geom g, int method, long long step, long long steps,
-                                                           double dt, const T *__restrict__ in, T *__restrict__ out,
-                                                           TiledWork<T> w, const int *__restrict__ ctrl)
-{
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int b = blockIdx.y;
-    if (ctrl != nullptr && (ctrl[2] != 0 || b < ctrl[0])) return;
-    const size_t off = (size_t)b * g.d;
-    const TiledWork<T> wb{w.u + off, w.acc ? w.acc + off : nullptr, w.ya + off, w.yb ? w.yb + off : nullptr,
-                          w.cmp ? w.cmp + off : nullptr};
-    const StageIO<T> io = stage_io<T>(method, STAGE, step, steps, in + off, out + off, nullptr, wb);
-    stage_tile<KIND, T, STAGE>(g, blockIdx.x, dt, io, reinterpret_cast<T *>(lds_raw));
-}
-
-template <int KIND, typename T>
-rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
-                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st)
-{
-    if constexpr (KIND == RPR_BURGERS1D) {
-        return fail(RPR_ERR_UNSUPPORTED, "the tiled propagator serves 2D grids only");
-    } else {
-        if (n <= 0) return RPR_OK;
-        if (n > 65535) return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 65535 states per launch");
-        const dim3 grid((unsigned)tiles_of(g), (unsigned)n);
-        const size_t lds = tiled_lds(g, sizeof(T));
-        const long long ns = (long long)steps;
-        for (long long s = 0; s < ns; ++s) {
-            if (method == RPR_RK4) {
-                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 1>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
-                                   in, out, w, ctrl);
-                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 2>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
-                                   in, out, w, ctrl);
-                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 3>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
-                                   in, out, w, ctrl);
-                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 4>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
-                                   in, out, w, ctrl);
-            } else {
-                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 0>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
-                                   in, out, w, ctrl);
-            }
-            RPR_HIP(hipGetLastError());
-        }
-        return RPR_OK;
-    }
-}
-
-template rpr_status launch_prop_tiled_kind<RPR_KIND, RPR_REAL>(const Geom &, int, int64_t, double, int,
-                                                                const RPR_REAL *, RPR_REAL *,
-                                                                const TiledWork<RPR_REAL> &, const int *,
-                                                                hipStream_t);
 
 // ------------------------------------------------------- persistent batch --
 template <int KIND, typename T, int CPT, bool DBUF>

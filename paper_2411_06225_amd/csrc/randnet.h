@@ -54,6 +54,14 @@ template <typename T>
 rpr_status launch_pairs(int N, int d, const T *U, const T *Fv, const T *Gc, T *X, T *Y, int *ok, int *nrows,
                         Ctrl *ctrl, hipStream_t st);
 
+// Nearest-neighbour store: this iteration's pairs (rows r < *nrows of X, Y,
+// Phi and ok) are copied to rows ctrl->nn_rows + r of Xs, Ys, Ps and oks
+// (n_cap rows).  The chain of the same iteration advances ctrl->nn_rows.
+template <typename T>
+rpr_status launch_nn_append(int N, int d, int M, const T *X, const T *Y, const double *Phi, const int *ok,
+                            const int *nrows, const Ctrl *ctrl, T *Xs, T *Ys, double *Ps, int *oks, int n_cap,
+                            hipStream_t st);
+
 // out[k] = U(-1, 1) from counter first + k (SplitMix64).
 rpr_status launch_uniform(uint64_t seed, uint64_t first, int64_t n, double *out, hipStream_t st);
 

@@ -699,4 +699,41 @@ template rpr_status launch_pairs<double>(int, int, const double *, const double 
 template rpr_status launch_pairs<float>(int, int, const float *, const float *, const float *, float *,
                                         float *, int *, int *, Ctrl *, hipStream_t);
 
+// ------------------------------------------------- nearest-neighbour store --
+template <typename T>
+__global__ __launch_bounds__(256) void k_nn_append(int d, int M, const T *__restrict__ X, const T *__restrict__ Y,
+                                                   const double *__restrict__ Phi, const int *__restrict__ ok,
+                                                   const int *__restrict__ nrows, const Ctrl *__restrict__ ctrl,
+                                                   T *__restrict__ Xs, T *__restrict__ Ys, double *__restrict__ Ps,
+                                                   int *__restrict__ oks, int n_cap)
+{
+    const int r = blockIdx.x;
+    if (r >= *nrows) return;
+    const int row = ctrl->nn_rows + r;
+    if (row >= n_cap) return;  // the store holds N k_max rows: cannot happen
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        Xs[(size_t)row * d + j] = X[(size_t)r * d + j];
+        Ys[(size_t)row * d + j] = Y[(size_t)r * d + j];
+    }
+    for (int m = threadIdx.x; m < M; m += blockDim.x) Ps[(size_t)row * M + m] = Phi[(size_t)r * M + m];
+    if (threadIdx.x == 0) oks[row] = ok[r];
+}
+
+template <typename T>
+rpr_status launch_nn_append(int N, int d, int M, const T *X, const T *Y, const double *Phi, const int *ok,
+                            const int *nrows, const Ctrl *ctrl, T *Xs, T *Ys, double *Ps, int *oks, int n_cap,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_nn_append<T>, dim3(N), dim3(256), 0, st, d, M, X, Y, Phi, ok, nrows, ctrl, Xs, Ys, Ps, oks,
+                       n_cap);
+    RPR_HIP(hipGetLastError());
+    return RPR_OK;
+}
+template rpr_status launch_nn_append<double>(int, int, int, const double *, const double *, const double *,
+                                             const int *, const int *, const Ctrl *, double *, double *, double *,
+                                             int *, int, hipStream_t);
+template rpr_status launch_nn_append<float>(int, int, int, const float *, const float *, const double *, const int *,
+                                            const int *, const Ctrl *, float *, float *, double *, int *, int,
+                                            hipStream_t);
+
 }  // namespace rpr

@@ -1,0 +1,68 @@
+// tiled.hip -- the propagators F and G over one slice (Sec. 2) for slot
+// states too large for one work-group: one launch per RK stage over the
+// 64 x 16-cell tiles of every slot state (tiledprop.h).
+#include "tiledprop.h"
+
+namespace rpr {
+
+// ------------------------------------------------------------ tiled form --
+// One stage of the propagation of n slot states too large for one
+// work-group: a block updates one tile of slot b (in + b d -> out + b d,
+// work arrays at b d), the pair taken from the block id by tile_of_block.
+// Blocks of final slots exit at once.
+template <int KIND, typename T, int STAGE>
+__global__ __launch_bounds__(TT_THREADS) void k_prop_tiled(Geom g, int method, long long step, long long steps,
+                                                           double dt, int n, const T *__restrict__ in,
+                                                           T *__restrict__ out, TiledWork<T> w,
+                                                           const int *__restrict__ ctrl)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int tile, b;
+    tile_of_block((int)blockIdx.x, tiles_of(g), n, tile, b);
+    if (ctrl != nullptr && (ctrl[2] != 0 || b < ctrl[0])) return;
+    const size_t off = (size_t)b * g.d;
+    const TiledWork<T> wb{w.u + off, w.acc ? w.acc + off : nullptr, w.ya + off, w.yb ? w.yb + off : nullptr,
+                          w.cmp ? w.cmp + off : nullptr};
+    const StageIO<T> io = stage_io<T>(method, STAGE, step, steps, in + off, out + off, nullptr, wb);
+    stage_tile<KIND, T, STAGE>(g, tile, dt, io, reinterpret_cast<T *>(lds_raw));
+}
+
+template <int KIND, typename T>
+rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
+                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st)
+{
+    if constexpr (KIND == RPR_BURGERS1D) {
+        return fail(RPR_ERR_UNSUPPORTED, "the tiled propagator serves 2D grids only");
+    } else {
+        if (n <= 0) return RPR_OK;
+        if ((long long)tiles_of(g) * n > 0x7fffffffLL)
+            return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 2^31 tiles per launch");
+        const dim3 grid((unsigned)(tiles_of(g) * n));
+        const size_t lds = tiled_lds(g, sizeof(T));
+        const long long ns = (long long)steps;
+        for (long long s = 0; s < ns; ++s) {
+            if (method == RPR_RK4) {
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 1>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   n, in, out, w, ctrl);
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 2>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   n, in, out, w, ctrl);
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 3>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   n, in, out, w, ctrl);
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 4>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   n, in, out, w, ctrl);
+            } else {
+                hipLaunchKernelGGL((k_prop_tiled<KIND, T, 0>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,
+                                   n, in, out, w, ctrl);
+            }
+            RPR_HIP(hipGetLastError());
+        }
+        return RPR_OK;
+    }
+}
+
+template rpr_status launch_prop_tiled_kind<RPR_KIND, RPR_REAL>(const Geom &, int, int64_t, double, int,
+                                                                const RPR_REAL *, RPR_REAL *,
+                                                                const TiledWork<RPR_REAL> &, const int *,
+                                                                hipStream_t);
+
+}  // namespace rpr

@@ -22,6 +22,27 @@ constexpr int TT_RPT = TT_X * TT_Y / TT_THREADS;  // rows per thread
 __host__ __device__ inline int tiles_x(const Geom &g) { return (g.nx + TT_X - 1) / TT_X; }
 __host__ __device__ inline int tiles_of(const Geom &g) { return tiles_x(g) * ((g.ny + TT_Y - 1) / TT_Y); }
 
+// Work-group id -> (tile, slot state) of a one-dimensional launch over
+// tiles x n work-groups.  Work-groups go to the eight XCDs round robin
+// (id % 8), each XCD with its own L2: each XCD gets whole slot states, their
+// tiles in row-major order one after the other, so the halo rows and columns
+// a tile shares with its neighbours come through the same L2.  States beyond
+// the last multiple of 8 take the plain order.
+__device__ __forceinline__ void tile_of_block(const int id, const int tiles, const int n, int &tile, int &slot)
+{
+    constexpr int XCD = 8;
+    const int n8 = n / XCD * XCD, head = tiles * n8;
+    if (id < head) {
+        const int x = id % XCD, j = id / XCD;
+        slot = (j / tiles) * XCD + x;
+        tile = j % tiles;
+    } else {
+        const int r = id - head;
+        slot = n8 + r / tiles;
+        tile = r % tiles;
+    }
+}
+
 // LDS of one haloed tile (shallow water: twice, for the per-cell flux
 // quantities).
 __host__ __device__ inline size_t tiled_lds(const Geom &g, size_t elem)

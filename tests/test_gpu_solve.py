@@ -41,14 +41,14 @@ def gpu_solve(w, eps=None, corr=0, k_max=0, prec=0, seeded=False, u0=None, **opt
     return U.cpu().numpy(), info
 
 
-def orc_solve(orc, w, eps=None, corr=0, k_max=None, A=None, zeta=None, keep=False):
+def orc_solve(orc, w, eps=None, corr=0, k_max=None, A=None, zeta=None, keep=False, m_nn=4):
     pb = orc.problem(w.kind, w.nx, w.ny, w.domain, w.params)
     if A is None:
         A, zeta = W.random_weights(w)
     net = orc.Net(A, zeta, w.act, w.lam, 0.0)
     return orc.parareal(pb, W.initial_condition(w), N=w.N, t0=w.t0, tN=w.tN, F=w.F, G=w.G,
                         eps=w.eps if eps is None else eps, corr=corr, net=net, k_max=k_max,
-                        nthreads=8, keep_iterates=keep)
+                        m_nn=m_nn, nthreads=8, keep_iterates=keep)
 
 
 def assert_same_run(Ug, ig, Uo, io, N):
@@ -296,3 +296,97 @@ def test_mixed_precision_solve_stays_within_fp32_error_of_oracle(orc, w):
     err = np.abs(Ug - Uf).max() / np.abs(Uf).max()
     print("mixed K", ig["K"], "rel err vs FP64 serial fine %.2e" % err)
     assert err <= 1e-4
+
+
+# ---- nearest-neighbour correction (eq. "randnet"): refit per prediction ----
+def nn_refit_condition(orc, w, io, m_nn):
+    """Largest kappa_2(Phi~ Phi~^T + lambda I) over the predictions of the
+    oracle's run: the stored inputs are U_{i-1}^{k-1}, i = L_{k-1}+1..N, of
+    every iteration so far; the queries of iteration k are U_{i-1}^k,
+    i = L_{k-1}+2..N."""
+    A, zeta = W.random_weights(w)
+    s = 2.0 ** math.ceil(math.log2(max(1.0, np.abs(W.initial_condition(w)).max())))
+    net = orc.Net(A, zeta, w.act, w.lam, s)
+    store, kmax = [], 0.0
+    for k in range(1, io["K"] + 1):
+        L = io["L_hist"][k - 1]
+        store.append(io["U_iter"][k - 1][L:w.N])
+        P = np.concatenate(store)
+        for i in range(L + 2, w.N + 1):
+            q = io["U_iter"][k][i - 1]
+            m = min(m_nn, P.shape[0])
+            Phi = orc.features(net, P[orc.nearest(P, q, m)])
+            kmax = max(kmax, np.linalg.cond(Phi @ Phi.T + w.lam * np.eye(m)))
+    return kmax
+
+
+NN_CASES = [("burgers_small_m4", BURGERS_SMALL, 4), ("diffreact_24x20_m3", DR_RAGGED, 3),
+            ("diffreact_32x32_m4", DR_SMALL, 4), ("swe_16x16_m4", SWE_SMALL, 4)]
+
+
+@pytest.mark.parametrize("name,w,m_nn", NN_CASES, ids=[c[0] for c in NN_CASES])
+def test_nearest_neighbour_solve_matches_oracle(orc, name, w, m_nn):
+    """Same decisions as the oracle (K, L history, pairs) and the same
+    states up to the rounding of the refits: the chain's bound N 1e-12 plus
+    the forward error of an m x m Cholesky solve, 10 kappa 2^-53, with kappa
+    the worst refit matrix of the run."""
+    Ug, ig = gpu_solve(w, corr=rpr.RPR_CORR_RANDNET_NN, m_nn=m_nn)
+    Uo, io = orc_solve(orc, w, corr=2, m_nn=m_nn, keep=True)
+    assert ig["K"] == io["K"]
+    assert ig["L_hist"].tolist() == io["L_hist"].tolist()
+    assert ig["rows_used"] == io["rows_used"]
+    assert ig["chol_fail"] == 0
+    kappa = nn_refit_condition(orc, w, io, m_nn)
+    err = np.abs(Ug - Uo).max() / np.abs(Uo).max()
+    tol = max(w.N * 1e-12, 10 * kappa * 2.0 ** -53)
+    print(name, "K", ig["K"], "L", ig["L_hist"].tolist(), "kappa %.1e rel err %.2e tol %.1e" % (kappa, err, tol))
+    assert err <= tol
+
+
+def test_nearest_neighbour_tiled_plan_matches_oracle(orc):
+    w = SWE_SMALL
+    Ug, ig = gpu_solve(tiled(w), corr=rpr.RPR_CORR_RANDNET_NN, m_nn=4)
+    Uo, io = orc_solve(orc, w, corr=2, m_nn=4, keep=True)
+    assert ig["K"] == io["K"] and ig["L_hist"].tolist() == io["L_hist"].tolist()
+    tol = max(w.N * 1e-12, 10 * nn_refit_condition(orc, w, io, 4) * 2.0 ** -53)
+    assert np.abs(Ug - Uo).max() / np.abs(Uo).max() <= tol
+
+
+def test_nearest_neighbour_with_every_pair_equals_global_fit():
+    # With m_nn at least the number of stored pairs the refit uses every pair,
+    # and the dual form equals the global primal fit (push-through identity):
+    # N = 6 stores at most 6 + 5 = 11 pairs in two iterations; the second
+    # iterate still depends on the correction (only K = N would not).  With
+    # lambda = 1e-3 both forms are well conditioned (as in the oracle's pin).
+    w = W.small(W.BURGERS_D128, nx=32, N=6, tN=1.5, F=(4, 100), G=(1, 10), M=24, params=(0.02,), lam=1e-3)
+    Ug, ig = gpu_solve(w, eps=0.0, k_max=2)
+    Un, inn = gpu_solve(w, eps=0.0, k_max=2, corr=rpr.RPR_CORR_RANDNET_NN, m_nn=32)
+    Up, ip = gpu_solve(w, eps=0.0, k_max=2, corr=rpr.RPR_CORR_PARAREAL)
+    assert ig["K"] == inn["K"] == 2
+    scale = np.abs(Ug).max()
+    err = np.abs(Ug - Un).max() / scale
+    spread = np.abs(Ug - Up).max() / scale  # how much the correction matters here
+    print("nn(all) vs global rel err %.2e; global vs classical %.2e" % (err, spread))
+    assert spread > 1e-6
+    assert err <= 1e-8
+
+
+def test_nearest_neighbour_in_a_captured_graph(orc):
+    w = DR_RAGGED
+    Ug, ig = gpu_solve(w, corr=rpr.RPR_CORR_RANDNET_NN, m_nn=3, poll_every=2, graph=1)
+    Un, inn = gpu_solve(w, corr=rpr.RPR_CORR_RANDNET_NN, m_nn=3)
+    assert ig["K"] == inn["K"] and ig["L_hist"].tolist() == inn["L_hist"].tolist()
+    # one work-group in the graph against the grid: sums in another order
+    Uo, io = orc_solve(orc, w, corr=2, m_nn=3, keep=True)
+    tol = max(w.N * 1e-12, 10 * nn_refit_condition(orc, w, io, 3) * 2.0 ** -53)
+    assert np.abs(Ug - Uo).max() / np.abs(Uo).max() <= tol
+
+
+def test_nearest_neighbour_mixed_precision_converges(orc):
+    w = DR_SMALL
+    Ug, ig = gpu_solve(w, prec=rpr.RPR_MIXED, corr=rpr.RPR_CORR_RANDNET_NN, m_nn=4)
+    pb = orc.problem(w.kind, w.nx, w.ny, w.domain, w.params)
+    T = (w.tN - w.t0) / w.N
+    Uf = orc.serial_fine(pb, w.F[0], w.F[1], T / w.F[1], w.N, W.initial_condition(w))
+    assert ig["converged"] == 1
+    assert np.abs(Ug - Uf).max() / np.abs(Uf).max() <= 1e-4
