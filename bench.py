@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--gemm", action="store_true",
+                    help="only time the random-feature GEMMs at the workloads' shapes and a compute-bound one")
+    ap.add_argument("--robustness", action="store_true",
+                    help="only run the sweep over neighbour counts, neurons and weight draws (App. D)")
     ap.add_argument("--f-only", choices=["swe_192x192"], default=None,
                     help="only time the fine propagator of this workload in FP64 and FP32 (for counter runs)")
     return ap.parse_args()
@@ -105,6 +109,12 @@ def main():
     w = W.DIFFREACT_64
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.gemm:
+        print(json.dumps({"feature_gemm": gemm_demo(torch, rpr, dev)}))
+        return
+    if args.robustness:
+        print(json.dumps({"robustness": robustness_sweep(torch, rpr, W, dev)}))
+        return
     if args.f_only:
         wf = W.SWE_192
         cb = copy_bandwidth(torch, dev)
@@ -121,9 +131,9 @@ def main():
     u0 = torch.tensor(u0h, dtype=torch.float64, device=dev)
     T = (w.tN - w.t0) / w.N
 
-    def make_plan(prec, k_max=0):
+    def make_plan(prec, k_max=0, correction=rpr.RPR_CORR_RANDNET, m_nn=4):
         return rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
-                        A=A, zeta=zeta, precision=prec, correction=rpr.RPR_CORR_RANDNET, autotune=1, k_max=k_max)
+                        A=A, zeta=zeta, precision=prec, correction=correction, autotune=1, k_max=k_max, m_nn=m_nn)
 
     def timed_solves(plan, steps, warmup):
         U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
@@ -236,6 +246,16 @@ def main():
         t32 = time_to_tau(rpr.RPR_MIXED, tau, minfo["K"])
         out["time_to_tau"] = {"tau": tau, "fp64": t64, "mixed": t32,
                               "fp64_over_mixed": (t64["s"] / t32["s"]) if t64["s"] and t32["s"] else None}
+        # the correction of the paper's experiments: a refit per prediction on
+        # the m = 4 nearest stored pairs
+        nn = {"m_nn": 4}
+        for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
+            pn = make_plan(prec, correction=rpr.RPR_CORR_RANDNET_NN)
+            tn, Un = timed_solves(pn, 2, 1)
+            nn[name] = {"ms_per_solve": tn * 1e3, "K": pn.info()["K"],
+                        "E_vs_fp64_serial_fine": float((Un[1:] - Uf[1:]).abs().amax(dim=1).mean())}
+            pn.close()
+        out["nearest_neighbour"] = nn
     plan.close()
 
     if args.copy_calibration:
@@ -329,6 +349,118 @@ def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
             "frac_of_copy": achieved / copy_bw if copy_bw else None,
             "launch": {"slots": w.N, "steps": steps, "ms_per_step": sec * 1e3 / steps,
                        "bytes_per_dof_step": TILED_ACCESSES_PER_DOF_STEP[esz] * esz}}
+
+
+BF16_MFMA_PEAK = 2.5e15  # MI355X dense bf16 matrix FLOP/s (AMD specification)
+
+
+def gemm_demo(torch, rpr, dev, reps=5):
+    """The random-feature GEMM Z = (X / s) A^T (eq. "HA"; n rows, M neurons,
+    K = d) through rpr_randnet_features_bf16 (split bfloat16, six MFMA
+    products per output) and rpr_randnet_features (FP64), at the shapes of
+    the diffusion-reaction and shallow-water workloads and at a compute-bound
+    shape.  Times are whole calls (weight splitting and workspace included;
+    kernel times are in the profiles); 'useful' counts 2 n M d FLOP, 'mfma'
+    the 6 x 2 n M d the matrix cores execute."""
+    res = []
+    for n, M, d in ((64, 200, 8192), (256, 300, 110592), (512, 512, 32768), (1024, 512, 65536)):
+        g = torch.Generator(device="cpu").manual_seed(n + M + d)
+        A = (torch.rand((M, d), generator=g, dtype=torch.float64) * 2 - 1).to(dev)
+        z = (torch.rand((M,), generator=g, dtype=torch.float64) * 2 - 1).to(dev)
+        X64 = (torch.rand((n, d), generator=g, dtype=torch.float64) * 2 - 1).to(dev)
+        X32 = X64.float()
+        Phi = torch.empty((n, M), dtype=torch.float64, device=dev)
+        row = {"n": n, "M": M, "d": d}
+        for name, fn, X in (("bf16_split", rpr.rpr_randnet_features_bf16, X32),
+                            ("fp64", rpr.rpr_randnet_features, X64)):
+            fn(M, d, n, 1, 1.0, A, z, X, Phi)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(reps):
+                fn(M, d, n, 1, 1.0, A, z, X, Phi)
+            ev[1].record()
+            torch.cuda.synchronize()
+            sec = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+            useful = 2.0 * n * M * d
+            r = {"ms": sec * 1e3, "useful_TFLOPs": useful / sec / 1e12}
+            if name == "bf16_split":
+                r["mfma_TFLOPs"] = 6 * useful / sec / 1e12
+                r["mfma_frac_of_peak"] = 6 * useful / sec / BF16_MFMA_PEAK
+            else:
+                r["frac_of_fp64_peak"] = useful / sec / FP64_VECTOR_PEAK
+            row[name] = r
+        res.append(row)
+        print(f"gemm n={n} M={M} d={d}: bf16 {row['bf16_split']['ms']:.3f} ms, fp64 {row['fp64']['ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+        del A, X64, X32
+    return res
+
+
+def robustness_sweep(torch, rpr, W, dev, n_seeds=10, ms=(2, 3, 4, 6, 8, 12, 16, 20),
+                     Ms=(20, 50, 100, 200, 300, 500)):
+    """Iterations to convergence K of RandNet-Parareal with the per-prediction
+    refit on the m nearest pairs (eq. "randnet"), over neighbour counts m,
+    neuron counts M and independent draws of the weights A, zeta: the study
+    of App. D, on a Burgers system with d = 128 and a diffusion-reaction
+    system with d = 722 (19 x 19 cells, two species).  Every (draw, m, M)
+    combination is one instance of one batch plan (same initial state, its
+    own weights), so each system is a single batched solve.  Returns, per
+    system, the histograms of K by m and by M, and K of classical Parareal
+    on the same problem for reference.  Progress goes to stderr."""
+    from collections import Counter
+
+    def hist(c):
+        return dict(sorted(c.items(), key=lambda kv: int(kv[0]) if kv[0].isdigit() else 1 << 30))
+
+    systems = {
+        "burgers_d128": W.BURGERS_D128_STABLE,
+        "diffreact_19x19": W.small(W.DIFFREACT_64, nx=19, ny=19, F=(4, 200), G=(1, 4)),
+    }
+    out = {}
+    for name, w in systems.items():
+        u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
+        h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+        combos, problems = [], []
+        for sd in range(n_seeds):
+            for M in Ms:
+                wM = w.replace(M=M)
+                A, z = W.random_weights(wM, seed=1000 + sd)
+                for m in ms:
+                    combos.append((sd, m, M))
+                    problems.append(dict(h=h, d=w.d, t0=w.t0, tN=w.tN, N=w.N, F=w.F, G=w.G, M=M, activation=w.act,
+                                         lam=w.lam, A=A, zeta=z, m_nn=m))
+        k_max = min(w.N, 32)
+        t0 = time.perf_counter()
+        plan = rpr.BatchPlan(problems, tol=[w.eps] * len(problems), correction=rpr.RPR_CORR_RANDNET_NN,
+                             k_max=k_max)
+        outs = [torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev) for _ in problems]
+        t1 = time.perf_counter()
+        plan.execute([u0] * len(problems), outs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        Ks = [plan.instance(b).info()["K"] for b in range(len(problems))]
+        conv = [plan.instance(b).info()["converged"] for b in range(len(problems))]
+        plan.close()
+        by_m = {m: Counter() for m in ms}
+        by_M = {M: Counter() for M in Ms}
+        for (sd, m, M), K, c in zip(combos, Ks, conv):
+            key = str(K) if c else f">{k_max}"
+            by_m[m][key] += 1
+            by_M[M][key] += 1
+        Up = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
+        pp = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, correction=rpr.RPR_CORR_PARAREAL)
+        pp.execute(u0, Up)
+        torch.cuda.synchronize()
+        K_para = pp.info()["K"]
+        pp.close()
+        out[name] = {"d": w.d, "N": w.N, "instances": len(problems), "weight_draws": n_seeds, "k_max": k_max,
+                     "create_s": t1 - t0, "solve_s": t2 - t1, "K_classical_parareal": K_para,
+                     "K_median": float(np.median(Ks)),
+                     "K_by_m": {str(m): hist(c) for m, c in by_m.items()},
+                     "K_by_M": {str(M): hist(c) for M, c in by_M.items()}}
+        print(f"robustness {name}: {len(problems)} instances, solve {t2 - t1:.2f} s, median K "
+              f"{np.median(Ks)}, classical K {K_para}", file=sys.stderr, flush=True)
+    return out
 
 
 def extra_workloads(torch, rpr, W, dev):

@@ -129,9 +129,8 @@ typedef enum {
                                   the dual form W = Phi~^T (Phi~ Phi~^T + lambda I)^-1 Y~
                                   (identical to the primal form); ties between
                                   equal distances go to the earlier pair.  The plan
-                                  stores every finite pair: 2 N k_max d states plus
-                                  N k_max M doubles of features.  Single plans only
-                                  (a batch gives RPR_ERR_UNSUPPORTED). */
+                                  stores every pair: 2 N k_max d states plus
+                                  N k_max M doubles of features. */
 } rpr_correction;
 
 typedef enum {

@@ -257,7 +257,8 @@ class BatchPlan:
 
     def __init__(self, problems, *, tol=1e-6, precision: int = RPR_FP64, correction: int = RPR_CORR_RANDNET,
                  k_max: int = 0, poll_every: int = 0, features: int = RPR_FEAT_AUTO, seed: int = 0, graph: int = 0):
-        """problems: list of dicts with keys h, d, t0, tN, N, F, G, M, activation, lam, A, zeta."""
+        """problems: list of dicts with keys h, d, t0, tN, N, F, G, M, activation, lam, A, zeta
+        (and m_nn for RPR_CORR_RANDNET_NN, default 4)."""
         import numpy as np
         n = len(problems)
         self.n = n
@@ -272,7 +273,8 @@ class BatchPlan:
         G = (rpr_propagator * n)(*[rpr_propagator(int(q["G"][0]), 0, int(q["G"][1])) for q in problems])
         TOL = (C.c_double * n)(*([float(tol)] * n if not isinstance(tol, (list, tuple)) else [float(t) for t in tol]))
         NET = (rpr_randnet * n)(*[rpr_randnet(int(q.get("M", 100)), int(q.get("activation", RPR_TANH)),
-                                              float(q.get("lam", 1e-6)), float(q.get("input_scale", 0.0)))
+                                              float(q.get("lam", 1e-6)), float(q.get("input_scale", 0.0)),
+                                              int(q.get("m_nn", 4)), 0)
                                   for q in problems])
         self._keep = []
         Ap = (C.c_void_p * n)()

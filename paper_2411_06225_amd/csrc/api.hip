@@ -989,8 +989,6 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
     if (n_inst < 1) return fail(RPR_ERR_INVALID_ARG, "n_inst must be >= 1");
     if (!h || !d || !t0 || !tN || !N || !F || !G || !tol || !opt)
         return fail(RPR_ERR_INVALID_ARG, "batch arrays must not be NULL");
-    if (opt->correction == RPR_CORR_RANDNET_NN)
-        return fail(RPR_ERR_UNSUPPORTED, "the nearest-neighbour correction serves single plans only");
     for (int b = 1; b < n_inst; ++b)
         if (h[b].kind != h[0].kind) return fail(RPR_ERR_INVALID_ARG, "all instances of a batch need the same rhs kind");
     rpr_plan *p = new rpr_plan();

@@ -113,17 +113,17 @@ def test_plan_create_rejects_bad_options():
     assert handle.value is None
 
 
-def test_batch_rejects_nearest_neighbour_correction():
+def test_batch_checks_nearest_neighbour_count():
     h = (rpr.rpr_rhs * 1)(rpr.make_rhs(0, 32))
     F, G = (rpr.rpr_propagator * 1)(_prop(4, 10)), (rpr.rpr_propagator * 1)(_prop(1, 2))
-    net = (rpr.rpr_randnet * 1)(rpr.rpr_randnet(10, 0, 1e-6, 0.0, 4, 0))
+    net = (rpr.rpr_randnet * 1)(rpr.rpr_randnet(10, 0, 1e-6, 0.0, 0, 0))
     d, N = (C.c_int32 * 1)(32), (C.c_int32 * 1)(4)
     t0, tN, tol = (C.c_double * 1)(0.0), (C.c_double * 1)(1.0), (C.c_double * 1)(1e-6)
     opt = rpr.rpr_options(0, rpr.RPR_CORR_RANDNET_NN, 0, 0, 0, 0, 0, 0)
     handle = C.c_void_p()
     st = rpr.lib().rpr_plan_create_batch(C.byref(handle), 1, h, d, t0, tN, N, F, G, tol, net, None, None, 0,
                                          C.byref(opt))
-    assert st == rpr.RPR_ERR_UNSUPPORTED
+    assert st == rpr.RPR_ERR_INVALID_ARG
     assert handle.value is None
 
 

@@ -140,3 +140,33 @@ def test_batch_graph_replays_match_plain_launches():
                 np.testing.assert_array_equal(Ug[b], Up[b])
     finally:
         plan.close()
+
+
+def test_nearest_neighbour_batch_matches_oracle_per_instance(orc):
+    # every instance its own store and neighbour count; the chain of each
+    # instance on one work-group.  Bound as for single plans: N 1e-12 plus the
+    # forward error of the worst refit, 10 kappa 2^-53 (kappa from the
+    # oracle's own neighbours).
+    from test_gpu_solve import nn_refit_condition
+    ws = burgers_instances(6, seed=9)
+    ms = [2, 3, 4, 5, 8, 20]
+    problems = batch_problems(ws)
+    for q, m in zip(problems, ms):
+        q["m_nn"] = m
+    plan = rpr.BatchPlan(problems, tol=[w.eps for w in ws], correction=rpr.RPR_CORR_RANDNET_NN)
+    try:
+        status, Us, infos = execute_batch(plan, ws)
+    finally:
+        plan.close()
+    assert status == rpr.RPR_OK
+    for w, m, Ug, ig in zip(ws, ms, Us, infos):
+        pb = orc.problem(w.kind, w.nx, w.ny, w.domain, w.params)
+        A, z = W.random_weights(w)
+        Uo, io = orc.parareal(pb, W.initial_condition(w), N=w.N, t0=w.t0, tN=w.tN, F=w.F, G=w.G, eps=w.eps,
+                              corr=2, m_nn=m, net=orc.Net(A, z, w.act, w.lam, 0.0), nthreads=4, keep_iterates=True)
+        assert ig["K"] == io["K"], w.name
+        assert ig["L_hist"].tolist() == io["L_hist"].tolist()
+        tol = max(w.N * 1e-12, 10 * nn_refit_condition(orc, w, io, m) * 2.0 ** -53)
+        err = np.abs(Ug - Uo).max() / np.abs(Uo).max()
+        print(w.name, w.d, "m", m, "K", ig["K"], "rel err %.2e tol %.1e" % (err, tol))
+        assert err <= tol
