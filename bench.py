@@ -60,7 +60,7 @@ FLOPS_PER_DOF_STEP = {"diffreact": 4 * 17.25}
 # change to them makes the field null until the counters are taken again.
 PROP_SOURCES = ("paper_2411_06225_amd/csrc/slotprop.h", "paper_2411_06225_amd/csrc/propagate.hip",
                 "paper_2411_06225_amd/csrc/common.h")
-PROP_TRAFFIC = {"sources": "3bce6799c68047c1", "fetch_kib": 2359.5, "fetch_scale": 2.0, "write_kib": 4608.0,
+PROP_TRAFFIC = {"sources": "e46de50c3020989d", "fetch_kib": 2359.1, "fetch_scale": 2.0, "write_kib": 4608.0,
                 "write_scale": 1.0}
 
 

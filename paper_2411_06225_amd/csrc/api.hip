@@ -713,11 +713,13 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         ChainArgs<double> a{};
         a.g = g;
         a.M = p->M;
+        a.mode = chain_mode(p);  // the kernel variant this plan launches
         st = launch_chain<double>(a, p->shG, 0, nullptr, &max_wg);
     } else {
         ChainArgs<float> a{};
         a.g = g;
         a.M = p->M;
+        a.mode = chain_mode(p);
         st = launch_chain<float>(a, p->shG, 0, nullptr, &max_wg);
     }
     if (st != RPR_OK) {

@@ -357,7 +357,10 @@ __device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src
 // (a grid barrier, or a work-group barrier when nwg == 1).
 // TILED: the slot state does not fit one work-group; the coarse solver is
 // then run by the whole grid (tiled_coarse) instead of work-group 0.
-template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, bool TILED, typename Sync>
+// NN_OK: the nearest-neighbour refit is compiled in (otherwise a kernel for
+// the other modes carries none of its code or registers).
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, bool TILED, bool NN_OK,
+          typename Sync>
 __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, const int nwg, Sync sync,
                                            unsigned char *lds_raw)
 {
@@ -395,7 +398,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     const int chunk = (d + nwg - 1) / nwg;
     const int j0 = wg * chunk, j1 = min(d, j0 + chunk);
 
-    const bool nn = a.mode == CHAIN_RANDNET_NN;
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
     const bool net = a.mode == CHAIN_RANDNET || nn;
     // stored pairs (this iteration's included)
     const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
@@ -559,12 +562,13 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     }
 }
 
-template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT, bool NN_OK>
 __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cg::grid_group grid = cg::this_grid();
-    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false, NN_OK>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); },
+                                                              lds_raw);
 }
 
 // Independent instances: work-group b runs the whole sweep of instance b.
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(MAXT) void k_chain_multi(const ChainArgs<T> *__rest
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ChainArgs<T> a = args[blockIdx.x];
-    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
 }
 
 // ---------------------------------------------------------- tiled form --
@@ -582,7 +586,7 @@ __global__ __launch_bounds__(TT_THREADS) void k_chain_tiled(ChainArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cg::grid_group grid = cg::this_grid();
-    chain_body<KIND, T, 1, false, false, 0, 0, true>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
+    chain_body<KIND, T, 1, false, false, 0, 0, true, true>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
 }
 
 template <int KIND, typename T>
@@ -590,7 +594,7 @@ __global__ __launch_bounds__(TT_THREADS) void k_chain_multi_tiled(const ChainArg
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ChainArgs<T> a = args[blockIdx.x];
-    chain_body<KIND, T, 1, false, false, 0, 0, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+    chain_body<KIND, T, 1, false, false, 0, 0, true, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
 }
 
 template <int KIND, typename T>
@@ -655,7 +659,14 @@ struct ChainLauncher {
     template <int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
     rpr_status run()
     {
-        auto kern = k_chain<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT>;
+        if (a.mode == CHAIN_RANDNET_NN) return run_kern<CPT, DBUF, FULL, NX, NY, MAXT, true>();
+        return run_kern<CPT, DBUF, FULL, NX, NY, MAXT, false>();
+    }
+
+    template <int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT, bool NN_OK>
+    rpr_status run_kern()
+    {
+        auto kern = k_chain<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, NN_OK>;
         static bool attr_set = false;
         if (!attr_set) {
             RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

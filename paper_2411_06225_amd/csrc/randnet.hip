@@ -228,6 +228,139 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
         }
 }
 
+// The same partial sums for large tiles: 128 rows of X x 128 neurons per
+// work-group (4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles), for
+// d % 8 == 0 so that every lane moves 16 bytes per global load.  The K-split,
+// the K-steps of 32 and the six products per step in the same order as
+// k_feat_bf16_partial, so both kernels give identical partial sums.  The
+// next K-step's global loads are in flight while the current one is
+// multiplied out of LDS.
+constexpr int GT = 128;
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_feat_bf16_gemm(int n, int M, int d, int kchunk, const TX *__restrict__ X,
+                                                        const uint16_t *__restrict__ Ab, double xs,
+                                                        float *__restrict__ part, const int *__restrict__ nrows_dev)
+{
+    constexpr int XV = 16 / sizeof(TX);          // X elements per 16-byte load
+    constexpr int XL = GT * BK / XV / 256;       // X loads per thread and K-step
+    constexpr int AL = GT * BK / 8 / 256;        // loads per thread, K-step and A piece (8 bf16 each)
+    const int nr = nrows_dev ? *nrows_dev : n;
+    const int r0 = blockIdx.x * GT, m0 = blockIdx.y * GT;
+    if (r0 >= nr) return;
+    const int k0 = blockIdx.z * kchunk, k1 = min(d, k0 + kchunk);
+    const size_t md = (size_t)M * d;
+    __shared__ __align__(16) uint16_t Xs[3][GT][BKP], As[3][GT][BKP];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;  // this wave's 64 x 64 quadrant
+
+    // global -> registers: X element group q of this thread is row
+    // (t + 256 q) / (BK / XV), k offset XV * ((t + 256 q) % (BK / XV)); A piece
+    // group q: neuron (t + 256 q) / 4, k offset 8 * ((t + 256 q) % 4)
+    TX xv[XL][XV];
+    uint4 av[3][AL];
+    auto load = [&](int kb) {
+#pragma unroll
+        for (int q = 0; q < XL; ++q) {
+            const int g = t + 256 * q, lr = g / (BK / XV), lk = XV * (g % (BK / XV));
+            const int r = r0 + lr, k = kb + lk;
+            if (r < nr && k < k1) {
+                const uint4 u = *reinterpret_cast<const uint4 *>(X + (size_t)r * d + k);
+                const TX *e = reinterpret_cast<const TX *>(&u);
+#pragma unroll
+                for (int c = 0; c < XV; ++c) xv[q][c] = e[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < XV; ++c) xv[q][c] = TX(0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < AL; ++q) {
+            const int g = t + 256 * q, lm = g >> 2, lk = 8 * (g & 3);
+            const int m = m0 + lm, k = kb + lk;
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                av[p][q] = (m < M && k < k1) ? *reinterpret_cast<const uint4 *>(Ab + p * md + (size_t)m * d + k)
+                                             : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    // registers -> LDS (X split into its three pieces on the way)
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < XL; ++q) {
+            const int g = t + 256 * q, lr = g / (BK / XV), lk = XV * (g % (BK / XV));
+#pragma unroll
+            for (int c = 0; c < XV; ++c) {
+                uint16_t x0, x1, x2;
+                split_bf16(double(xv[q][c]) * xs, x0, x1, x2);
+                Xs[0][lr][lk + c] = x0;
+                Xs[1][lr][lk + c] = x1;
+                Xs[2][lr][lk + c] = x2;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < AL; ++q) {
+            const int g = t + 256 * q, lm = g >> 2, lk = 8 * (g & 3);
+#pragma unroll
+            for (int p = 0; p < 3; ++p) *reinterpret_cast<uint4 *>(&As[p][lm][lk]) = av[p][q];
+        }
+    };
+
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    load(k0);
+    store();
+    __syncthreads();
+    for (int kb = k0; kb < k1; kb += BK) {
+        const bool more = kb + BK < k1;
+        if (more) load(kb + BK);
+        bf16x8_t ab[4][3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                ab[j][p] = __builtin_bit_cast(
+                    bf16x8_t, *reinterpret_cast<const uint4 *>(&As[p][wc * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)]));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bf16x8_t xa[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                xa[p] = __builtin_bit_cast(
+                    bf16x8_t, *reinterpret_cast<const uint4 *>(&Xs[p][wr * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                // smallest products first (as k_feat_bf16_partial)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[j][1], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[2], ab[j][0], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[j][2], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[j][0], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[j][1], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[j][0], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + wr * 64 + i * 16 + 4 * (lane >> 4) + e;
+                const int m = m0 + wc * 64 + j * 16 + (lane & 15);
+                if (r < nr && m < M) part[((size_t)blockIdx.z * n + r) * M + m] = acc[i][j][e];
+            }
+}
+
 // Phi = sigma(sum of the K-split partials + zeta), in double.
 __global__ void k_feat_bf16_finish(int n, int M, int nsplit, const float *__restrict__ part,
                                    const double *__restrict__ zeta, int act, double *__restrict__ Phi,
@@ -256,9 +389,16 @@ rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, cons
     if (n <= 0) return RPR_OK;
     const int ns = feat_bf16_splits(d);
     const int kchunk = ((d + ns - 1) / ns + BK - 1) / BK * BK;
-    dim3 grid((n + BT - 1) / BT, (M + BT - 1) / BT, ns);
-    hipLaunchKernelGGL(k_feat_bf16_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, inv_s, part,
-                       nrows_dev);
+    if (n > BT && d % 8 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
+        // large tiles when there are more rows than one small tile holds
+        dim3 grid((n + GT - 1) / GT, (M + GT - 1) / GT, ns);
+        hipLaunchKernelGGL(k_feat_bf16_gemm<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, inv_s, part,
+                           nrows_dev);
+    } else {
+        dim3 grid((n + BT - 1) / BT, (M + BT - 1) / BT, ns);
+        hipLaunchKernelGGL(k_feat_bf16_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, inv_s, part,
+                           nrows_dev);
+    }
     RPR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_feat_bf16_finish, dim3((n * M + 255) / 256), dim3(256), 0, st, n, M, ns, part, zeta,
                        act, Phi, nrows_dev);

@@ -257,7 +257,8 @@ def test_uniform_generator_bitwise(orc):
 
 
 @pytest.mark.parametrize("n,M,d,act", [(64, 200, 8192, 1), (37, 50, 300, 0), (5, 13, 1000, 0), (130, 70, 96, 1),
-                                       (8, 300, 110592, 1)])
+                                       (8, 300, 110592, 1), (300, 200, 4096, 1), (256, 300, 2056, 0),
+                                       (200, 150, 722, 0)])
 def test_split_bf16_features_close_to_fp64_oracle(orc, n, M, d, act):
     """Split-bfloat16 features against the FP64 features of the same (FP32)
     inputs.  Per product the three-piece splits leave <= 2^-27 of each factor
@@ -278,3 +279,26 @@ def test_split_bf16_features_close_to_fp64_oracle(orc, n, M, d, act):
     ratio = np.abs(got - ref) / S
     print("split bf16 features", n, M, d, "max |diff| / sum|a x| = %.2e (bound %.2e)" % (ratio.max(), 2.0 ** -16))
     assert np.all(np.abs(got - ref) <= 2.0 ** -16 * S)
+
+
+@pytest.mark.parametrize("n,M,d", [(300, 200, 4096), (130, 70, 96), (256, 300, 2056)])
+def test_split_bf16_large_tiles_equal_small_tiles(n, M, d):
+    # More than 64 rows with d % 8 == 0 take the 128 x 128-tile kernel when X
+    # is 16-byte aligned; the same X one float off that alignment takes the
+    # 64 x 64-tile kernel.  Same K split, K steps and product order: the
+    # features must agree bit for bit.
+    rng = np.random.default_rng(n + M + d)
+    A = rng.uniform(-1, 1, (M, d))
+    zeta = rng.uniform(-1, 1, M)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    xa = dev(X, torch.float32)
+    buf = torch.zeros(n * d + 4, dtype=torch.float32, device="cuda")
+    buf[1:1 + n * d] = xa.reshape(-1)
+    xm = buf[1:1 + n * d]
+    assert xa.data_ptr() % 16 == 0 and xm.data_ptr() % 16 != 0
+    out = []
+    for x in (xa, xm):
+        Phi = torch.empty((n, M), dtype=torch.float64, device="cuda")
+        rpr.rpr_randnet_features_bf16(M, d, n, 1, 2.0, dev(A), dev(zeta), x, Phi)
+        out.append(host(Phi))
+    np.testing.assert_array_equal(out[0], out[1])
