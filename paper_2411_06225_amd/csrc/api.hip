@@ -197,6 +197,7 @@ struct rpr_plan {
            *u0max = nullptr;
     int *ok = nullptr, *nrows = nullptr, *L_hist = nullptr, *cfail = nullptr, *u0bad = nullptr;
     uint16_t *Ab = nullptr;   // bf16 copy of A (reduced precision)
+    uint16_t *Xb = nullptr;   // bf16 pieces of the training inputs (large-tile feature GEMM)
     double *At = nullptr;     // A^T, d x M (the chain's hidden layer)
     float *fpart32 = nullptr; // split-K partials of the bf16 feature GEMM
     Ctrl *ctrl = nullptr;
@@ -259,7 +260,7 @@ static void plan_free(rpr_plan *p)
         if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
                     p->Lt, p->Bm, p->W, p->phi, p->part, p->chg_hist, p->u0max, p->ok, p->nrows, p->L_hist,
-                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At};
+                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At, p->Xb};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->ctrl_host) (void)hipHostFree(p->ctrl_host);
@@ -351,6 +352,7 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
             RPR_TRY(dalloc(&p->Ab, 3 * (size_t)M * d));
             RPR_TRY(dalloc(&p->fpart32, (size_t)feat_bf16_splits(d) * N * M));
             RPR_TRY(launch_to_bf16(p->A, p->Ab, (size_t)M * d, nullptr));
+            if (feat_bf16_large(N, d)) RPR_TRY(dalloc(&p->Xb, 3 * (size_t)N * d));
         }
         RPR_HIP(hipDeviceSynchronize());
     }
@@ -841,7 +843,8 @@ static rpr_status phase_model(rpr_plan *p, double inv_s, hipStream_t st)
     T *X = static_cast<T *>(p->X), *Y = static_cast<T *>(p->Y);
     RPR_TRY(launch_pairs<T>(N, d, U, Fv, Gc, X, Y, p->ok, p->nrows, p->ctrl, st));
     if (p->Ab)
-        RPR_TRY(launch_features_bf16<T>(N, M, d, p->act, inv_s, p->Ab, p->zeta, X, p->Phi, p->fpart32, p->nrows, st));
+        RPR_TRY(launch_features_bf16<T>(N, M, d, p->act, inv_s, p->Ab, p->zeta, X, p->Phi, p->fpart32, p->nrows, st,
+                                        p->Xb));
     else
         RPR_TRY(launch_features<T>(N, M, d, p->act, inv_s, p->A, p->zeta, X, p->Phi, p->fpart, p->nrows, st));
     if (p->nn)
@@ -1302,10 +1305,14 @@ extern "C" rpr_status rpr_randnet_features_bf16(int32_t M, int32_t d, int32_t n,
     float *part = nullptr;
     RPR_HIP(hipMallocAsync((void **)&Ab, 3 * sizeof(uint16_t) * (size_t)M * d, st));
     RPR_HIP(hipMallocAsync((void **)&part, sizeof(float) * feat_bf16_splits(d) * n * M, st));
+    uint16_t *xb = nullptr;
+    if (feat_bf16_large(n, d)) RPR_HIP(hipMallocAsync((void **)&xb, 3 * sizeof(uint16_t) * (size_t)n * d, st));
     rpr_status rc = launch_to_bf16(A, Ab, (size_t)M * d, st);
-    if (rc == RPR_OK) rc = launch_features_bf16<float>(n, M, d, activation, 1.0 / s, Ab, zeta, X, Phi, part, nullptr, st);
+    if (rc == RPR_OK)
+        rc = launch_features_bf16<float>(n, M, d, activation, 1.0 / s, Ab, zeta, X, Phi, part, nullptr, st, xb);
     RPR_HIP(hipFreeAsync(Ab, st));
     RPR_HIP(hipFreeAsync(part, st));
+    if (xb) RPR_HIP(hipFreeAsync(xb, st));
     return rc;
 }
 

@@ -20,11 +20,15 @@ rpr_status launch_features(int n, int M, int d, int act, double inv_s, const dou
 // from launch_to_bf16) split in three bfloat16 pieces, the six leading
 // products of the pieces accumulated in FP32 on the matrix cores, the K-split
 // partials and sigma in double.  part holds feat_bf16_splits(d) x n x M floats.
+// With xb (3 n d bfloat16 workspace) non-null and feat_bf16_large(n, d),
+// the inputs are split in a pass of their own and a 128 x 128-tile kernel
+// forms the same partial sums (bit for bit).
 int feat_bf16_splits(int d);
+bool feat_bf16_large(int n, int d);
 template <typename TX>
 rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, const uint16_t *Ab,
                                 const double *zeta, const TX *X, double *Phi, float *part,
-                                const int *nrows_dev, hipStream_t st);
+                                const int *nrows_dev, hipStream_t st, uint16_t *xb = nullptr);
 
 // The three bfloat16 pieces of in (round to nearest even each): out holds
 // 3 n values, piece p at out + p n.

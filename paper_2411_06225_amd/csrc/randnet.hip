@@ -202,21 +202,21 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
         for (int p = 0; p < 3; ++p)
             xa[p] = __builtin_bit_cast(bf16x8_t,
                                        *reinterpret_cast<const uint4 *>(&Xs[p][w * 16 + (lane & 15)][8 * (lane >> 4)]));
+        bf16x8_t ab[4][3];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            bf16x8_t ab[3];
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int p = 0; p < 3; ++p)
-                ab[p] = __builtin_bit_cast(bf16x8_t,
-                                           *reinterpret_cast<const uint4 *>(&As[p][j * 16 + (lane & 15)][8 * (lane >> 4)]));
-            // smallest products first
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[1], acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[2], ab[0], acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[2], acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[0], acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[1], acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[0], acc[j], 0, 0, 0);
-        }
+                ab[j][p] = __builtin_bit_cast(
+                    bf16x8_t, *reinterpret_cast<const uint4 *>(&As[p][j * 16 + (lane & 15)][8 * (lane >> 4)]));
+        // smallest products first: x1 a1, x2 a0, x0 a2, x1 a0, x0 a1, x0 a0,
+        // the four accumulators interleaved so consecutive MFMAs are independent
+        constexpr int PX[6] = {1, 2, 0, 1, 0, 0}, PA[6] = {1, 0, 2, 0, 1, 0};
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[PX[q]], ab[j][PA[q]], acc[j], 0, 0, 0);
         __syncthreads();
     }
 #pragma unroll
@@ -230,79 +230,72 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
 
 // The same partial sums for large tiles: 128 rows of X x 128 neurons per
 // work-group (4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles), for
-// d % 8 == 0 so that every lane moves 16 bytes per global load.  The K-split,
-// the K-steps of 32 and the six products per step in the same order as
-// k_feat_bf16_partial, so both kernels give identical partial sums.  The
-// next K-step's global loads are in flight while the current one is
-// multiplied out of LDS.
+// d % 8 == 0 so that every lane moves 16 bytes per load.  The inputs come
+// split beforehand (k_split_rows: the pieces split_bf16 gives on the fly in
+// k_feat_bf16_partial), so the K-loop is loads, LDS and MFMA only.  The
+// K-split, the K-steps of 32 and the six products per step are in the same
+// order as k_feat_bf16_partial, so both kernels give identical partial
+// sums.  The next K-step's global loads are in flight while the current one
+// is multiplied out of LDS.
 constexpr int GT = 128;
 
+// The three bfloat16 pieces of X / s, rows r < nr: piece p of X[r][k] at
+// out[p n d + r d + k].
 template <typename TX>
-__global__ __launch_bounds__(256) void k_feat_bf16_gemm(int n, int M, int d, int kchunk, const TX *__restrict__ X,
-                                                        const uint16_t *__restrict__ Ab, double xs,
-                                                        float *__restrict__ part, const int *__restrict__ nrows_dev)
+__global__ __launch_bounds__(256) void k_split_rows(int n, int d, const TX *__restrict__ X, double xs,
+                                                    uint16_t *__restrict__ out, const int *__restrict__ nrows_dev)
 {
-    constexpr int XV = 16 / sizeof(TX);          // X elements per 16-byte load
-    constexpr int XL = GT * BK / XV / 256;       // X loads per thread and K-step
-    constexpr int AL = GT * BK / 8 / 256;        // loads per thread, K-step and A piece (8 bf16 each)
+    const int nr = nrows_dev ? *nrows_dev : n;
+    const size_t nd = (size_t)n * d, e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)nr * d) return;
+    uint16_t x0, x1, x2;
+    split_bf16(double(X[e]) * xs, x0, x1, x2);
+    out[e] = x0;
+    out[nd + e] = x1;
+    out[2 * nd + e] = x2;
+}
+
+__global__ __launch_bounds__(256, 2) void k_feat_bf16_gemm(int n, int M, int d, int kchunk,
+                                                        const uint16_t *__restrict__ Xb,
+                                                        const uint16_t *__restrict__ Ab, float *__restrict__ part,
+                                                        const int *__restrict__ nrows_dev)
+{
+    constexpr int LQ = GT * BK / 8 / 256;  // 16-byte loads per thread, K-step and piece, for X and for A
     const int nr = nrows_dev ? *nrows_dev : n;
     const int r0 = blockIdx.x * GT, m0 = blockIdx.y * GT;
     if (r0 >= nr) return;
     const int k0 = blockIdx.z * kchunk, k1 = min(d, k0 + kchunk);
-    const size_t md = (size_t)M * d;
+    const size_t md = (size_t)M * d, nd = (size_t)n * d;
     __shared__ __align__(16) uint16_t Xs[3][GT][BKP], As[3][GT][BKP];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;  // this wave's 64 x 64 quadrant
 
-    // global -> registers: X element group q of this thread is row
-    // (t + 256 q) / (BK / XV), k offset XV * ((t + 256 q) % (BK / XV)); A piece
-    // group q: neuron (t + 256 q) / 4, k offset 8 * ((t + 256 q) % 4)
-    TX xv[XL][XV];
-    uint4 av[3][AL];
+    // load group q of this thread: tile row (t + 256 q) / 4, k offset
+    // 8 ((t + 256 q) % 4), for every piece of X and of A
+    uint4 xv[3][LQ], av[3][LQ];
     auto load = [&](int kb) {
 #pragma unroll
-        for (int q = 0; q < XL; ++q) {
-            const int g = t + 256 * q, lr = g / (BK / XV), lk = XV * (g % (BK / XV));
-            const int r = r0 + lr, k = kb + lk;
-            if (r < nr && k < k1) {
-                const uint4 u = *reinterpret_cast<const uint4 *>(X + (size_t)r * d + k);
-                const TX *e = reinterpret_cast<const TX *>(&u);
+        for (int q = 0; q < LQ; ++q) {
+            const int g = t + 256 * q, lr = g >> 2, k = kb + 8 * (g & 3);
+            const int r = r0 + lr, m = m0 + lr;
 #pragma unroll
-                for (int c = 0; c < XV; ++c) xv[q][c] = e[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < XV; ++c) xv[q][c] = TX(0);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < AL; ++q) {
-            const int g = t + 256 * q, lm = g >> 2, lk = 8 * (g & 3);
-            const int m = m0 + lm, k = kb + lk;
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
+            for (int p = 0; p < 3; ++p) {
+                xv[p][q] = (r < nr && k < k1) ? *reinterpret_cast<const uint4 *>(Xb + p * nd + (size_t)r * d + k)
+                                              : uint4{0u, 0u, 0u, 0u};
                 av[p][q] = (m < M && k < k1) ? *reinterpret_cast<const uint4 *>(Ab + p * md + (size_t)m * d + k)
                                              : uint4{0u, 0u, 0u, 0u};
-        }
-    };
-    // registers -> LDS (X split into its three pieces on the way)
-    auto store = [&]() {
-#pragma unroll
-        for (int q = 0; q < XL; ++q) {
-            const int g = t + 256 * q, lr = g / (BK / XV), lk = XV * (g % (BK / XV));
-#pragma unroll
-            for (int c = 0; c < XV; ++c) {
-                uint16_t x0, x1, x2;
-                split_bf16(double(xv[q][c]) * xs, x0, x1, x2);
-                Xs[0][lr][lk + c] = x0;
-                Xs[1][lr][lk + c] = x1;
-                Xs[2][lr][lk + c] = x2;
             }
         }
+    };
+    auto store = [&]() {
 #pragma unroll
-        for (int q = 0; q < AL; ++q) {
-            const int g = t + 256 * q, lm = g >> 2, lk = 8 * (g & 3);
+        for (int q = 0; q < LQ; ++q) {
+            const int g = t + 256 * q, lr = g >> 2, lk = 8 * (g & 3);
 #pragma unroll
-            for (int p = 0; p < 3; ++p) *reinterpret_cast<uint4 *>(&As[p][lm][lk]) = av[p][q];
+            for (int p = 0; p < 3; ++p) {
+                *reinterpret_cast<uint4 *>(&Xs[p][lr][lk]) = xv[p][q];
+                *reinterpret_cast<uint4 *>(&As[p][lr][lk]) = av[p][q];
+            }
         }
     };
 
@@ -332,16 +325,15 @@ __global__ __launch_bounds__(256) void k_feat_bf16_gemm(int n, int M, int d, int
             for (int p = 0; p < 3; ++p)
                 xa[p] = __builtin_bit_cast(
                     bf16x8_t, *reinterpret_cast<const uint4 *>(&Xs[p][wr * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]));
+            // smallest products first (as k_feat_bf16_partial); the four
+            // accumulators of the row block interleaved, so consecutive
+            // MFMAs are independent
+            constexpr int PX[6] = {1, 2, 0, 1, 0, 0}, PA[6] = {1, 0, 2, 0, 1, 0};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                // smallest products first (as k_feat_bf16_partial)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[j][1], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[2], ab[j][0], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[j][2], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1], ab[j][0], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[j][1], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0], ab[j][0], acc[i][j], 0, 0, 0);
-            }
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[PX[q]], ab[j][PA[q]], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
         if (more) {
@@ -377,23 +369,28 @@ __global__ void k_feat_bf16_finish(int n, int M, int nsplit, const float *__rest
 
 int feat_bf16_splits(int d)
 {
-    int s = (d + 2047) / 2048;  // about 2048 of K per work-group
+    int s = (d + 1023) / 1024;  // about 1024 of K per work-group
     return s < 1 ? 1 : (s > 64 ? 64 : s);
 }
+
+// The large-tile kernel's vector loads keep a K-step's loads in flight
+// together; the small one issues element loads and serves only a few rows.
+bool feat_bf16_large(int n, int d) { return n > 16 && d % 8 == 0; }
 
 template <typename TX>
 rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, const uint16_t *Ab,
                                 const double *zeta, const TX *X, double *Phi, float *part,
-                                const int *nrows_dev, hipStream_t st)
+                                const int *nrows_dev, hipStream_t st, uint16_t *xb)
 {
     if (n <= 0) return RPR_OK;
     const int ns = feat_bf16_splits(d);
     const int kchunk = ((d + ns - 1) / ns + BK - 1) / BK * BK;
-    if (n > BT && d % 8 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
-        // large tiles when there are more rows than one small tile holds
+    if (xb && feat_bf16_large(n, d)) {
+        const size_t nd = (size_t)n * d;
+        hipLaunchKernelGGL(k_split_rows<TX>, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, n, d, X, inv_s,
+                           xb, nrows_dev);
         dim3 grid((n + GT - 1) / GT, (M + GT - 1) / GT, ns);
-        hipLaunchKernelGGL(k_feat_bf16_gemm<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, inv_s, part,
-                           nrows_dev);
+        hipLaunchKernelGGL(k_feat_bf16_gemm, grid, dim3(256), 0, st, n, M, d, kchunk, xb, Ab, part, nrows_dev);
     } else {
         dim3 grid((n + BT - 1) / BT, (M + BT - 1) / BT, ns);
         hipLaunchKernelGGL(k_feat_bf16_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, Ab, inv_s, part,
@@ -406,9 +403,11 @@ rpr_status launch_features_bf16(int n, int M, int d, int act, double inv_s, cons
     return RPR_OK;
 }
 template rpr_status launch_features_bf16<float>(int, int, int, int, double, const uint16_t *, const double *,
-                                                const float *, double *, float *, const int *, hipStream_t);
+                                                const float *, double *, float *, const int *, hipStream_t,
+                                                uint16_t *);
 template rpr_status launch_features_bf16<double>(int, int, int, int, double, const uint16_t *, const double *,
-                                                 const double *, double *, float *, const int *, hipStream_t);
+                                                 const double *, double *, float *, const int *, hipStream_t,
+                                                 uint16_t *);
 
 // ----------------------------------------------------------- statistics ---
 // G[a][b] += sum_r ok_r Phi[r][a] Phi[r][b]; rows in order r = 0..n-1.

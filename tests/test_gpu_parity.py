@@ -263,7 +263,7 @@ def test_split_bf16_features_close_to_fp64_oracle(orc, n, M, d, act):
     """Split-bfloat16 features against the FP64 features of the same (FP32)
     inputs.  Per product the three-piece splits leave <= 2^-27 of each factor
     and the six kept products drop terms <= 3 2^-24 |a x|; the FP32 sums run
-    over at most 6 x 2048 products per K split.  Bound on the pre-activation
+    over at most 6 x 2048 products per K split (d <= 131072).  Bound on the pre-activation
     (sigma is 1-Lipschitz): 2^-16 sum_j |a x_j / s|, about 8 x the summation
     error of a random walk over 12288 FP32 additions."""
     rng = np.random.default_rng(n * 7 + d)
@@ -283,22 +283,22 @@ def test_split_bf16_features_close_to_fp64_oracle(orc, n, M, d, act):
 
 @pytest.mark.parametrize("n,M,d", [(300, 200, 4096), (130, 70, 96), (256, 300, 2056)])
 def test_split_bf16_large_tiles_equal_small_tiles(n, M, d):
-    # More than 64 rows with d % 8 == 0 take the 128 x 128-tile kernel when X
-    # is 16-byte aligned; the same X one float off that alignment takes the
-    # 64 x 64-tile kernel.  Same K split, K steps and product order: the
-    # features must agree bit for bit.
+    # More than 16 rows with d % 8 == 0 take the 128 x 128-tile kernel on
+    # inputs split beforehand; 16 rows take the 64 x 64-tile kernel that
+    # splits on the fly.  A row's features do not depend on the other rows,
+    # and both kernels use the same K split, K steps and product order: every
+    # block of 16 rows of the large call must equal the small call on those
+    # rows bit for bit.
     rng = np.random.default_rng(n + M + d)
     A = rng.uniform(-1, 1, (M, d))
     zeta = rng.uniform(-1, 1, M)
     X = rng.standard_normal((n, d)).astype(np.float32)
-    xa = dev(X, torch.float32)
-    buf = torch.zeros(n * d + 4, dtype=torch.float32, device="cuda")
-    buf[1:1 + n * d] = xa.reshape(-1)
-    xm = buf[1:1 + n * d]
-    assert xa.data_ptr() % 16 == 0 and xm.data_ptr() % 16 != 0
-    out = []
-    for x in (xa, xm):
-        Phi = torch.empty((n, M), dtype=torch.float64, device="cuda")
-        rpr.rpr_randnet_features_bf16(M, d, n, 1, 2.0, dev(A), dev(zeta), x, Phi)
-        out.append(host(Phi))
-    np.testing.assert_array_equal(out[0], out[1])
+    Ad, zd = dev(A), dev(zeta)
+    big = torch.empty((n, M), dtype=torch.float64, device="cuda")
+    rpr.rpr_randnet_features_bf16(M, d, n, 1, 2.0, Ad, zd, dev(X, torch.float32), big)
+    big = host(big)
+    for r0 in range(0, n, 16):
+        rows = X[r0:r0 + 16]
+        small = torch.empty((rows.shape[0], M), dtype=torch.float64, device="cuda")
+        rpr.rpr_randnet_features_bf16(M, d, rows.shape[0], 1, 2.0, Ad, zd, dev(rows, torch.float32), small)
+        np.testing.assert_array_equal(big[r0:r0 + 16], host(small))
