@@ -239,6 +239,12 @@ __global__ __launch_bounds__(256) void k_feat_bf16_partial(int n, int M, int d, 
 // is multiplied out of LDS.
 constexpr int GT = 128;
 
+// LDS rows of the large-tile kernel are 64 bytes (32 bfloat16, no padding);
+// 16-byte chunk c of row r sits at chunk c ^ lds_swz(r).  Writes (4 lanes
+// per row) and fragment reads (16 rows at one chunk) then hit distinct banks
+// for 32 as for 64 banks of 4 bytes.
+__device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
 // The three bfloat16 pieces of X / s, rows r < nr: piece p of X[r][k] at
 // out[p n d + r d + k].
 template <typename TX>
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(256, 2) void k_feat_bf16_gemm(int n, int M, int d, 
     if (r0 >= nr) return;
     const int k0 = blockIdx.z * kchunk, k1 = min(d, k0 + kchunk);
     const size_t md = (size_t)M * d, nd = (size_t)n * d;
-    __shared__ __align__(16) uint16_t Xs[3][GT][BKP], As[3][GT][BKP];
+    __shared__ __align__(16) uint16_t Xs[3][GT][BK], As[3][GT][BK];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;  // this wave's 64 x 64 quadrant
 
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(256, 2) void k_feat_bf16_gemm(int n, int M, int d, 
     auto store = [&]() {
 #pragma unroll
         for (int q = 0; q < LQ; ++q) {
-            const int g = t + 256 * q, lr = g >> 2, lk = 8 * (g & 3);
+            const int g = t + 256 * q, lr = g >> 2, lk = 8 * ((g & 3) ^ lds_swz(lr));
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
                 *reinterpret_cast<uint4 *>(&Xs[p][lr][lk]) = xv[p][q];
@@ -313,18 +319,19 @@ __global__ __launch_bounds__(256, 2) void k_feat_bf16_gemm(int n, int M, int d, 
         if (more) load(kb + BK);
         bf16x8_t ab[4][3];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            const int R = wc * 64 + j * 16 + (lane & 15), c = 8 * ((lane >> 4) ^ lds_swz(R));
 #pragma unroll
             for (int p = 0; p < 3; ++p)
-                ab[j][p] = __builtin_bit_cast(
-                    bf16x8_t, *reinterpret_cast<const uint4 *>(&As[p][wc * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)]));
+                ab[j][p] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4 *>(&As[p][R][c]));
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             bf16x8_t xa[3];
+            const int R = wr * 64 + i * 16 + (lane & 15), c = 8 * ((lane >> 4) ^ lds_swz(R));
 #pragma unroll
             for (int p = 0; p < 3; ++p)
-                xa[p] = __builtin_bit_cast(
-                    bf16x8_t, *reinterpret_cast<const uint4 *>(&Xs[p][wr * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]));
+                xa[p] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4 *>(&Xs[p][R][c]));
             // smallest products first (as k_feat_bf16_partial); the four
             // accumulators of the row block interleaved, so consecutive
             // MFMAs are independent
