@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "chain.h"
+#include "tiledprop.h"
 #include "common.h"
 #include "randnet.h"
 #include "slotprop.h"
@@ -568,6 +569,9 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         for (int c : cands) {
             if (c < 1 || c > max_wg) continue;
             if (p->M > 0 && c > 1 && c - 1 > p->M && c != cus) continue;
+            // the tiled coarse solver spreads its tiles over the grid: one
+            // work-group would take all of them in turn (seconds per sweep)
+            if (p->shG.maxt == TILED_THREADS && c < tiles_of(g)) continue;
             float ms = 0.f;
             hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
             RPR_TRY(launch_chain<T>(a, p->shG, c, st));
@@ -827,7 +831,9 @@ static rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStr
     }
     ChainArgs<T> a = chain_args<T>(p, s);
     a.mode = CHAIN_SWEEP;
-    RPR_TRY(launch_chain<T>(a, p->shG, 1, st));
+    // on chip the sweep's state stays in one work-group; the tiled coarse
+    // solver spreads each slot's tiles over the plan's grid
+    RPR_TRY(launch_chain<T>(a, p->shG, p->shG.maxt == TILED_THREADS ? p->nwg : 1, st));
     a.mode = chain_mode(p);
     *out = a;
     return RPR_OK;

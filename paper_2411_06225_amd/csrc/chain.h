@@ -52,8 +52,8 @@ struct ChainArgs {
 // Dynamic LDS of the chain kernel for coarse-solver shape sh and M neurons.
 size_t chain_lds(const OnchipShape &sh, int M);
 
-// Cooperative launch of one sweep on nwg work-groups (nwg = 1 for
-// CHAIN_SWEEP).  With max_wg non-null nothing is launched and *max_wg receives
+// Cooperative launch of one sweep on nwg work-groups (CHAIN_SWEEP on chip:
+// work-group 0 runs it alone, so nwg = 1).  With max_wg non-null nothing is launched and *max_wg receives
 // the number of work-groups that can be co-resident on the device.
 template <typename T>
 rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,

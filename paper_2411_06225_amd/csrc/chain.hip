@@ -343,6 +343,24 @@ __device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src
                                              const int nwg, Sync sync, T *lds)
 {
     const int nt = tiles_of(a.g);
+    if (a.G_method == RPR_RK1) {
+        // forward Euler: up to EH steps per pass without a grid barrier
+        // (euler_tile_multi); the state alternates between the work arrays
+        // u and ya between passes, the FP32 compensation stays in cmp
+        T *buf[2] = {a.gw.u, a.gw.ya};
+        int pass = 0;
+        for (long long s = 0; s < a.G_steps; s += EH, ++pass) {
+            const int n = (int)(a.G_steps - s < EH ? a.G_steps - s : EH);
+            const bool last = s + n >= a.G_steps;
+            const T *in = s == 0 ? src : buf[(pass - 1) & 1];
+            T *out = last ? dst : buf[pass & 1];
+            for (int tile = wg; tile < nt; tile += nwg)
+                euler_tile_multi<KIND, T>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr, a.gw.cmp,
+                                          s == 0 ? 1 : 0, lds);
+            sync();
+        }
+        return;
+    }
     for (long long s = 0; s < a.G_steps; ++s) {
         for (int stage = a.G_method == RPR_RK4 ? 1 : 0; stage <= (a.G_method == RPR_RK4 ? 4 : 0); ++stage) {
             const StageIO<T> io = stage_io<T>(a.G_method, stage, s, a.G_steps, src, dst, dst2, a.gw);

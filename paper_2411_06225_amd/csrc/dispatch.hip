@@ -63,7 +63,8 @@ OnchipShape tiled_shape(const Geom &g, size_t elem)
     OnchipShape sh{};
     sh.block = TT_THREADS;
     sh.maxt = TILED_THREADS;
-    sh.lds = tiled_lds(g, elem);
+    // the coarse solver of the sweep also runs several Euler steps per tile
+    sh.lds = std::max(tiled_lds(g, elem), euler_multi_lds(g, elem));
     return sh;
 }
 

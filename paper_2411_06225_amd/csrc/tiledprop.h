@@ -388,6 +388,118 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int tile, const 
     __syncthreads();  // the tile buffer is reused by the next tile
 }
 
+// Several forward-Euler steps of one tile without leaving the work-group
+// (the coarse solver of the sequential sweep, where a grid barrier per step
+// would cost more than the step).  The tile is loaded with an EH-cell halo
+// (the cells of the domain within EH of it: wrapped when periodic, cut at a
+// wall), then step t = 1..steps (steps <= EH) updates the region shrunk by t
+// cells on every side that is not a wall, in LDS; after the last step the
+// tile's own cells are exact and go to dst (and dst2).  A cell at a wall
+// takes itself as the missing neighbour, as the one-step form does.  Per
+// cell and step the arithmetic is that of stage_tile<KIND, T, 0>, FP32 state
+// compensation included (cmp in memory between calls; cmp_zero: start from
+// zero).
+constexpr int EH = 8;
+constexpr int ERX = TT_X + 2 * EH, ERY = TT_Y + 2 * EH;
+
+__host__ __device__ inline size_t euler_multi_lds(const Geom &g, size_t elem)
+{
+    return (size_t)(elem == 4 ? 3 : 2) * g.ns * ERY * ERX * elem;
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, const int steps, const double dt,
+                                                 const T *__restrict__ src, T *__restrict__ dst,
+                                                 T *__restrict__ dst2, T *__restrict__ cmp, const int cmp_zero,
+                                                 T *__restrict__ lds)
+{
+    constexpr int NS = kind_ns<KIND>();
+    constexpr int RN = ERX * ERY;
+    constexpr bool KAHAN = sizeof(T) == 4;
+    const int nx = g.nx, ny = g.ny, nc = g.nc;
+    const bool per = g.periodic != 0;
+    const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
+    const int gx0 = x0 - EH, gy0 = y0 - EH;  // domain cell of region cell (0, 0)
+    T *buf[2] = {lds, lds + NS * RN};
+    T *cm = lds + 2 * NS * RN;  // FP32 compensation
+    // sides that cut the domain (the rest lie at a wall)
+    const int cw = per || gx0 > 0, ce = per || gx0 + ERX < nx;
+    const int cs = per || gy0 > 0, cn = per || gy0 + ERY < ny;
+    auto gcoord = [&](int l, int o, int n) {  // region index -> domain index, or -1 outside a wall
+        int v = o + l;
+        if (per) return ((v % n) + n) % n;
+        return (v < 0 || v >= n) ? -1 : v;
+    };
+    for (int e = threadIdx.x; e < RN; e += blockDim.x) {
+        const int gx = gcoord(e % ERX, gx0, nx), gy = gcoord(e / ERX, gy0, ny);
+        if (gx < 0 || gy < 0) continue;
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const int idx = sp * nc + gy * nx + gx;
+            buf[0][sp * RN + e] = src[idx];
+            if constexpr (KAHAN) cm[sp * RN + e] = cmp_zero ? T(0) : cmp[idx];
+        }
+    }
+    __syncthreads();
+    const T dtT = T(dt);
+    int cur = 0;
+    for (int t = 1; t <= steps; ++t) {
+        const int lx0 = t * cw, lx1 = ERX - t * ce, ly0 = t * cs, ly1 = ERY - t * cn;
+        const T *b = buf[cur];
+        T *o = buf[cur ^ 1];
+        for (int e = threadIdx.x; e < RN; e += blockDim.x) {
+            const int lx = e % ERX, ly = e / ERX;
+            if (lx < lx0 || lx >= lx1 || ly < ly0 || ly >= ly1) continue;
+            const int gx = gcoord(lx, gx0, nx), gy = gcoord(ly, gy0, ny);
+            if (gx < 0 || gy < 0) continue;
+            const bool ww = !per && gx == 0, we = !per && gx == nx - 1;
+            const bool ws = !per && gy == 0, wn = !per && gy == ny - 1;
+            const int ew = ww ? e : e - 1, ee = we ? e : e + 1, es = ws ? e : e - ERX, en = wn ? e : e + ERX;
+            T c[NS], w[NS], ea[NS], s[NS], n[NS], k[NS];
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+                const T *bb = b + sp * RN;
+                c[sp] = bb[e];
+                w[sp] = bb[ew];
+                ea[sp] = bb[ee];
+                s[sp] = bb[es];
+                n[sp] = bb[en];
+            }
+            rhs_cell<KIND, T>(g, c, w, ea, s, n, ww, we, ws, wn, k);
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+                const T u = c[sp], inc = dtT * k[sp];
+                if constexpr (KAHAN) {
+                    const T yk = inc - cm[sp * RN + e];
+                    const T un = u + yk;
+                    cm[sp * RN + e] = (un - u) - yk;
+                    o[sp * RN + e] = un;
+                } else {
+                    o[sp * RN + e] = u + inc;
+                }
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // the tile's own cells
+    for (int e = threadIdx.x; e < TT_X * TT_Y; e += blockDim.x) {
+        const int lx = EH + e % TT_X, ly = EH + e / TT_X;
+        const int gx = x0 + e % TT_X, gy = y0 + e / TT_X;
+        if (gx >= nx || gy >= ny) continue;
+        const int r = ly * ERX + lx;
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const int idx = sp * nc + gy * nx + gx;
+            const T v = buf[cur][sp * RN + r];
+            dst[idx] = v;
+            if (dst2) dst2[idx] = v;
+            if constexpr (KAHAN) cmp[idx] = cm[sp * RN + r];
+        }
+    }
+    __syncthreads();  // the region buffers are reused by the next tile
+}
+
 // stage_tile with the stage chosen at run time.
 template <int KIND, typename T>
 __device__ __forceinline__ void stage_tile_any(const Geom &g, const int tile, const int stage, const double dt,
