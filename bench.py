@@ -475,31 +475,70 @@ def extra_workloads(torch, rpr, W, dev):
         K = plan.info()["K"]
         return sum(w.N - int(Lh[k - 1]) for k in range(1, K + 1)) * w.F[1] / sec
 
-    def single(w):
+    def serial_fine(w, h, u0, prec):
+        """F slice after slice from u0 (the serial fine solution), as FP64."""
+        dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
+        dt = (w.tN - w.t0) / w.N / w.F[1]
+        cur = u0.to(dtype)[None].contiguous()
+        out = [cur[0].double().clone()]
+        for _ in range(w.N):
+            nxt = torch.empty_like(cur)
+            rpr.rpr_propagate(h, w.d, w.F[0], w.F[1], prec, dt, 1, cur, nxt)
+            cur = nxt
+            out.append(cur[0].double().clone())
+        torch.cuda.synchronize()
+        return torch.stack(out)
+
+    def single(w, with_tau=False):
         h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
         A, z = W.random_weights(w)
         u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
         r = {"d": w.d, "N": w.N}
         Us = {}
-        for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
+
+        def solve(prec, k_max=0):
             plan = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
-                            A=A, zeta=z, precision=prec, autotune=1)
+                            A=A, zeta=z, precision=prec, autotune=1, k_max=k_max)
             U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             plan.execute(u0, U)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
-            Us[name] = U
-            r[name] = {"s": sec, "K": plan.info()["K"], "fine_state_steps_per_s": fine_rate(plan, w, sec)}
+            res = {"s": sec, "K": plan.info()["K"], "fine_state_steps_per_s": fine_rate(plan, w, sec)}
             plan.close()
-            print(f"extra {w.name} {name}: {sec:.3f} s, K = {r[name]['K']}", file=sys.stderr, flush=True)
+            return U, res
+
+        for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
+            Us[name], r[name] = solve(prec)
+            print(f"extra {w.name} {name}: {r[name]['s']:.3f} s, K = {r[name]['K']}", file=sys.stderr, flush=True)
         r["mixed"]["E_vs_fp64"] = float((Us["mixed"][1:] - Us["fp64"][1:]).abs().amax(dim=1).mean())
+        if with_tau:
+            # the common accuracy of the benchmark line: tau = 10 x the error
+            # of the FP32 serial fine solution against the FP64 one
+            Uf = serial_fine(w, h, u0, rpr.RPR_FP64)
+            Uf32 = serial_fine(w, h, u0, rpr.RPR_MIXED)
+            E = lambda U: float((U[1:] - Uf[1:]).abs().amax(dim=1).mean())
+            tau = 10.0 * E(Uf32)
+            tt = {"tau": tau, "fp32_serial_fine_error_floor": E(Uf32)}
+            for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
+                r[name]["E_vs_fp64_serial_fine"] = E(Us[name])
+                tt[name] = {"k": None, "s": None, "E": None}
+                for k in range(1, r[name]["K"] + 1):
+                    Uk, rk = solve(prec, k_max=k)
+                    if E(Uk) <= tau:
+                        tt[name] = {"k": k, "s": rk["s"], "E": E(Uk)}
+                        break
+                print(f"extra {w.name} {name}: tau {tau:.2e} reached at k = {tt[name]['k']}", file=sys.stderr,
+                      flush=True)
+            tt["fp64_over_mixed"] = (tt["fp64"]["s"] / tt["mixed"]["s"]) if tt["fp64"]["s"] and tt["mixed"]["s"] \
+                else None
+            r["time_to_tau"] = tt
         return r
 
     res["burgers_d128"] = single(W.BURGERS_D128)
     res["bruss_128x128"] = single(W.BRUSS_128)
-    res["swe_192x192"] = single(W.SWE_192)
+    res["swe_192x192"] = single(W.SWE_192, with_tau=True)
     cb = copy_bandwidth(torch, dev)
     res["swe_192x192"]["F_roofline"] = {"fp64": f_roofline(torch, rpr, W.SWE_192, rpr.RPR_FP64, dev, copy_bw=cb),
                                         "fp32": f_roofline(torch, rpr, W.SWE_192, rpr.RPR_MIXED, dev, copy_bw=cb)}
