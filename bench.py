@@ -464,10 +464,12 @@ def robustness_sweep(torch, rpr, W, dev, n_seeds=10, ms=(2, 3, 4, 6, 8, 12, 16, 
 
 
 def extra_workloads(torch, rpr, W, dev):
-    """One FP64 and one mixed-precision solve of each of the other workloads:
-    time to tolerance, fine state-steps per second and the accuracy of the
-    mixed solve against the FP64 one (per slot max |U_mixed - U_fp64|,
-    averaged over slots).  Progress goes to stderr."""
+    """One FP64 and one mixed-precision solve of each of the other workloads
+    with the global-fit correction, and the same with the refit on the 4
+    nearest pairs: time to tolerance, fine state-steps per second and the
+    accuracy of the mixed solve against the FP64 one (per slot max
+    |U_mixed - U_fp64|, averaged over slots); for shallow water also the time
+    to a common accuracy.  Progress goes to stderr."""
     res = {}
 
     def fine_rate(plan, w, sec):
@@ -496,9 +498,9 @@ def extra_workloads(torch, rpr, W, dev):
         r = {"d": w.d, "N": w.N}
         Us = {}
 
-        def solve(prec, k_max=0):
+        def solve(prec, k_max=0, correction=rpr.RPR_CORR_RANDNET):
             plan = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
-                            A=A, zeta=z, precision=prec, autotune=1, k_max=k_max)
+                            A=A, zeta=z, precision=prec, autotune=1, k_max=k_max, correction=correction, m_nn=4)
             U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -513,6 +515,10 @@ def extra_workloads(torch, rpr, W, dev):
             Us[name], r[name] = solve(prec)
             print(f"extra {w.name} {name}: {r[name]['s']:.3f} s, K = {r[name]['K']}", file=sys.stderr, flush=True)
         r["mixed"]["E_vs_fp64"] = float((Us["mixed"][1:] - Us["fp64"][1:]).abs().amax(dim=1).mean())
+        # the paper's correction: a refit per prediction on the 4 nearest pairs
+        for name, prec in (("nn_fp64", rpr.RPR_FP64), ("nn_mixed", rpr.RPR_MIXED)):
+            Us[name], r[name] = solve(prec, correction=rpr.RPR_CORR_RANDNET_NN)
+            print(f"extra {w.name} {name}: {r[name]['s']:.3f} s, K = {r[name]['K']}", file=sys.stderr, flush=True)
         if with_tau:
             # the common accuracy of the benchmark line: tau = 10 x the error
             # of the FP32 serial fine solution against the FP64 one
@@ -521,6 +527,8 @@ def extra_workloads(torch, rpr, W, dev):
             E = lambda U: float((U[1:] - Uf[1:]).abs().amax(dim=1).mean())
             tau = 10.0 * E(Uf32)
             tt = {"tau": tau, "fp32_serial_fine_error_floor": E(Uf32)}
+            for name in ("nn_fp64", "nn_mixed"):
+                r[name]["E_vs_fp64_serial_fine"] = E(Us[name])
             for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
                 r[name]["E_vs_fp64_serial_fine"] = E(Us[name])
                 tt[name] = {"k": None, "s": None, "E": None}
