@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--solve-only", choices=["burgers_d128", "bruss_128x128", "swe_192x192"], default=None,
+                    help="only run the --extra solves of this workload (for traces)")
     ap.add_argument("--gemm", action="store_true",
                     help="only time the random-feature GEMMs at the workloads' shapes and a compute-bound one")
     ap.add_argument("--robustness", action="store_true",
@@ -111,6 +113,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.gemm:
         print(json.dumps({"feature_gemm": gemm_demo(torch, rpr, dev)}))
+        return
+    if args.solve_only:
+        print(json.dumps({"extra": extra_workloads(torch, rpr, W, dev, only=args.solve_only)}))
         return
     if args.robustness:
         print(json.dumps({"robustness": robustness_sweep(torch, rpr, W, dev)}))
@@ -463,7 +468,7 @@ def robustness_sweep(torch, rpr, W, dev, n_seeds=10, ms=(2, 3, 4, 6, 8, 12, 16, 
     return out
 
 
-def extra_workloads(torch, rpr, W, dev):
+def extra_workloads(torch, rpr, W, dev, only=None):
     """One FP64 and one mixed-precision solve of each of the other workloads
     with the global-fit correction, and the same with the refit on the 4
     nearest pairs: time to tolerance, fine state-steps per second and the
@@ -544,9 +549,12 @@ def extra_workloads(torch, rpr, W, dev):
             r["time_to_tau"] = tt
         return r
 
-    res["burgers_d128"] = single(W.BURGERS_D128)
-    res["bruss_128x128"] = single(W.BRUSS_128)
-    res["swe_192x192"] = single(W.SWE_192, with_tau=True)
+    singles = {"burgers_d128": (W.BURGERS_D128, False), "bruss_128x128": (W.BRUSS_128, False),
+               "swe_192x192": (W.SWE_192, True)}
+    if only is not None:
+        return {only: single(singles[only][0])}
+    for name, (w, tau) in singles.items():
+        res[name] = single(w, with_tau=tau)
     cb = copy_bandwidth(torch, dev)
     res["swe_192x192"]["F_roofline"] = {"fp64": f_roofline(torch, rpr, W.SWE_192, rpr.RPR_FP64, dev, copy_bw=cb),
                                         "fp32": f_roofline(torch, rpr, W.SWE_192, rpr.RPR_MIXED, dev, copy_bw=cb)}
