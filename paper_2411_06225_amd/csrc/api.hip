@@ -200,6 +200,8 @@ struct rpr_plan {
     uint16_t *Ab = nullptr;   // bf16 copy of A (reduced precision)
     uint16_t *Xb = nullptr;   // bf16 pieces of the training inputs (large-tile feature GEMM)
     double *At = nullptr;     // A^T, d x M (the chain's hidden layer)
+    float *Atf = nullptr;     // reduced plans: FP32 copies of A^T and of W for the chain
+    float *Wf = nullptr;
     float *fpart32 = nullptr; // split-K partials of the bf16 feature GEMM
     Ctrl *ctrl = nullptr;
     Ctrl *ctrl_host = nullptr;  // pinned
@@ -261,7 +263,7 @@ static void plan_free(rpr_plan *p)
         if (b) (void)hipFree(b);
     void *bufs[] = {p->U, p->Fv, p->Gc, p->X, p->Y, p->gtmp, p->A, p->zeta, p->Phi, p->fpart, p->Gm, p->Lf,
                     p->Lt, p->Bm, p->W, p->phi, p->part, p->chg_hist, p->u0max, p->ok, p->nrows, p->L_hist,
-                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At, p->Xb};
+                    p->cfail, p->u0bad, p->ctrl, p->Ab, p->fpart32, p->At, p->Xb, p->Atf, p->Wf};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->ctrl_host) (void)hipHostFree(p->ctrl_host);
@@ -349,6 +351,12 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
         // the chain's hidden layer reads the weights column by column (A^T)
         RPR_TRY(dalloc(&p->At, (size_t)M * d));
         RPR_TRY(launch_transpose<double>(p->A, p->At, M, d, nullptr));
+        if (p->esz == 4) {
+            // the chain of a reduced plan reads its weights in FP32 (sums in FP64)
+            RPR_TRY(dalloc(&p->Atf, (size_t)M * d));
+            RPR_TRY((convert<double, float>(p->At, p->Atf, (size_t)M * d, nullptr)));
+            if (!p->nn) RPR_TRY(dalloc(&p->Wf, (size_t)M * d));
+        }
         if (p->feat_bf16) {
             RPR_TRY(dalloc(&p->Ab, 3 * (size_t)M * d));
             RPR_TRY(dalloc(&p->fpart32, (size_t)feat_bf16_splits(d) * N * M));
@@ -367,6 +375,21 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
         RPR_HIP(hipMalloc(&p->gchain, sizeof(ChainArgs<double>)));
     }
     return RPR_OK;
+}
+
+// The chain's weights in state precision: FP64 plans read W and A^T
+// themselves, reduced plans their FP32 copies.
+template <typename T>
+static const T *chain_W(const rpr_plan *p)
+{
+    if constexpr (sizeof(T) == 8) return p->W;
+    else return p->Wf;
+}
+template <typename T>
+static const T *chain_At(const rpr_plan *p)
+{
+    if constexpr (sizeof(T) == 8) return p->At;
+    else return p->Atf;
 }
 
 // Chain mode of a plan's iterations.
@@ -487,6 +510,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
     RPR_TRY(zero(Fv, (size_t)(N + 1) * d, st));
     RPR_TRY(zero(Gc, (size_t)(N + 1) * d, st));
     if (p->W) RPR_TRY(zero(p->W, (size_t)p->M * d, st));
+    if (p->Wf) RPR_TRY(zero(p->Wf, (size_t)p->M * d, st));
 
     // fine propagator: on chip with 1024-thread (short strips) or 512-thread
     // (long strips) work-groups, or tiled through memory (2D grids)
@@ -557,8 +581,8 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         a.gw = tiled_work<T>(p->gwork, (size_t)d);
         a.A = p->A;
         a.zeta = p->zeta;
-        a.W = p->W;
-        a.At = p->At;
+        a.W = chain_W<T>(p);
+        a.At = chain_At<T>(p);
         a.part = p->part;
         a.ctrl = p->ctrl;
         nn_args<T>(p, a);
@@ -791,8 +815,8 @@ static ChainArgs<T> chain_args(rpr_plan *p, double s)
     a.gw = tiled_work<T>(p->gwork, (size_t)p->g.d);
     a.A = p->A;
     a.zeta = p->zeta;
-    a.W = p->W;
-    a.At = p->At;
+    a.W = chain_W<T>(p);
+    a.At = chain_At<T>(p);
     a.part = p->part;
     a.ctrl = p->ctrl;
     a.L_hist = p->L_hist;
@@ -859,6 +883,7 @@ static rpr_status phase_model(rpr_plan *p, double inv_s, hipStream_t st)
     RPR_TRY(launch_stats<T>(N, M, d, p->Phi, Y, p->ok, p->Gm, p->Bm, p->nrows, st));
     RPR_TRY(launch_ridge_solve(M, d, p->Gm, p->lambda, p->Lf, p->Lt, p->W, p->Bm, p->cfail, &p->ctrl->chol_fail,
                                &p->ctrl->done, st));
+    if constexpr (sizeof(T) == 4) RPR_TRY((convert<double, float>(p->W, p->Wf, (size_t)M * d, st)));
     return RPR_OK;
 }
 

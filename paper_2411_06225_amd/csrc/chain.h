@@ -30,8 +30,9 @@ struct ChainArgs {
     double *phi;               // M: hidden layer of the current slot
     double *hpart;             // grid x M: per-work-group partial sums of A x / s
     TiledWork<T> gw;           // work arrays of the tiled coarse solver (d values each)
-    const double *A, *zeta, *W;
-    const double *At;          // d x M: A^T
+    const double *A, *zeta;
+    const T *W;                // M x d readout weights (state precision: FP32 copies in reduced plans)
+    const T *At;               // d x M: A^T (state precision)
     // nearest-neighbour mode: the store of every pair so far (rows 0 ..
     // ctrl->nn_rows + *nrows; the last *nrows are this iteration's)
     int m_nn;                  // neighbours per prediction

@@ -105,7 +105,7 @@ __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *_
 #pragma unroll
                     for (int k = 0; k < CB4; ++k) {
                         const int j = cb + k;
-                        wv4[u][k] = (m < a.M && j < c1) ? a.At[(size_t)j * a.M + m] : 0.0;
+                        wv4[u][k] = (m < a.M && j < c1) ? double(a.At[(size_t)j * a.M + m]) : 0.0;
                     }
                 }
 #pragma unroll
@@ -498,7 +498,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
 #pragma unroll
                             for (int q = 0; q < TPT; ++q) {
                                 const int j = jb + WL * q + lane;
-                                wr[u][q] = (m < a.M && j < j1) ? a.W[(size_t)m * d + j] : 0.0;
+                                wr[u][q] = (m < a.M && j < j1) ? double(a.W[(size_t)m * d + j]) : 0.0;
                             }
                         }
 #pragma unroll
