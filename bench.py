@@ -22,7 +22,7 @@ against the FP64 serial fine solution is <= tau), and the CPU oracle timed
 on the host cores on the same workload.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline] [--no-mixed]
-                    [--extra] [--copy-calibration] [--f-only swe_192x192]
+                    [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
 (Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems;
@@ -93,7 +93,7 @@ def parse():
                     help="only time the random-feature GEMMs at the workloads' shapes and a compute-bound one")
     ap.add_argument("--robustness", action="store_true",
                     help="only run the sweep over neighbour counts, neurons and weight draws (App. D)")
-    ap.add_argument("--f-only", choices=["swe_192x192"], default=None,
+    ap.add_argument("--f-only", choices=["swe_192x192", "bruss_128x128"], default=None,
                     help="only time the fine propagator of this workload in FP64 and FP32 (for counter runs)")
     return ap.parse_args()
 
@@ -121,7 +121,7 @@ def main():
         print(json.dumps({"robustness": robustness_sweep(torch, rpr, W, dev)}))
         return
     if args.f_only:
-        wf = W.SWE_192
+        wf = W.WORKLOADS[args.f_only]
         cb = copy_bandwidth(torch, dev)
         res = {"workload": wf.name, "F_roofline": {
             "fp64": f_roofline(torch, rpr, wf, rpr.RPR_FP64, dev, steps=args.steps, copy_bw=cb),
@@ -325,6 +325,10 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s (AMD specification)
 #            the FP32 compensation)                          4 (FP32: 6)
 # The one-cell halo rows and columns a tile re-reads are not counted.
 TILED_ACCESSES_PER_DOF_STEP = {8: 17, 4: 19}
+# The 5-point Laplacian systems take one pass per RK4 step instead: read u,
+# write u (+ read and write the FP32 compensation); the 4-cell halo a tile
+# re-reads is not counted.
+FUSED_ACCESSES_PER_DOF_STEP = {8: 2, 4: 4}
 
 
 def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
@@ -339,21 +343,26 @@ def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
     Y = torch.empty_like(X)
     dt = (w.tN - w.t0) / w.N / w.F[1]
     stream = torch.cuda.current_stream()
-    rpr.rpr_propagate(h, w.d, w.F[0], 2, prec, dt, w.N, X, Y, stream)
+    # the tiled form, also where a state would fit one work-group's LDS
+    rpr.rpr_propagate(h, w.d, w.F[0], 2, prec, dt, w.N, X, Y, stream, threads=256)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record(stream)
-    rpr.rpr_propagate(h, w.d, w.F[0], steps, prec, dt, w.N, X, Y, stream)
+    rpr.rpr_propagate(h, w.d, w.F[0], steps, prec, dt, w.N, X, Y, stream, threads=256)
     ev[1].record(stream)
     torch.cuda.synchronize()
     sec = ev[0].elapsed_time(ev[1]) / 1e3
-    bytes_ = w.N * w.d * steps * TILED_ACCESSES_PER_DOF_STEP[esz] * esz
+    fused = w.kind != rpr.RPR_SWE2D and w.F[0] == 4
+    acc = (FUSED_ACCESSES_PER_DOF_STEP if fused else TILED_ACCESSES_PER_DOF_STEP)[esz]
+    bytes_ = w.N * w.d * steps * acc * esz
     achieved = bytes_ / sec
+    kernel = ("k_prop_rk4_fused (fine RK4, one launch per step)" if fused
+              else "k_prop_tiled (fine RK4, one launch per stage)")
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "kernel": "k_prop_tiled (fine RK4, one launch per stage)",
+            "frac": achieved / HBM_PEAK, "kernel": kernel,
             "measured_copy_GBps": copy_bw / 1e9 if copy_bw else None,
             "frac_of_copy": achieved / copy_bw if copy_bw else None,
             "launch": {"slots": w.N, "steps": steps, "ms_per_step": sec * 1e3 / steps,
-                       "bytes_per_dof_step": TILED_ACCESSES_PER_DOF_STEP[esz] * esz}}
+                       "bytes_per_dof_step": acc * esz}}
 
 
 BF16_MFMA_PEAK = 2.5e15  # MI355X dense bf16 matrix FLOP/s (AMD specification)

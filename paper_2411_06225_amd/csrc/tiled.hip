@@ -1,6 +1,7 @@
 // tiled.hip -- the propagators F and G over one slice (Sec. 2) for slot
-// states too large for one work-group: one launch per RK stage over the
-// 64 x 16-cell tiles of every slot state (tiledprop.h).
+// states too large for one work-group: passes over the 64 x 16-cell tiles of
+// every slot state (tiledprop.h), one per RK stage, or one per RK4 step for
+// the 5-point Laplacian systems.
 #include "tiledprop.h"
 
 namespace rpr {
@@ -27,6 +28,26 @@ __global__ __launch_bounds__(TT_THREADS) void k_prop_tiled(Geom g, int method, l
     stage_tile<KIND, T, STAGE>(g, tile, dt, io, reinterpret_cast<T *>(lds_raw));
 }
 
+// One whole RK4 step (rk4_tile_fused) of a tile of slot b; the state
+// alternates between the work arrays u and ya, in on the first step and out
+// after the last.
+template <int KIND, typename T>
+__global__ __launch_bounds__(TT_THREADS) void k_prop_rk4_fused(Geom g, long long step, long long steps, double dt,
+                                                               int n, const T *__restrict__ in, T *__restrict__ out,
+                                                               TiledWork<T> w, const int *__restrict__ ctrl)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int tile, b;
+    tile_of_block((int)blockIdx.x, tiles_of(g), n, tile, b);
+    if (ctrl != nullptr && (ctrl[2] != 0 || b < ctrl[0])) return;
+    const size_t off = (size_t)b * g.d;
+    T *buf[2] = {w.u + off, w.ya + off};
+    const T *src = step == 0 ? in + off : buf[(step - 1) & 1];
+    T *dst = step == steps - 1 ? out + off : buf[step & 1];
+    rk4_tile_fused<KIND, T>(g, tile, dt, src, dst, w.cmp ? w.cmp + off : nullptr, step == 0 ? 1 : 0,
+                            reinterpret_cast<T *>(lds_raw));
+}
+
 template <int KIND, typename T>
 rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
                                   const TiledWork<T> &w, const int *ctrl, hipStream_t st)
@@ -40,6 +61,19 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
         const dim3 grid((unsigned)(tiles_of(g) * n));
         const size_t lds = tiled_lds(g, sizeof(T));
         const long long ns = (long long)steps;
+        if constexpr (KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D) {
+            if (method == RPR_RK4) {
+                // a whole step per pass: the Laplacian right-hand side is
+                // cheap to recompute on a 4-cell halo
+                const size_t flds = rk4_fused_lds(g, sizeof(T));
+                for (long long s = 0; s < ns; ++s) {
+                    hipLaunchKernelGGL((k_prop_rk4_fused<KIND, T>), grid, dim3(TT_THREADS), flds, st, g, s, ns, dt,
+                                       n, in, out, w, ctrl);
+                    RPR_HIP(hipGetLastError());
+                }
+                return RPR_OK;
+            }
+        }
         for (long long s = 0; s < ns; ++s) {
             if (method == RPR_RK4) {
                 hipLaunchKernelGGL((k_prop_tiled<KIND, T, 1>), grid, dim3(TT_THREADS), lds, st, g, method, s, ns, dt,

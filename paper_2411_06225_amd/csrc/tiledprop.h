@@ -226,6 +226,14 @@ __device__ __forceinline__ void swe_tile(const Geom &g, const int x0, const int 
     }
 }
 
+// The boundary of each system, as the geometry records it: the Burgers
+// equation and the Brusselator wrap, the other systems have walls.
+template <int KIND>
+constexpr bool kind_periodic()
+{
+    return KIND == RPR_BURGERS1D || KIND == RPR_BRUSS2D;
+}
+
 // The tile of the stage input with its one-cell halo goes to LDS; each wave
 // copies whole rows (one cell per lane, the boundary rule applied to the
 // row index), the two halo columns follow in one pass.  Every load of the
@@ -245,7 +253,7 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int tile, const 
     constexpr bool Y_IS_U = STAGE <= 1;                // Euler and the first RK4 stage read u itself
     static_assert(TT_X == 64 && NH <= TT_THREADS, "tile shape");
     const int nx = g.nx, ny = g.ny, nc = g.nc;
-    const bool per = g.periodic != 0;
+    constexpr bool per = kind_periodic<KIND>();
     const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
@@ -417,7 +425,7 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
     constexpr int RN = ERX * ERY;
     constexpr bool KAHAN = sizeof(T) == 4;
     const int nx = g.nx, ny = g.ny, nc = g.nc;
-    const bool per = g.periodic != 0;
+    constexpr bool per = kind_periodic<KIND>();
     const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
     const int gx0 = x0 - EH, gy0 = y0 - EH;  // domain cell of region cell (0, 0)
     T *buf[2] = {lds, lds + NS * RN};
@@ -498,6 +506,242 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
         }
     }
     __syncthreads();  // the region buffers are reused by the next tile
+}
+
+// One classical RK4 step of one tile in a single pass, for the 5-point
+// Laplacian systems (a cheap right-hand side, so the step is bound by
+// memory, and recomputing a halo costs less than a pass per stage): the tile
+// is loaded with an RH-cell halo (cut at walls, wrapped when periodic),
+// stage s = 1..3 updates the region shrunk by s cells on every side that is
+// not a wall, stage 4 the tile's own cells.  Lane l of wavefront v holds the
+// tile cells (l, 4 v .. 4 v + 3) and the halo cells t + 256 r (r < 3) of the
+// region in registers (state, stage input, slope sum and FP32 compensation
+// of the tile cells), so a tile cell reads only its west and east neighbours
+// and, at the ends of its column, one north or south neighbour from LDS; the
+// stage inputs live in one LDS buffer, rewritten between two barriers.  Per
+// cell the arithmetic is that of stage_tile<KIND, T, 1..4>.
+constexpr int RH = 4;
+constexpr int RRX = TT_X + 2 * RH, RRY = TT_Y + 2 * RH, RRN = RRX * RRY;
+constexpr int RSB = RRN + 2 * RRX;                        // species stride: one padding row above and below
+constexpr int RHALO = RRN - TT_X * TT_Y;                  // halo cells of the region
+constexpr int ROWN = TT_Y / (TT_THREADS / 64);            // tile cells per thread (a column of them)
+constexpr int RHPT = (RHALO + TT_THREADS - 1) / TT_THREADS;  // halo cells per thread
+
+__host__ __device__ inline size_t rk4_fused_lds(const Geom &g, size_t elem)
+{
+    return (size_t)g.ns * RSB * elem;
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ void rk4_tile_fused(const Geom &g, const int tile, const double dt,
+                                               const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ cmp,
+                                               const int cmp_zero, T *__restrict__ lds)
+{
+    static_assert(KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D, "5-point Laplacian systems only");
+    static_assert(TT_X == 64 && ROWN * TT_THREADS == TT_X * TT_Y && RH < 8, "tile shape");
+    constexpr int NS = kind_ns<KIND>();
+    constexpr bool KAHAN = sizeof(T) == 4;
+    const int nx = g.nx, ny = g.ny, nc = g.nc;
+    constexpr bool per = kind_periodic<KIND>();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
+    const int gx0 = x0 - RH, gy0 = y0 - RH;
+    const int cw = per || gx0 > 0, ce = per || gx0 + RRX < nx;
+    const int cs = per || gy0 > 0, cn = per || gy0 + RRY < ny;
+    T *const yb = lds + RRX;  // species sp at yb + sp RSB, region cell e = ly RRX + lx
+    auto gcoord = [&](int l, int o, int n) {  // region index -> domain index, or -1 beyond a wall
+        const int v = o + l;
+        if (per) return ((v % n) + n) % n;
+        return (v < 0 || v >= n) ? -1 : v;
+    };
+
+    // tile cells: region index eo + q RRX, domain coordinates (gxo, gyo[q]),
+    // < 0 beyond a wall; a tile cell past the end of a periodic domain is a
+    // copy of a cell at its start: it takes part in stages 1 to 3 but is
+    // not written (ownm)
+    const int eo = (RH + wv * ROWN) * RRX + RH + lane;
+    const int gxo = gcoord(RH + lane, gx0, nx);
+    int gyo[ROWN], ownm = 0;
+#pragma unroll
+    for (int q = 0; q < ROWN; ++q) {
+        const int ly = RH + wv * ROWN + q;
+        gyo[q] = gcoord(ly, gy0, ny);
+        if (x0 + lane < nx && y0 + ly - RH < ny) ownm |= 1 << q;
+    }
+    auto valid_o = [&](int q) { return gxo >= 0 && gyo[q] >= 0; };
+    // halo cells: region index, domain coordinates, stages they take part in (dh)
+    int eh[RHPT], gxh[RHPT], gyh[RHPT], dh[RHPT];
+#pragma unroll
+    for (int r = 0; r < RHPT; ++r) {
+        const int h = t + TT_THREADS * r;
+        int lx, ly;
+        if (h < 2 * RH * RRX) {  // RH full rows below and above the tile
+            const int br = h / RRX;
+            lx = h - br * RRX;
+            ly = br < RH ? br : br + TT_Y;
+        } else {  // RH columns left and right of the tile
+            const int m = h - 2 * RH * RRX, c = m % (2 * RH);
+            ly = RH + m / (2 * RH);
+            lx = c < RH ? c : c + TT_X;
+        }
+        const bool in = h < RHALO;
+        eh[r] = in ? ly * RRX + lx : 0;
+        const int gx = gcoord(lx, gx0, nx), gy = gcoord(ly, gy0, ny);
+        gxh[r] = gx;
+        gyh[r] = gy;
+        int dep = 3;
+        if (cw) dep = min(dep, lx);
+        if (ce) dep = min(dep, RRX - 1 - lx);
+        if (cs) dep = min(dep, ly);
+        if (cn) dep = min(dep, RRY - 1 - ly);
+        dh[r] = (in && gx >= 0 && gy >= 0) ? dep : -1;
+    }
+
+    // state (and compensation) of the cells; every load is issued before the first use
+    T uo[ROWN][NS], uh[RHPT][NS], cm[ROWN][NS];
+#pragma unroll
+    for (int q = 0; q < ROWN; ++q)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const int idx = valid_o(q) ? sp * nc + gyo[q] * nx + gxo : 0;
+            uo[q][sp] = src[idx];
+            if constexpr (KAHAN) cm[q][sp] = cmp[idx];
+        }
+#pragma unroll
+    for (int r = 0; r < RHPT; ++r)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const int idx = dh[r] >= 0 ? sp * nc + gyh[r] * nx + gxh[r] : 0;
+            uh[r][sp] = src[idx];
+        }
+#pragma unroll
+    for (int q = 0; q < ROWN; ++q)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            if (valid_o(q)) yb[sp * RSB + eo + q * RRX] = uo[q][sp];
+            if constexpr (KAHAN) cm[q][sp] = cmp_zero ? T(0) : cm[q][sp];
+        }
+#pragma unroll
+    for (int r = 0; r < RHPT; ++r)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp)
+            if (dh[r] >= 0) yb[sp * RSB + eh[r]] = uh[r][sp];
+    __syncthreads();
+
+    const T dtT = T(dt), hdt = T(0.5 * dt), dt6 = T(dt / 6.0);
+    // right-hand side of a cell from its stage input c and neighbours; a
+    // cell at a wall takes itself as the missing neighbour
+    auto slope = [&](const int gx, const int gy, const T *c, const T *wr, const T *er, const T *sr, const T *nr,
+                     T *k) {
+        const bool ww = !per && gx == 0, we = !per && gx == nx - 1;
+        const bool ws = !per && gy == 0, wn = !per && gy == ny - 1;
+        T w[NS], ea[NS], sv[NS], nv[NS];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            w[sp] = ww ? c[sp] : wr[sp];
+            ea[sp] = we ? c[sp] : er[sp];
+            sv[sp] = ws ? c[sp] : sr[sp];
+            nv[sp] = wn ? c[sp] : nr[sp];
+        }
+        rhs_cell<KIND, T>(g, c, w, ea, sv, nv, ww, we, ws, wn, k);
+    };
+    // tile cell q from the stage inputs yc of this thread's column
+    auto slope_o = [&](const int q, const T (*yc)[NS], T *k) {
+        T wr[NS], er[NS], sr[NS], nr[NS];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const T *bb = yb + sp * RSB + eo + q * RRX;
+            wr[sp] = bb[-1];
+            er[sp] = bb[1];
+            sr[sp] = q > 0 ? yc[q > 0 ? q - 1 : 0][sp] : bb[-RRX];
+            nr[sp] = q < ROWN - 1 ? yc[q < ROWN - 1 ? q + 1 : 0][sp] : bb[RRX];
+        }
+        slope(gxo, gyo[q], yc[q], wr, er, sr, nr, k);
+    };
+    // halo cell r from LDS
+    auto slope_h = [&](const int r, T *k) {
+        T c[NS], wr[NS], er[NS], sr[NS], nr[NS];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const T *bb = yb + sp * RSB + eh[r];
+            c[sp] = bb[0];
+            wr[sp] = bb[-1];
+            er[sp] = bb[1];
+            sr[sp] = bb[-RRX];
+            nr[sp] = bb[RRX];
+        }
+        slope(gxh[r], gyh[r], c, wr, er, sr, nr, k);
+    };
+
+    T acc[ROWN][NS], yc[ROWN][NS];  // yc: stage input of the tile cells
+#pragma unroll
+    for (int q = 0; q < ROWN; ++q)
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            yc[q][sp] = uo[q][sp];
+            acc[q][sp] = T(0);
+        }
+#pragma unroll
+    for (int st = 1; st <= 3; ++st) {
+        const T cst = st == 3 ? dtT : hdt;
+        T yn[ROWN][NS], yh[RHPT][NS];
+#pragma unroll
+        for (int q = 0; q < ROWN; ++q) {
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) yn[q][sp] = yc[q][sp];
+            if (!valid_o(q)) continue;
+            T k[NS];
+            slope_o(q, yc, k);
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+                acc[q][sp] = st == 1 ? k[sp] : acc[q][sp] + T(2) * k[sp];
+                yn[q][sp] = uo[q][sp] + cst * k[sp];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RHPT; ++r) {
+            if (dh[r] < st) continue;
+            T k[NS];
+            slope_h(r, k);
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) yh[r][sp] = uh[r][sp] + cst * k[sp];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ROWN; ++q) {
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+                if (valid_o(q)) yb[sp * RSB + eo + q * RRX] = yn[q][sp];
+                yc[q][sp] = yn[q][sp];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RHPT; ++r)
+            if (dh[r] >= st)
+#pragma unroll
+                for (int sp = 0; sp < NS; ++sp) yb[sp * RSB + eh[r]] = yh[r][sp];
+        __syncthreads();
+    }
+    // stage 4 on the tile's cells
+#pragma unroll
+    for (int q = 0; q < ROWN; ++q) {
+        if (!((ownm >> q) & 1)) continue;
+        T k[NS];
+        slope_o(q, yc, k);
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const int idx = sp * nc + gyo[q] * nx + gxo;
+            const T inc = dt6 * (acc[q][sp] + k[sp]);
+            if constexpr (KAHAN) {
+                const T yk = inc - cm[q][sp];
+                const T un = uo[q][sp] + yk;
+                cmp[idx] = (un - uo[q][sp]) - yk;
+                dst[idx] = un;
+            } else {
+                dst[idx] = uo[q][sp] + inc;
+            }
+        }
+    }
 }
 
 // stage_tile with the stage chosen at run time.

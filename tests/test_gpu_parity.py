@@ -131,6 +131,8 @@ TILED_CASES = [c for c in PROP_CASES if c[1] != rpr.RPR_BURGERS1D] + [
     ("swe_96x80", rpr.RPR_SWE2D, 96, 80, (0, 1, 0, 1), (9.81,), 30, 2e-4, 4),
     ("diffreact_130x70", rpr.RPR_DIFFREACT2D, 130, 70, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 20, 2e-4, 4),
     ("bruss_80x33_rk1", rpr.RPR_BRUSS2D, 80, 33, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 30, 1e-4, 1),
+    ("bruss_70x37", rpr.RPR_BRUSS2D, 70, 37, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 30, 1e-4, 4),
+    ("diffreact_67x17", rpr.RPR_DIFFREACT2D, 67, 17, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 30, 2e-4, 4),
 ]
 
 
@@ -138,8 +140,9 @@ TILED_CASES = [c for c in PROP_CASES if c[1] != rpr.RPR_BURGERS1D] + [
 @pytest.mark.parametrize("prec", [rpr.RPR_FP64, rpr.RPR_MIXED], ids=["fp64", "fp32"])
 def test_tiled_propagate_matches_oracle(orc, case, prec):
     """The tiled form (states in memory, one pass over 64 x 16-cell tiles
-    per RK stage) on grids with full and ragged tiles, walls and periodic
-    boundaries, several states per launch."""
+    per RK stage, or per RK4 step with a 4-cell halo for the Laplacian
+    systems) on grids with full and ragged tiles, tails of a few cells, walls
+    and periodic boundaries, several states per launch."""
     name, kind, nx, ny, dom, params, steps, dt, method = case
     rng = np.random.default_rng(abs(hash(name)) % 2 ** 32 + 1)
     d = rpr.nspecies(kind) * nx * ny
