@@ -561,7 +561,7 @@ def extra_workloads(torch, rpr, W, dev, only=None):
     singles = {"burgers_d128": (W.BURGERS_D128, False), "bruss_128x128": (W.BRUSS_128, False),
                "swe_192x192": (W.SWE_192, True)}
     if only is not None:
-        return {only: single(singles[only][0])}
+        return {only: single(*singles[only])}
     for name, (w, tau) in singles.items():
         res[name] = single(w, with_tau=tau)
     cb = copy_bandwidth(torch, dev)

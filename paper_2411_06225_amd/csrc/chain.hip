@@ -19,6 +19,8 @@
 // in the device control block, so the host never waits on the sweep.
 #include <hip/hip_cooperative_groups.h>
 
+#include <type_traits>
+
 #include "chain.h"
 #include "slotprop.h"
 #include "tiledprop.h"
@@ -87,37 +89,62 @@ __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *_
     if (wv < nw) {
         const int cpw = (j1 - j0 + nw - 1) / nw;
         const int c0 = j0 + wv * cpw, c1 = min(j1, c0 + cpw);
-        constexpr int MPL = 4, CB4 = 4;  // neurons per lane and pass, columns per load batch
-        for (int mb = 0; mb < a.M; mb += WL * MPL) {
-            double p[MPL];
+        constexpr int MPL = 4;  // neurons per lane and pass
+        // FP32 weights with M even: lane l takes the neuron pairs (2l, 2l + 1)
+        // and (2 WL + 2l, 2 WL + 2l + 1) of each pass, one 8-byte load per pair
+        // and column, and twice the columns per load batch, so that as many
+        // bytes are in flight as with FP64 weights
+        auto pass = [&](auto pair_tag) {
+            constexpr bool PAIR = decltype(pair_tag)::value;
+            constexpr int CB4 = PAIR ? 8 : 4;  // columns per load batch
+            auto neuron = [&](int mb, int u) {
+                return PAIR ? mb + 2 * WL * (u >> 1) + 2 * lane + (u & 1) : mb + lane + WL * u;
+            };
+            for (int mb = 0; mb < a.M; mb += WL * MPL) {
+                double p[MPL];
 #pragma unroll
-            for (int u = 0; u < MPL; ++u) p[u] = 0.0;
-            for (int cb = c0; cb < c1; cb += CB4) {
-                double xv[CB4], wv4[MPL][CB4];
-#pragma unroll
-                for (int k = 0; k < CB4; ++k) {
-                    const int j = cb + k;
-                    xv[k] = j < c1 ? double(x[j]) * a.inv_s : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < MPL; ++u) {
-                    const int m = mb + lane + WL * u;
+                for (int u = 0; u < MPL; ++u) p[u] = 0.0;
+                for (int cb = c0; cb < c1; cb += CB4) {
+                    double xv[CB4], wv4[MPL][CB4];
 #pragma unroll
                     for (int k = 0; k < CB4; ++k) {
                         const int j = cb + k;
-                        wv4[u][k] = (m < a.M && j < c1) ? double(a.At[(size_t)j * a.M + m]) : 0.0;
+                        xv[k] = j < c1 ? double(x[j]) * a.inv_s : 0.0;
                     }
+#pragma unroll
+                    for (int u = 0; u < MPL; u += PAIR ? 2 : 1) {
+                        const int m = neuron(mb, u);
+#pragma unroll
+                        for (int k = 0; k < CB4; ++k) {
+                            const int j = cb + k;
+                            const bool ok = m < a.M && j < c1;
+                            if constexpr (PAIR) {
+                                float2 v = make_float2(0.0f, 0.0f);
+                                if (ok) v = *reinterpret_cast<const float2 *>(a.At + (size_t)j * a.M + m);
+                                wv4[u][k] = v.x;
+                                wv4[u + 1][k] = v.y;
+                            } else {
+                                wv4[u][k] = ok ? double(a.At[(size_t)j * a.M + m]) : 0.0;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < MPL; ++u)
+#pragma unroll
+                        for (int k = 0; k < CB4; ++k) p[u] = fma(wv4[u][k], xv[k], p[u]);
                 }
 #pragma unroll
-                for (int u = 0; u < MPL; ++u)
-#pragma unroll
-                    for (int k = 0; k < CB4; ++k) p[u] = fma(wv4[u][k], xv[k], p[u]);
+                for (int u = 0; u < MPL; ++u) {
+                    const int m = neuron(mb, u);
+                    if (m < a.M) red[wv * a.M + m] = p[u];
+                }
             }
-#pragma unroll
-            for (int u = 0; u < MPL; ++u) {
-                const int m = mb + lane + WL * u;
-                if (m < a.M) red[wv * a.M + m] = p[u];
-            }
+        };
+        if constexpr (sizeof(T) == 4) {
+            if (a.M % 2 == 0) pass(std::true_type{});
+            else pass(std::false_type{});
+        } else {
+            pass(std::false_type{});
         }
     }
     __syncthreads();
@@ -413,8 +440,9 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     const int N = a.N;
 
     // columns of this work-group
-    const int chunk = (d + nwg - 1) / nwg;
-    const int j0 = wg * chunk, j1 = min(d, j0 + chunk);
+    // (an even count, so that FP32 rows of even length start 8-byte aligned)
+    const int chunk = (((d + nwg - 1) / nwg) + 1) & ~1;
+    const int j0 = min(d, wg * chunk), j1 = min(d, j0 + chunk);
 
     const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
     const bool net = a.mode == CHAIN_RANDNET || nn;
@@ -484,40 +512,67 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
             double *red = scratch + ((a.M + 63) / 64) * 64;                // nw x TPT x WL
             for (int m = t; m < a.M; m += B) sphi[m] = a.phi[m];
             __syncthreads();
-            for (int jb = j0; jb < j1; jb += WL * TPT) {
-                if (wv < nw) {
-                    double acc[TPT];
+            // FP32 weights with d even: lane l takes the adjacent columns
+            // jb + 2l, jb + 2l + 1 (one 8-byte load per neuron) instead of
+            // jb + l and jb + WL + l; the chunk bounds are even, so is d
+            bool pair = false;
+            if constexpr (sizeof(T) == 4) pair = d % 2 == 0;
+            auto tile = [&](const int jb, auto pair_tag) {
+                constexpr bool PAIR = decltype(pair_tag)::value;
+                static_assert(TPT == 2 || !PAIR, "a pair is two tiles");
+                double acc[TPT];
 #pragma unroll
-                    for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
-                    // batches of 8 neurons x TPT columns: 16 loads in flight
-                    for (int m0 = wv; m0 < a.M; m0 += 8 * nw) {
-                        double wr[8][TPT];
+                for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
+                // batches of NB neurons x TPT columns: 8 KB per wavefront in
+                // flight (16 FP64 loads, or 16 FP32 pairs)
+                constexpr int NB = PAIR ? 16 : 8;
+                for (int m0 = wv; m0 < a.M; m0 += NB * nw) {
+                    double wr[NB][TPT];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int m = m0 + u * nw;
+                    for (int u = 0; u < NB; ++u) {
+                        const int m = m0 + u * nw;
+                        if constexpr (PAIR) {
+                            const int j = jb + 2 * lane;
+                            float2 v = make_float2(0.0f, 0.0f);
+                            if (m < a.M && j < j1) v = *reinterpret_cast<const float2 *>(a.W + (size_t)m * d + j);
+                            wr[u][0] = v.x;
+                            wr[u][1] = v.y;
+                        } else {
 #pragma unroll
                             for (int q = 0; q < TPT; ++q) {
                                 const int j = jb + WL * q + lane;
                                 wr[u][q] = (m < a.M && j < j1) ? double(a.W[(size_t)m * d + j]) : 0.0;
                             }
                         }
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int m = m0 + u * nw;
-                            const double ph = m < a.M ? sphi[m] : 0.0;
-#pragma unroll
-                            for (int q = 0; q < TPT; ++q) acc[q] = fma(wr[u][q], ph, acc[q]);
-                        }
                     }
 #pragma unroll
-                    for (int q = 0; q < TPT; ++q) red[(wv * TPT + q) * WL + lane] = acc[q];
+                    for (int u = 0; u < NB; ++u) {
+                        const int m = m0 + u * nw;
+                        const double ph = m < a.M ? sphi[m] : 0.0;
+#pragma unroll
+                        for (int q = 0; q < TPT; ++q) acc[q] = fma(wr[u][q], ph, acc[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < TPT; ++q) red[(wv * TPT + q) * WL + lane] = acc[q];
+            };
+            for (int jb = j0; jb < j1; jb += WL * TPT) {
+                if (wv < nw) {
+                    if constexpr (sizeof(T) == 4) {
+                        if (pair) tile(jb, std::true_type{});
+                        else tile(jb, std::false_type{});
+                    } else {
+                        tile(jb, std::false_type{});
+                    }
                 }
                 __syncthreads();
                 for (int q = wv; q < TPT && wv < nw; q += nw) {
                     const int j = jb + WL * q + lane;
                     if (j < j1) {
+                        // partial sums of column j: tile q, lane l, or the pair layout
+                        const int x = j - jb, qq = pair ? (x & 1) : q, ll = pair ? (x >> 1) : lane;
                         double c = 0.0;
-                        for (int w = 0; w < nw; ++w) c += red[(w * TPT + q) * WL + lane];
+                        for (int w = 0; w < nw; ++w) c += red[(w * TPT + qq) * WL + ll];
                         const T gv = a.gtmp[j];
                         const T unew = T(double(gv) + c);
                         emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
