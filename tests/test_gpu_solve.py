@@ -282,12 +282,21 @@ def test_full_diffreact_workload_matches_stored_oracle_run():
     assert Ef <= g["E_vs_serial_fine"] * 1.000001 + 1e-12
 
 
-@pytest.mark.parametrize("w", [W.BURGERS_D128_STABLE, DR_SMALL], ids=["burgers", "diffreact"])
-def test_mixed_precision_solve_stays_within_fp32_error_of_oracle(orc, w):
+# odd d and odd M: the sweep reads its FP32 weights one value per lane
+BURGERS_ODD = W.small(W.BURGERS_D128, nx=33, N=8, tN=2.0, F=(4, 200), G=(1, 20), M=25, params=(0.02,))
+MIXED_CASES = [("burgers", W.BURGERS_D128_STABLE), ("diffreact", DR_SMALL), ("burgers_odd_d_odd_M", BURGERS_ODD),
+               ("diffreact_24x20_tiled", tiled(DR_RAGGED)), ("bruss_32x32_tiled", tiled(BRUSS_SMALL))]
+
+
+@pytest.mark.parametrize("name,w", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_precision_solve_stays_within_fp32_error_of_oracle(orc, name, w):
     # FP32 states change the run itself: with eps near the FP32 error floor of
     # the fine solver the iteration count can grow, so the check is on accuracy.
     # Bound: the FP64 oracle's serial fine solution is matched to 1e-4 relative,
-    # a hundred times the FP32 floor of these runs (~1e-6).
+    # a hundred times the FP32 floor of these runs (~1e-6).  The FP32 sweep
+    # reads its weights in adjacent pairs where d (readout) and M (hidden
+    # layer) are even, one value per lane otherwise; tiled plans take the
+    # one-pass RK4 kernel for the Laplacian systems.
     Ug, ig = gpu_solve(w, prec=rpr.RPR_MIXED)
     pb = orc.problem(w.kind, w.nx, w.ny, w.domain, w.params)
     T = (w.tN - w.t0) / w.N
