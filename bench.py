@@ -218,6 +218,9 @@ def main():
         "L_hist": [int(v) for v in Lh],
         "E_vs_serial_fine": E,
         "dof_steps_per_s": value * w.d,
+        # device time of the last timed solve by phase (events between the phases)
+        "phases_s": {"total": info["t_total"], "fine": info["t_fine"], "model": info["t_model"],
+                     "sweep": info["t_sweep"]},
         "roofline": roofline,
     }
 

@@ -67,7 +67,7 @@ class rpr_options(C.Structure):
 class rpr_info(C.Structure):
     _fields_ = [("K", C.c_int32), ("L_final", C.c_int32), ("converged", C.c_int32), ("rows_used", C.c_int32),
                 ("nonfinite_rows", C.c_int32), ("chol_fail", C.c_int32), ("input_scale", C.c_double),
-                ("t_total", C.c_double)]
+                ("t_total", C.c_double), ("t_fine", C.c_double), ("t_model", C.c_double), ("t_sweep", C.c_double)]
 
 
 _lib = None

@@ -239,6 +239,7 @@ struct rpr_plan {
     OnchipShape bshF{}, bshG{};
     int bgrid = 0, bM = 0, bkmax = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> pev;  // phase boundaries of a burst of iterations (1 + 3 per iteration)
     rpr_info info{};
     std::vector<int> Lh;
     std::vector<double> ch;
@@ -273,6 +274,7 @@ static void plan_free(rpr_plan *p)
     if (p->gchain) (void)hipFree(p->gchain);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
+    for (hipEvent_t e : p->pev) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -901,6 +903,7 @@ static rpr_status phase_finish(rpr_plan *p, double *U_out, float ms, hipStream_t
     p->info.nonfinite_rows = c.nonfinite;
     p->info.chol_fail = c.chol_fail;
     p->info.t_total = ms * 1e-3;
+    p->info.t_fine = p->info.t_model = p->info.t_sweep = -1.0;
     p->Lh.assign(N + 1, 0);
     p->ch.assign(N + 1, 0.0);
     RPR_HIP(hipMemcpyAsync(p->Lh.data(), p->L_hist, sizeof(int) * (c.k + 1), hipMemcpyDeviceToHost, st));
@@ -945,24 +948,47 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     RPR_HIP(hipStreamSynchronize(st));
     if (bad) return fail(RPR_ERR_NONFINITE, "u0 has non-finite entries");
 
+    // phase events (eager iterations only): pev[0] after the set-up or at
+    // the start of a burst, then after the fine solves, the model and the
+    // sweep of each iteration of the burst
+    const bool timed = !p->use_graph;
+    const size_t n_ev = 1 + 3 * (size_t)(p->poll < p->k_max ? p->poll : p->k_max);  // bursts are at most this long
+    if (timed && p->pev.size() < n_ev) {
+        for (size_t e = p->pev.size(); e < n_ev; ++e) {
+            hipEvent_t ev = nullptr;
+            RPR_HIP(hipEventCreate(&ev));
+            p->pev.push_back(ev);
+        }
+    }
+    double t_fine = 0.0, t_model = 0.0, t_sweep = 0.0;
+    auto span = [&](int e0, int e1) -> double {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p->pev[e0], p->pev[e1]);
+        return ms * 1e-3;
+    };
     RPR_HIP(hipEventRecord(p->ev0, st));
     ChainArgs<T> a;
     RPR_TRY(phase_setup<T>(p, u0, umax, st, &a));
+    if (timed) RPR_HIP(hipEventRecord(p->pev[0], st));
     const int *ctrl_i = reinterpret_cast<const int *>(p->ctrl);
     // one iteration: fine solves of the unfinished slots (Fv[i] = F(U[i-1])),
     // the model, the predictor-corrector sweep with the stopping rule
     // `s` is the stream the iteration is enqueued on (the caller's, or the
     // capture stream); inside a graph the chain runs as one work-group with
     // plain barriers, so the graph holds no grid-wide barrier
-    auto iteration = [&](hipStream_t s, bool graph) -> rpr_status {
+    // (ev: the first of the iteration's three phase events, or -1)
+    auto iteration = [&](hipStream_t s, bool graph, int ev) -> rpr_status {
         const TiledWork<T> fw = tiled_work<T>(p->fwork, (size_t)N * d);
         RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, s, p->shF.maxt,
                                     p->fwork ? &fw : nullptr));
+        if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev], s));
         RPR_TRY(phase_model<T>(p, a.inv_s, s));
+        if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 1], s));
         if (graph)
             RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->gchain), 1, g, p->shG, p->M, s));
         else
             RPR_TRY(launch_chain<T>(a, p->shG, p->nwg, s));
+        if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 2], s));
         return RPR_OK;
     };
     if (p->use_graph) RPR_HIP(hipMemcpyAsync(p->gchain, &a, sizeof(a), hipMemcpyHostToDevice, st));
@@ -971,33 +997,56 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     // is raised return at once
     if (p->use_graph && (!p->graph_exec || p->graph_s != a.inv_s)) {
         RPR_TRY(capture_block(p, [&]() -> rpr_status {
-            for (int b = 0; b < p->poll; ++b) RPR_TRY(iteration(p->cap_stream, true));
+            for (int b = 0; b < p->poll; ++b) RPR_TRY(iteration(p->cap_stream, true, -1));
             return RPR_OK;
         }));
         p->graph_s = a.inv_s;
     }
     int k = 0;
     bool done = false;
+    bool first = true;
     while (k < p->k_max && !done) {
         const int burst = (p->k_max - k) < p->poll ? (p->k_max - k) : p->poll;
         if (p->use_graph) {
             RPR_HIP(hipGraphLaunch(p->graph_exec, st));
             k += p->poll;
         } else {
+            // the first burst starts at the set-up's event (its time goes to the
+            // sweeps); later ones at a new one
+            if (!first) RPR_HIP(hipEventRecord(p->pev[0], st));
             for (int b = 0; b < burst; ++b) {
-                RPR_TRY(iteration(st, false));
+                RPR_TRY(iteration(st, false, 1 + 3 * b));
                 ++k;
             }
         }
         RPR_HIP(hipMemcpyAsync(p->ctrl_host, p->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
         RPR_HIP(hipStreamSynchronize(st));
         done = p->ctrl_host->done != 0;
+        if (timed) {
+            if (first) {
+                float ms = 0.f;
+                RPR_HIP(hipEventElapsedTime(&ms, p->ev0, p->pev[0]));
+                t_sweep += ms * 1e-3;
+            }
+            for (int b = 0; b < burst; ++b) {
+                const int e = 1 + 3 * b;
+                t_fine += span(e - 1, e);
+                t_model += span(e, e + 1);
+                t_sweep += span(e + 1, e + 2);
+            }
+        }
+        first = false;
     }
     RPR_HIP(hipEventRecord(p->ev1, st));
     RPR_HIP(hipEventSynchronize(p->ev1));
     float ms = 0.f;
     RPR_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
     RPR_TRY(phase_finish<T>(p, U_out, ms, st));
+    if (timed) {
+        p->info.t_fine = t_fine;
+        p->info.t_model = t_model;
+        p->info.t_sweep = t_sweep;
+    }
     RPR_HIP(hipStreamSynchronize(st));
     return p->ctrl_host->L >= N ? RPR_OK : RPR_NOT_CONVERGED;
 }

@@ -241,6 +241,19 @@ def test_state_too_large_for_one_work_group_is_solved_tiled(orc):
     assert_same_run(Ug, ig, Uo, io, w.N)
 
 
+def test_phase_times_add_up_to_the_solve():
+    # eager plans time the fine solves, the model and the sweeps with events
+    # between the phases; only host polls between bursts fall outside them
+    _, info = gpu_solve(DR_SMALL)
+    parts = info["t_fine"] + info["t_model"] + info["t_sweep"]
+    print({k: info[k] for k in ("t_total", "t_fine", "t_model", "t_sweep")})
+    assert min(info["t_fine"], info["t_model"], info["t_sweep"]) > 0.0
+    assert 0.5 * info["t_total"] <= parts <= info["t_total"] * (1 + 1e-6)
+    # a captured graph has no events between its phases
+    _, ginfo = gpu_solve(DR_SMALL, graph=1)
+    assert ginfo["t_fine"] == ginfo["t_model"] == ginfo["t_sweep"] == -1.0 and ginfo["t_total"] > 0.0
+
+
 def test_repeated_execute_is_bitwise_reproducible():
     w = DR_RAGGED
     a, _ = gpu_solve(w)
