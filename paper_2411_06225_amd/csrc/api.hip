@@ -590,26 +590,61 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         nn_args<T>(p, a);
         if (p->nn) RPR_TRY(zero(p->nrows, 1, st));  // the trials run with an empty store
         float best = 1e30f;
-        int best_n = p->nwg;
+        int best_n = p->nwg, best_gt = p->shG.maxt;
+        // coarse-solver shapes: the plan's, and for an on-chip G of free
+        // thread count the 512-thread one too (longer strips, twice the
+        // registers per thread)
+        OnchipShape gshapes[2] = {p->shG, p->shG};
+        int n_shapes = 1;
+        if (p->G.threads == 0 && p->shG.maxt == 1024 && onchip_shape(g, p->esz, &gshapes[1], 512) &&
+            check_threads(g, p->esz, 512) == RPR_OK)
+            n_shapes = 2;
         const int cands[] = {1, cus / 4, cus / 2, cus};
-        for (int c : cands) {
-            if (c < 1 || c > max_wg) continue;
-            if (p->M > 0 && c > 1 && c - 1 > p->M && c != cus) continue;
-            // the tiled coarse solver spreads its tiles over the grid: one
-            // work-group would take all of them in turn (seconds per sweep)
-            if (p->shG.maxt == TILED_THREADS && c < tiles_of(g)) continue;
-            float ms = 0.f;
-            hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
-            RPR_TRY(launch_chain<T>(a, p->shG, c, st));
-            RPR_HIP(hipEventRecord(e0, st));
-            hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
-            RPR_TRY(launch_chain<T>(a, p->shG, c, st));
-            RPR_HIP(hipEventRecord(e1, st));
-            RPR_HIP(hipEventSynchronize(e1));
-            RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; best_n = c; }
+        for (int s = 0; s < n_shapes; ++s) {
+            const OnchipShape &sh = gshapes[s];
+            int mwg = max_wg;  // grids beyond the plan's max_wg have no partial-sum rows
+            if (s > 0) {
+                int m2 = 0;
+                RPR_TRY(launch_chain<T>(a, sh, 0, nullptr, &m2));
+                mwg = std::min(mwg, m2);
+            }
+            for (int c : cands) {
+                if (c < 1 || c > mwg) continue;
+                if (p->M > 0 && c > 1 && c - 1 > p->M && c != cus) continue;
+                // the tiled coarse solver spreads its tiles over the grid: one
+                // work-group would take all of them in turn (seconds per sweep)
+                if (sh.maxt == TILED_THREADS && c < tiles_of(g)) continue;
+                float ms = 0.f;
+                hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
+                RPR_TRY(launch_chain<T>(a, sh, c, st));
+                RPR_HIP(hipEventRecord(e0, st));
+                hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, st, p->ctrl, p->L_hist, p->chg_hist);
+                RPR_TRY(launch_chain<T>(a, sh, c, st));
+                RPR_HIP(hipEventRecord(e1, st));
+                RPR_HIP(hipEventSynchronize(e1));
+                RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; best_n = c; best_gt = sh.maxt; }
+            }
         }
         g_tune[kc.str()] = best_n;
+        g_tune[kc.str() + ":G"] = best_gt;
+    }
+    // the coarse solver's work-group size (tuned only where G's is free)
+    const auto gt = g_tune.find(kc.str() + ":G");
+    if (p->G.threads == 0 && p->shG.maxt == 1024 && gt != g_tune.end() && gt->second == 512) {
+        OnchipShape sh;
+        if (onchip_shape(g, p->esz, &sh, 512) && check_threads(g, p->esz, 512) == RPR_OK) {
+            int m2 = 0;
+            ChainArgs<T> q{};
+            q.g = g;
+            q.M = p->M;
+            q.mode = chain_mode(p);
+            RPR_TRY(launch_chain<T>(q, sh, 0, nullptr, &m2));
+            if (m2 >= 1) {
+                p->shG = sh;
+                max_wg = std::min(max_wg, m2);
+            }
+        }
     }
     p->nwg = g_tune[kc.str()] < max_wg ? g_tune[kc.str()] : max_wg;
     if (!haveF || !haveC) tune_store();

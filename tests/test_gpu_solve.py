@@ -241,6 +241,27 @@ def test_state_too_large_for_one_work_group_is_solved_tiled(orc):
     assert_same_run(Ug, ig, Uo, io, w.N)
 
 
+@pytest.mark.parametrize("name,w", [("diffreact_32x32", DR_SMALL), ("swe_16x16", SWE_SMALL)],
+                         ids=["diffreact_32x32", "swe_16x16"])
+def test_autotuned_plan_matches_oracle(orc, name, w):
+    """The autotuner picks the fine kernel, the sweep's grid and the coarse
+    solver's work-group size by timing them; the run is the oracle's (the
+    grid only changes the order of the hidden layer's partial sums)."""
+    Ug, ig = gpu_solve(w, autotune=1)
+    Uo, io = orc_solve(orc, w)
+    assert_same_run(Ug, ig, Uo, io, w.N)
+
+
+def test_autotuned_full_diffreact_workload_matches_stored_oracle_run():
+    g = json.load(open(os.path.join(GOLDEN, "diffreact_64x64_oracle.json")))
+    w = W.DIFFREACT_64
+    Ug, ig = gpu_solve(w, autotune=1)
+    assert ig["K"] == g["K"] and ig["L_hist"].tolist() == g["L_hist"] and ig["rows_used"] == g["rows_used"]
+    idx = np.asarray(g["sample_index"])
+    err = np.abs(Ug[:, idx] - np.asarray(g["U_sample"])).max() / g["U_absmax"]
+    assert err <= w.N * 1e-12, err
+
+
 def test_phase_times_add_up_to_the_solve():
     # eager plans time the fine solves, the model and the sweeps with events
     # between the phases; only host polls between bursts fall outside them
