@@ -511,40 +511,52 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
 // One classical RK4 step of one tile in a single pass, for the 5-point
 // Laplacian systems (a cheap right-hand side, so the step is bound by
 // memory, and recomputing a halo costs less than a pass per stage): the tile
-// is loaded with an RH-cell halo (cut at walls, wrapped when periodic),
-// stage s = 1..3 updates the region shrunk by s cells on every side that is
-// not a wall, stage 4 the tile's own cells.  Lane l of wavefront v holds the
-// tile cells (l, 4 v .. 4 v + 3) and the halo cells t + 256 r (r < 3) of the
-// region in registers (state, stage input, slope sum and FP32 compensation
+// (64 x FY cells, NT threads) is loaded with an RH-cell halo (cut at walls,
+// wrapped when periodic), stage s = 1..3 updates the region shrunk by s
+// cells on every side that is not a wall, stage 4 the tile's own cells.
+// Lane l of wavefront v holds the tile cells (l, ROWN v .. ROWN v + ROWN - 1)
+// and the halo cells t + NT r of the region in registers (state, stage input, slope sum and FP32 compensation
 // of the tile cells), so a tile cell reads only its west and east neighbours
 // and, at the ends of its column, one north or south neighbour from LDS; the
 // stage inputs live in one LDS buffer, rewritten between two barriers.  Per
 // cell the arithmetic is that of stage_tile<KIND, T, 1..4>.
-constexpr int RH = 4;
-constexpr int RRX = TT_X + 2 * RH, RRY = TT_Y + 2 * RH, RRN = RRX * RRY;
-constexpr int RSB = RRN + 2 * RRX;                        // species stride: one padding row above and below
-constexpr int RHALO = RRN - TT_X * TT_Y;                  // halo cells of the region
-constexpr int ROWN = TT_Y / (TT_THREADS / 64);            // tile cells per thread (a column of them)
-constexpr int RHPT = (RHALO + TT_THREADS - 1) / TT_THREADS;  // halo cells per thread
+constexpr int RH = 4, RRX = TT_X + 2 * RH;
+template <int FY>
+struct FusedTile {
+    static constexpr int RRY = FY + 2 * RH, RRN = RRX * RRY;
+    static constexpr int RSB = RRN + 2 * RRX;  // species stride: one padding row above and below
+    static constexpr int RHALO = RRN - TT_X * FY;  // halo cells of the region
+};
 
-__host__ __device__ inline size_t rk4_fused_lds(const Geom &g, size_t elem)
+template <int FY>
+__host__ __device__ inline int fused_tiles_of(const Geom &g)
 {
-    return (size_t)g.ns * RSB * elem;
+    return tiles_x(g) * ((g.ny + FY - 1) / FY);
 }
 
-template <int KIND, typename T>
+template <int FY>
+__host__ __device__ inline size_t rk4_fused_lds(const Geom &g, size_t elem)
+{
+    return (size_t)g.ns * FusedTile<FY>::RSB * elem;
+}
+
+template <int KIND, typename T, int FY, int NT>
 __device__ __forceinline__ void rk4_tile_fused(const Geom &g, const int tile, const double dt,
                                                const T *__restrict__ src, T *__restrict__ dst, T *__restrict__ cmp,
                                                const int cmp_zero, T *__restrict__ lds)
 {
     static_assert(KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D, "5-point Laplacian systems only");
-    static_assert(TT_X == 64 && ROWN * TT_THREADS == TT_X * TT_Y && RH < 8, "tile shape");
+    constexpr int RRY = FusedTile<FY>::RRY, RRN = FusedTile<FY>::RRN, RSB = FusedTile<FY>::RSB;
+    constexpr int RHALO = FusedTile<FY>::RHALO;
+    constexpr int ROWN = FY / (NT / 64);                // tile cells per thread (a column of them)
+    constexpr int RHPT = (RHALO + NT - 1) / NT;         // halo cells per thread
+    static_assert(TT_X == 64 && ROWN * NT == TT_X * FY && RH < 8, "tile shape");
     constexpr int NS = kind_ns<KIND>();
     constexpr bool KAHAN = sizeof(T) == 4;
     const int nx = g.nx, ny = g.ny, nc = g.nc;
     constexpr bool per = kind_periodic<KIND>();
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
+    const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * FY;
     const int gx0 = x0 - RH, gy0 = y0 - RH;
     const int cw = per || gx0 > 0, ce = per || gx0 + RRX < nx;
     const int cs = per || gy0 > 0, cn = per || gy0 + RRY < ny;
@@ -573,12 +585,12 @@ __device__ __forceinline__ void rk4_tile_fused(const Geom &g, const int tile, co
     int eh[RHPT], gxh[RHPT], gyh[RHPT], dh[RHPT];
 #pragma unroll
     for (int r = 0; r < RHPT; ++r) {
-        const int h = t + TT_THREADS * r;
+        const int h = t + NT * r;
         int lx, ly;
         if (h < 2 * RH * RRX) {  // RH full rows below and above the tile
             const int br = h / RRX;
             lx = h - br * RRX;
-            ly = br < RH ? br : br + TT_Y;
+            ly = br < RH ? br : br + FY;
         } else {  // RH columns left and right of the tile
             const int m = h - 2 * RH * RRX, c = m % (2 * RH);
             ly = RH + m / (2 * RH);
