@@ -172,7 +172,10 @@ def main():
         torch.cuda.synchronize()
         return torch.stack(out)
 
+    serial_fine(torch.float64, rpr.RPR_FP64)  # warm-up
+    t_sf = time.perf_counter()
     Uf = serial_fine(torch.float64, rpr.RPR_FP64)
+    t_sf = time.perf_counter() - t_sf
     E = float((U[1:] - Uf[1:]).abs().amax(dim=1).mean())
 
     # roofline of the dominant kernel: the fine propagator over all N slots
@@ -217,6 +220,10 @@ def main():
         "K": K,
         "L_hist": [int(v) for v in Lh],
         "E_vs_serial_fine": E,
+        # the fine solver slice after slice on the same GPU (one launch per
+        # slice), and the speed-up of the solve over it (N T_F / T_alg, Sec. 5)
+        "serial_fine_s": t_sf,
+        "speedup_vs_serial_fine": t_sf / sec,
         "dof_steps_per_s": value * w.d,
         # device time of the last timed solve by phase (events between the phases)
         "phases_s": {"total": info["t_total"], "fine": info["t_fine"], "model": info["t_model"],
