@@ -87,7 +87,10 @@ typedef struct {
                                   512 or 1024 fix the on-chip work-group size (512
                                   exists for the 64 x 64 grids only); 256 selects
                                   the tiled form (2D grids: slot states in memory,
-                                  one pass over 64 x 16-cell tiles per RK stage).
+                                  one pass over 64 x 16-cell tiles per RK stage, or
+                                  for RK4 on the 5-point Laplacian systems one pass
+                                  per step over 64 x 32-cell tiles with a 4-cell
+                                  halo).
                                   Other sizes give RPR_ERR_INVALID_ARG, sizes
                                   without a kernel RPR_ERR_UNSUPPORTED.  Batch
                                   plans choose their own and ignore it. */
