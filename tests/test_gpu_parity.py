@@ -158,6 +158,25 @@ def test_tiled_propagate_matches_oracle(orc, case, prec):
     assert err <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
 
 
+@pytest.mark.parametrize("steps", [1, 3])
+@pytest.mark.parametrize("kind,nx,ny,params", [(rpr.RPR_BRUSS2D, 70, 37, (1.0, 3.0, 0.02, 0.01)),
+                                               (rpr.RPR_DIFFREACT2D, 67, 17, (1e-3, 5e-3, 5e-3))],
+                         ids=["bruss_70x37", "diffreact_67x17"])
+@pytest.mark.parametrize("prec", [rpr.RPR_FP64, rpr.RPR_MIXED], ids=["fp64", "fp32"])
+def test_tiled_rk4_single_and_odd_step_counts(orc, kind, nx, ny, params, steps, prec):
+    """The one-pass RK4 tiles alternate the state between two work arrays:
+    one step goes from the input straight to the output, an odd count ends
+    on the other array than an even one."""
+    rng = np.random.default_rng(steps + nx)
+    d = rpr.nspecies(kind) * nx * ny
+    X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(2)])
+    ref = orc.propagate_many(orc.problem(kind, nx, ny, (-1, 1, -1, 1), params), 4, steps, 2e-4, X)
+    dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
+    xin, xout = dev(X, dtype), torch.empty((2, d), dtype=dtype, device="cuda")
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, params=params), d, 4, steps, prec, 2e-4, 2, xin, xout, threads=256)
+    assert rel_err(host(xout), ref) <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
+
+
 def test_large_state_takes_the_tiled_form_automatically(orc):
     # 128 x 128 Brusselator in FP64 (256 KiB) does not fit one work-group
     kind, nx, ny, params = rpr.RPR_BRUSS2D, 128, 128, (1.0, 3.0, 0.02, 0.01)
