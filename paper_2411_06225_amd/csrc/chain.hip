@@ -92,11 +92,10 @@ __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *_
         constexpr int MPL = 4;  // neurons per lane and pass
         // FP32 weights with M even: lane l takes the neuron pairs (2l, 2l + 1)
         // and (2 WL + 2l, 2 WL + 2l + 1) of each pass, one 8-byte load per pair
-        // and column, and twice the columns per load batch, so that as many
-        // bytes are in flight as with FP64 weights
+        // and column
         auto pass = [&](auto pair_tag) {
             constexpr bool PAIR = decltype(pair_tag)::value;
-            constexpr int CB4 = PAIR ? 8 : 4;  // columns per load batch
+            constexpr int CB4 = 4;  // columns per load batch
             auto neuron = [&](int mb, int u) {
                 return PAIR ? mb + 2 * WL * (u >> 1) + 2 * lane + (u & 1) : mb + lane + WL * u;
             };
@@ -523,9 +522,10 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
                 double acc[TPT];
 #pragma unroll
                 for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
-                // batches of NB neurons x TPT columns: 8 KB per wavefront in
-                // flight (16 FP64 loads, or 16 FP32 pairs)
-                constexpr int NB = PAIR ? 16 : 8;
+                // batches of NB neurons x TPT columns (twice the batch for
+                // the FP32 pairs moved no faster and cost registers that the
+                // coarse solver's step loop then spilled)
+                constexpr int NB = 8;
                 for (int m0 = wv; m0 < a.M; m0 += NB * nw) {
                     double wr[NB][TPT];
 #pragma unroll
