@@ -212,11 +212,12 @@ typedef struct {
     double t_total;            /* seconds of device time of the last execute */
     /* The same time by phase of Alg. "Parareal (generic)" (seconds of device
        time, from events recorded between the phases; -1 for plans that run
-       as a captured graph and for batch plans, where no event separates
-       them): the fine solves, the model (training pairs, features, ridge
-       statistics and solve, or the pair store of the nearest-neighbour
-       correction), and the sequential predictor-corrector sweeps, the first
-       coarse sweep of the set-up included. */
+       as a captured graph, where no event separates them; for an instance of
+       a batch plan, the batch's times, as t_total): the fine solves, the
+       model (training pairs, features, ridge statistics and solve, or the
+       pair store of the nearest-neighbour correction), and the sequential
+       predictor-corrector sweeps, the first coarse sweep of the set-up
+       included. */
     double t_fine;
     double t_model;
     double t_sweep;

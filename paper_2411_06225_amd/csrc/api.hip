@@ -1230,20 +1230,41 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
     for (int b = 0; b < n; ++b)
         if (bad[b]) return fail(RPR_ERR_NONFINITE, "u0 of instance " + std::to_string(b) + " has non-finite entries");
 
+    // phase events of eager iterations, as in execute_impl (batch-wide)
+    const bool timed = !p->use_graph;
+    const size_t n_ev = 1 + 3 * (size_t)(p->poll < p->bkmax ? p->poll : p->bkmax);
+    if (timed && p->pev.size() < n_ev) {
+        for (size_t e = p->pev.size(); e < n_ev; ++e) {
+            hipEvent_t ev = nullptr;
+            RPR_HIP(hipEventCreate(&ev));
+            p->pev.push_back(ev);
+        }
+    }
+    double t_fine = 0.0, t_model = 0.0, t_sweep = 0.0;
+    auto span = [&](int e0, int e1) -> double {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p->pev[e0], p->pev[e1]);
+        return ms * 1e-3;
+    };
     RPR_HIP(hipEventRecord(p->ev0, st));
     std::vector<ChainArgs<T>> args(n);
     for (int b = 0; b < n; ++b) RPR_TRY(phase_setup<T>(p->sub[b], u0[b], umax[b], st, &args[b]));
     std::memcpy(p->hchain.data(), args.data(), sizeof(ChainArgs<T>) * n);
     RPR_HIP(hipMemcpyAsync(p->bchain, p->hchain.data(), sizeof(ChainArgs<T>) * n, hipMemcpyHostToDevice, st));
+    if (timed) RPR_HIP(hipEventRecord(p->pev[0], st));
     const auto *insts = static_cast<const BatchInst<T> *>(p->binsts);
-    auto iteration = [&](hipStream_t s) -> rpr_status {
+    // (ev: the first of the iteration's three phase events, or -1)
+    auto iteration = [&](hipStream_t s, int ev) -> rpr_status {
         // every unfinished (instance, slot) fine solve in one persistent launch
         RPR_TRY(zero(p->bcounter, 1, s));
         RPR_TRY(launch_prop_persistent<T>(insts, p->bitems, p->bn_items, p->bcounter, p->bgmax, p->bshF, p->bgrid,
                                           s));
+        if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev], s));
         for (int b = 0; b < n; ++b) RPR_TRY(phase_model<T>(p->sub[b], args[b].inv_s, s));
+        if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 1], s));
         // every instance's predictor-corrector sweep, one work-group each
         RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->bchain), n, p->bgmax, p->bshG, p->bM, s));
+        if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 2], s));
         return RPR_OK;
     };
     if (p->use_graph) {
@@ -1252,7 +1273,7 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
         bool same = p->graph_exec != nullptr && p->bscale.size() == (size_t)n;
         for (int b = 0; same && b < n; ++b) same = p->bscale[b] == args[b].inv_s;
         if (!same) RPR_TRY(capture_block(p, [&]() -> rpr_status {
-            for (int it = 0; it < p->poll; ++it) RPR_TRY(iteration(p->cap_stream));
+            for (int it = 0; it < p->poll; ++it) RPR_TRY(iteration(p->cap_stream, -1));
             return RPR_OK;
         }));
         p->bscale.resize(n);
@@ -1260,14 +1281,16 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
     }
     int k = 0;
     bool done = false;
+    bool first = true;
     while (k < p->bkmax && !done) {
         const int burst = (p->bkmax - k) < p->poll ? (p->bkmax - k) : p->poll;
         if (p->use_graph) {
             RPR_HIP(hipGraphLaunch(p->graph_exec, st));
             k += p->poll;
         } else {
+            if (!first) RPR_HIP(hipEventRecord(p->pev[0], st));
             for (int it = 0; it < burst; ++it) {
-                RPR_TRY(iteration(st));
+                RPR_TRY(iteration(st, 1 + 3 * it));
                 ++k;
             }
         }
@@ -1276,12 +1299,33 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
         RPR_HIP(hipStreamSynchronize(st));
         done = true;
         for (int b = 0; b < n; ++b) done = done && p->sub[b]->ctrl_host->done != 0;
+        if (timed) {
+            if (first) {
+                float ms0 = 0.f;
+                RPR_HIP(hipEventElapsedTime(&ms0, p->ev0, p->pev[0]));
+                t_sweep += ms0 * 1e-3;
+            }
+            for (int it = 0; it < burst; ++it) {
+                const int e = 1 + 3 * it;
+                t_fine += span(e - 1, e);
+                t_model += span(e, e + 1);
+                t_sweep += span(e + 1, e + 2);
+            }
+        }
+        first = false;
     }
     RPR_HIP(hipEventRecord(p->ev1, st));
     RPR_HIP(hipEventSynchronize(p->ev1));
     float ms = 0.f;
     RPR_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-    for (int b = 0; b < n; ++b) RPR_TRY(phase_finish<T>(p->sub[b], U_out[b], ms, st));
+    for (int b = 0; b < n; ++b) {
+        RPR_TRY(phase_finish<T>(p->sub[b], U_out[b], ms, st));
+        if (timed) {
+            p->sub[b]->info.t_fine = t_fine;
+            p->sub[b]->info.t_model = t_model;
+            p->sub[b]->info.t_sweep = t_sweep;
+        }
+    }
     RPR_HIP(hipStreamSynchronize(st));
     bool conv = true;
     for (int b = 0; b < n; ++b) conv = conv && p->sub[b]->ctrl_host->L >= p->sub[b]->N;

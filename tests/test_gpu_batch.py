@@ -97,6 +97,20 @@ def test_batch_matches_oracle_per_instance(orc, family):
         assert err <= w.N * 1e-12
 
 
+def test_batch_phase_times():
+    # eager batches time their shared phases (every instance reports the
+    # batch's); captured graphs have no events between the phases
+    ws = burgers_instances(4)
+    _, _, infos = run_batch(ws)
+    for inf in infos:
+        parts = inf["t_fine"] + inf["t_model"] + inf["t_sweep"]
+        assert min(inf["t_fine"], inf["t_model"], inf["t_sweep"]) > 0.0
+        assert 0.5 * inf["t_total"] <= parts <= inf["t_total"] * (1 + 1e-6)
+        assert inf["t_fine"] == infos[0]["t_fine"]
+    _, _, ginfos = run_batch(ws, graph=1)
+    assert all(g["t_fine"] == g["t_model"] == g["t_sweep"] == -1.0 for g in ginfos)
+
+
 def test_batch_of_one_equals_single_plan():
     w = burgers_instances(1)[0]
     _, Us, infos = run_batch([w])
