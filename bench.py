@@ -586,7 +586,7 @@ def extra_workloads(torch, rpr, W, dev, only=None):
                              N=w.N, F=w.F, G=w.G, M=w.M, activation=w.act, lam=w.lam, A=A, zeta=z))
     u0s = [torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev) for w in bw.instances]
     r = {"instances": len(problems), "slots": sum(w.N for w in bw.instances)}
-    for name, prec, graph in (("fp64", rpr.RPR_FP64, 0), ("mixed_graph", rpr.RPR_MIXED, 1)):
+    for name, prec, graph in (("fp64", rpr.RPR_FP64, 0), ("mixed", rpr.RPR_MIXED, 0), ("mixed_graph", rpr.RPR_MIXED, 1)):
         plan = rpr.BatchPlan(problems, tol=[w.eps for w in bw.instances], precision=prec, graph=graph)
         outs = [torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev) for w in bw.instances]
         torch.cuda.synchronize()
@@ -599,7 +599,9 @@ def extra_workloads(torch, rpr, W, dev, only=None):
             inst = plan.instance(b)
             Lh, _ = inst.history()
             steps += sum(w.N - int(Lh[k - 1]) for k in range(1, inst.info()["K"] + 1)) * w.F[1]
-        r[name] = {"s": sec, "status": status, "fine_state_steps_per_s": steps / sec}
+        i0 = plan.instance(0).info()  # the batch's phase times (eager runs; -1 with graphs)
+        r[name] = {"s": sec, "status": status, "fine_state_steps_per_s": steps / sec,
+                   "phases_s": {"fine": i0["t_fine"], "model": i0["t_model"], "sweep": i0["t_sweep"]}}
         plan.close()
         print(f"extra burgers_batch64 {name}: {sec:.3f} s", file=sys.stderr, flush=True)
     res["burgers_batch64"] = r
