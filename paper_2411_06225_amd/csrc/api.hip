@@ -560,7 +560,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         }
     }
 
-    // chain grid: one work-group, or a quarter, half or all of the CUs
+    // chain grid: one work-group, or 1/16, 1/8, a quarter, half or all of the CUs
     if (!haveC) {
         ChainArgs<T> a{};
         a.g = g;
@@ -599,7 +599,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         if (p->G.threads == 0 && p->shG.maxt == 1024 && onchip_shape(g, p->esz, &gshapes[1], 512) &&
             check_threads(g, p->esz, 512) == RPR_OK)
             n_shapes = 2;
-        const int cands[] = {1, cus / 4, cus / 2, cus};
+        const int cands[] = {1, cus / 16, cus / 8, cus / 4, cus / 2, cus};
         for (int s = 0; s < n_shapes; ++s) {
             const OnchipShape &sh = gshapes[s];
             int mwg = max_wg;  // grids beyond the plan's max_wg have no partial-sum rows
