@@ -509,17 +509,18 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
 }
 
 // One classical RK4 step of one tile in a single pass, for the 5-point
-// Laplacian systems (a cheap right-hand side, so the step is bound by
-// memory, and recomputing a halo costs less than a pass per stage): the tile
-// (64 x FY cells, NT threads) is loaded with an RH-cell halo (cut at walls,
-// wrapped when periodic), stage s = 1..3 updates the region shrunk by s
-// cells on every side that is not a wall, stage 4 the tile's own cells.
-// Lane l of wavefront v holds the tile cells (l, ROWN v .. ROWN v + ROWN - 1)
-// and the halo cells t + NT r of the region in registers (state, stage input, slope sum and FP32 compensation
-// of the tile cells), so a tile cell reads only its west and east neighbours
-// and, at the ends of its column, one north or south neighbour from LDS; the
-// stage inputs live in one LDS buffer, rewritten between two barriers.  Per
-// cell the arithmetic is that of stage_tile<KIND, T, 1..4>.
+// Laplacian systems (a cheap right-hand side: recomputing a halo costs less
+// than a pass through memory per stage): the tile (64 x FY cells, NT
+// threads) is loaded with an RH-cell halo (cut at walls, wrapped when
+// periodic), stage s = 1..3 updates the region shrunk by s cells on every
+// side that is not a wall, stage 4 the tile's own cells.  Lane l of
+// wavefront v holds the tile cells (l, ROWN v .. ROWN v + ROWN - 1) and the
+// halo cells t + NT r of the region in registers (state, stage input, slope
+// sum and FP32 compensation of the tile cells), so a tile cell reads only
+// its west and east neighbours and, at the ends of its column, one north or
+// south neighbour from LDS; the stage inputs live in one LDS buffer,
+// rewritten between two barriers.  Per cell the arithmetic is that of
+// stage_tile<KIND, T, 1..4>.
 constexpr int RH = 4, RRX = TT_X + 2 * RH;
 template <int FY>
 struct FusedTile {
