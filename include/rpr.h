@@ -45,6 +45,7 @@ typedef enum {
     RPR_ERR_OOM = -4,           /* device allocation failed */
     RPR_ERR_NONFINITE = -5,     /* non-finite values where the method needs finite ones */
     RPR_ERR_NOT_SPD = -6,       /* ridge matrix not numerically positive definite */
+    RPR_ERR_UNSTABLE = -7,      /* stability pre-check failed (opt.stability = 1 only) */
     RPR_ERR_UNSUPPORTED = -8    /* a valid combination this build does not implement */
 } rpr_status;
 
@@ -160,7 +161,13 @@ typedef struct {
     int32_t graph;             /* 1: capture a block of poll_every iterations as a
                                   hipGraph on the first execute (again when the input
                                   scale changes) and replay it; 0: plain launches */
-    int32_t reserved;          /* must be 0 */
+    int32_t stability;         /* stability pre-check of F and G (rpr_stability at
+                                  u0): 0 records the ratios in rpr_info; 1 (strict)
+                                  also returns RPR_ERR_UNSTABLE from rpr_plan_create
+                                  when a ratio exceeds 1 for every state (the
+                                  state-independent part of the bound) and from
+                                  rpr_plan_execute, before anything is enqueued,
+                                  when it exceeds 1 at u0 */
 } rpr_options;
 
 /* ---- plans: one IVP solved by RandNet-Parareal -------------------------- */
@@ -221,6 +228,14 @@ typedef struct {
     double t_fine;
     double t_model;
     double t_sweep;
+    /* Stability pre-check at u0 (rpr_stability): dt / dt_max of F and G, and
+       bit 0 (F) / bit 1 (G) set where that ratio exceeds 1.  Sec. 6: an
+       unsuitable G keeps the iteration from converging; the run then degrades
+       to K = N (non-finite pairs are dropped). */
+    double stab_F;
+    double stab_G;
+    int32_t unstable;
+    int32_t reserved;
 } rpr_info;
 
 /* Results of the last execute (host pointer `info`). */
@@ -259,6 +274,29 @@ rpr_status rpr_plan_execute_batch(rpr_plan *plan, const void *const *u0, void *c
 /* The plan of instance b of a batch, for rpr_plan_info / rpr_plan_history.
  * The handle belongs to the batch: do not destroy it. */
 rpr_status rpr_plan_instance(const rpr_plan *batch, int32_t b, const rpr_plan **inst);
+
+/*
+ * Stability pre-check of one propagator (host only: touches no device).
+ * Sec. 6 notes that an unsuitable coarse solver keeps Parareal from
+ * converging; an explicit Runge-Kutta step is stable only while dt times the
+ * spectral radius of h's Jacobian lies in the method's stability region.
+ * The spectral radius is bounded from the grid, h's parameters and the state
+ * (a real part rho_r from diffusion, reaction and the Rusanov dissipation; an
+ * imaginary part rho_i from central-difference advection):
+ *   Burgers        rho_r = 4 nu/dx^2, rho_i = umax/dx
+ *   diffusion-reaction  rho_r = max(Du,Dv)(4/dx^2 + 4/dy^2) + 2 + 3 umax^2
+ *   Brusselator    rho_r = max(Du,Dv)(4/dx^2 + 4/dy^2) + B + 1 + 3 umax^2
+ *   shallow water  rho_r = 2 speed (1/dx + 1/dy)
+ * and *ratio = dt / dt_max with dt_max = min(2 / rho_r, rho_r / (2 rho_i^2))
+ * for forward Euler and 2.78 / (rho_r + rho_i) for classical RK4; a ratio
+ * above 1 flags the step as outside the stability region.
+ *   umax  : max |u| of the state (>= 0);
+ *   speed : largest wave speed |velocity| + sqrt(g h) (shallow water; ignored
+ *           otherwise, >= 0).
+ * Errors: RPR_ERR_INVALID_ARG.
+ */
+rpr_status rpr_stability(const rpr_rhs *h, int32_t d, const rpr_propagator *P, double dt, double umax,
+                         double speed, double *ratio);
 
 /* Release every buffer of the plan (a batch releases its instances).  NULL is accepted. */
 rpr_status rpr_plan_destroy(rpr_plan *plan);

@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["rhs.c", "integrate.c", "randnet.c", "parareal.c"]
+_SOURCES = ["rhs.c", "integrate.c", "randnet.c", "parareal.c", "stability.c"]
 
 BURGERS1D, DIFFREACT2D, BRUSS2D, SWE2D = 0, 1, 2, 3
 TANH, RELU = 0, 1
@@ -98,6 +98,10 @@ def lib():
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_uniform_pm1.restype = None
         L.orc_uniform_pm1.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, dp]
+        L.orc_stability.restype = C.c_double
+        L.orc_stability.argtypes = [C.POINTER(Problem), C.c_int32, C.c_double, dp]
+        L.orc_input_scale.restype = C.c_double
+        L.orc_input_scale.argtypes = [C.c_int32, dp]
         L.orc_parareal.restype = C.c_int32
         L.orc_parareal.argtypes = [C.POINTER(Problem), C.POINTER(PararealCfg), C.POINTER(RandNet),
                                    dp, dp, ip, dp, dp, C.POINTER(Info)]
@@ -219,6 +223,18 @@ def uniform_pm1(seed: int, first: int, n: int) -> np.ndarray:
     out = np.empty(n)
     lib().orc_uniform_pm1(C.c_uint64(seed), C.c_uint64(first), int(n), _dp(out))
     return out
+
+
+def stability(pb: Problem, method: int, dt: float, u) -> float:
+    """dt / dt_max of the propagator `method` for h linearised at u."""
+    u = _f64(u)
+    return float(lib().orc_stability(C.byref(pb), int(method), float(dt), _dp(u)))
+
+
+def input_scale(u0) -> float:
+    """The default input scale of the random network for initial state u0."""
+    u0 = _f64(u0)
+    return float(lib().orc_input_scale(u0.size, _dp(u0)))
 
 
 def parareal(pb: Problem, u0, *, N: int, t0: float, tN: float, F=(4, 1), G=(1, 1), eps: float,

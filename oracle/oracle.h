@@ -66,6 +66,11 @@ int32_t orc_propagate_many(const orc_problem *pb, int32_t method, int64_t steps,
 int32_t orc_serial_fine(const orc_problem *pb, int32_t method, int64_t steps, double dt,
                         int32_t N, const double *u0, double *U);
 
+/* dt over the largest stable step of `method` (1 = forward Euler, 4 = RK4) for
+ * h linearised at state u: > 1 flags the step as outside the stability
+ * region (Sec. 6: an unsuitable G stalls the iteration). */
+double orc_stability(const orc_problem *pb, int32_t method, double dt, const double *u);
+
 /* ---- random network ----------------------------------------------------- */
 enum { ORC_TANH = 0, ORC_RELU = 1 };
 

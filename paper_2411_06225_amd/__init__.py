@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "librpr.so")
 # status codes (rpr_status)
 RPR_OK, RPR_NOT_CONVERGED = 0, 1
 RPR_ERR_INVALID_ARG, RPR_ERR_NO_DEVICE, RPR_ERR_HIP, RPR_ERR_OOM = -1, -2, -3, -4
-RPR_ERR_NONFINITE, RPR_ERR_NOT_SPD, RPR_ERR_UNSUPPORTED = -5, -6, -8
+RPR_ERR_NONFINITE, RPR_ERR_NOT_SPD, RPR_ERR_UNSTABLE, RPR_ERR_UNSUPPORTED = -5, -6, -7, -8
 # enums
 RPR_BURGERS1D, RPR_DIFFREACT2D, RPR_BRUSS2D, RPR_SWE2D = 0, 1, 2, 3
 RPR_RK1, RPR_RK4 = 1, 4
@@ -34,7 +34,7 @@ RPR_FEAT_AUTO, RPR_FEAT_FP64, RPR_FEAT_BF16 = 0, 1, 2
 EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
             "rpr_plan_history", "rpr_plan_destroy", "rpr_propagate", "rpr_randnet_features", "rpr_ridge_fit",
             "rpr_randnet_readout", "rpr_uniform_pm1", "rpr_randnet_features_bf16", "rpr_plan_create_batch",
-            "rpr_plan_execute_batch", "rpr_plan_instance")
+            "rpr_plan_execute_batch", "rpr_plan_instance", "rpr_stability")
 
 
 class RprError(RuntimeError):
@@ -61,13 +61,14 @@ class rpr_randnet(C.Structure):
 class rpr_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("correction", C.c_int32), ("k_max", C.c_int32),
                 ("poll_every", C.c_int32), ("features", C.c_int32), ("autotune", C.c_int32),
-                ("graph", C.c_int32), ("reserved", C.c_int32)]
+                ("graph", C.c_int32), ("stability", C.c_int32)]
 
 
 class rpr_info(C.Structure):
     _fields_ = [("K", C.c_int32), ("L_final", C.c_int32), ("converged", C.c_int32), ("rows_used", C.c_int32),
                 ("nonfinite_rows", C.c_int32), ("chol_fail", C.c_int32), ("input_scale", C.c_double),
-                ("t_total", C.c_double), ("t_fine", C.c_double), ("t_model", C.c_double), ("t_sweep", C.c_double)]
+                ("t_total", C.c_double), ("t_fine", C.c_double), ("t_model", C.c_double), ("t_sweep", C.c_double),
+                ("stab_F", C.c_double), ("stab_G", C.c_double), ("unstable", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -105,6 +106,7 @@ def lib() -> C.CDLL:
             "rpr_ridge_fit": (i32, [i32, i32, i32, vp, vp, dbl, vp, vp]),
             "rpr_randnet_readout": (i32, [i32, i32, i32, vp, vp, vp, vp]),
             "rpr_uniform_pm1": (i32, [u64, u64, i64, vp, vp]),
+            "rpr_stability": (i32, [C.POINTER(rpr_rhs), i32, C.POINTER(rpr_propagator), dbl, dbl, dbl, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -125,11 +127,33 @@ def check(status: int, allow=(RPR_OK,)) -> int:
 
 
 def _ptr(t) -> int | None:
-    """Device (or host) address of a torch tensor, an int, or None."""
+    """Address of a torch tensor, an int (a raw pointer, passed through
+    unchecked), or None."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    return t.data_ptr()
+
+
+def _dev(t, dtype: str, numel: int, name: str) -> int | None:
+    """Address of a device tensor after checking what the C ABI assumes of it:
+    a CUDA tensor of the given dtype ("float64" or "float32"), contiguous, with
+    at least `numel` elements.  Raw integer pointers pass through unchecked."""
+    if t is None or isinstance(t, int):
+        return _ptr(t)
+    import torch
+    want = getattr(torch, dtype)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor or an int pointer, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device (cuda) tensor")
+    if t.dtype != want:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {numel} needed")
     return t.data_ptr()
 
 
@@ -154,33 +178,50 @@ def nspecies(kind: int) -> int:
 def rpr_propagate(h: rpr_rhs, d: int, method: int, steps: int, precision: int, dt: float, n_states: int, x_in,
                   x_out, stream=None, threads: int = 0) -> int:
     P = rpr_propagator(int(method), int(threads), int(steps))
+    dt_ = "float64" if precision == RPR_FP64 else "float32"
+    n = int(n_states) * int(d)
     return check(lib().rpr_propagate(C.byref(h), int(d), C.byref(P), int(precision), float(dt), int(n_states),
-                                     _ptr(x_in), _ptr(x_out), _stream(stream)))
+                                     _dev(x_in, dt_, n, "x_in"), _dev(x_out, dt_, n, "x_out"), _stream(stream)))
 
 
 def rpr_randnet_features(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi, stream=None) -> int:
-    return check(lib().rpr_randnet_features(int(M), int(d), int(n), int(activation), float(s), _ptr(A), _ptr(zeta),
-                                            _ptr(X), _ptr(Phi), _stream(stream)))
+    return check(lib().rpr_randnet_features(int(M), int(d), int(n), int(activation), float(s),
+                                            _dev(A, "float64", M * d, "A"), _dev(zeta, "float64", M, "zeta"),
+                                            _dev(X, "float64", n * d, "X"), _dev(Phi, "float64", n * M, "Phi"),
+                                            _stream(stream)))
 
 
 def rpr_randnet_features_bf16(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi,
                               stream=None) -> int:
-    return check(lib().rpr_randnet_features_bf16(int(M), int(d), int(n), int(activation), float(s), _ptr(A),
-                                                 _ptr(zeta), _ptr(X), _ptr(Phi), _stream(stream)))
+    return check(lib().rpr_randnet_features_bf16(int(M), int(d), int(n), int(activation), float(s),
+                                                 _dev(A, "float64", M * d, "A"), _dev(zeta, "float64", M, "zeta"),
+                                                 _dev(X, "float32", n * d, "X"), _dev(Phi, "float64", n * M, "Phi"),
+                                                 _stream(stream)))
 
 
 def rpr_ridge_fit(M: int, d: int, n: int, Phi, Y, lam: float, W, stream=None) -> int:
-    return check(lib().rpr_ridge_fit(int(M), int(d), int(n), _ptr(Phi), _ptr(Y), float(lam), _ptr(W),
+    return check(lib().rpr_ridge_fit(int(M), int(d), int(n), _dev(Phi, "float64", n * M, "Phi"),
+                                     _dev(Y, "float64", n * d, "Y"), float(lam), _dev(W, "float64", M * d, "W"),
                                      _stream(stream)))
 
 
 def rpr_randnet_readout(M: int, d: int, n: int, W, Phi, Yhat, stream=None) -> int:
-    return check(lib().rpr_randnet_readout(int(M), int(d), int(n), _ptr(W), _ptr(Phi), _ptr(Yhat),
+    return check(lib().rpr_randnet_readout(int(M), int(d), int(n), _dev(W, "float64", M * d, "W"),
+                                           _dev(Phi, "float64", n * M, "Phi"), _dev(Yhat, "float64", n * d, "Yhat"),
                                            _stream(stream)))
 
 
 def rpr_uniform_pm1(seed: int, first: int, n: int, out, stream=None) -> int:
-    return check(lib().rpr_uniform_pm1(C.c_uint64(seed), C.c_uint64(first), int(n), _ptr(out), _stream(stream)))
+    return check(lib().rpr_uniform_pm1(C.c_uint64(seed), C.c_uint64(first), int(n), _dev(out, "float64", n, "out"),
+                                       _stream(stream)))
+
+
+def rpr_stability(h: rpr_rhs, d: int, method: int, steps: int, dt: float, umax: float, speed: float = 0.0) -> float:
+    """dt / dt_max of one propagator at a state with max |u| = umax (host only)."""
+    P = rpr_propagator(int(method), 0, int(steps))
+    r = C.c_double(0.0)
+    check(lib().rpr_stability(C.byref(h), int(d), C.byref(P), float(dt), float(umax), float(speed), C.byref(r)))
+    return r.value
 
 
 # ---- plans ---------------------------------------------------------------------
@@ -191,7 +232,8 @@ class Plan:
                  tol: float = 1e-6, M: int = 100, activation: int = RPR_TANH, lam: float = 1e-6,
                  input_scale: float = 0.0, A=None, zeta=None, seed: int = 0, precision: int = RPR_FP64,
                  correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0,
-                 features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0, m_nn: int = 4):
+                 features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0, m_nn: int = 4,
+                 stability: int = 0):
         import numpy as np
         self.d, self.N = int(d), int(N)
         # F, G: (method, steps) or (method, steps, threads)
@@ -199,7 +241,7 @@ class Plan:
         self._G = rpr_propagator(int(G[0]), int(G[2]) if len(G) > 2 else 0, int(G[1]))
         self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale), int(m_nn), 0)
         self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features),
-                                int(autotune), int(graph), 0)
+                                int(autotune), int(graph), int(stability))
         self._h = h
         Ah = zh = None
         if A is not None:
@@ -213,7 +255,8 @@ class Plan:
 
     def execute(self, u0, U_out, stream=None) -> int:
         """u0: cuda float64 tensor (d); U_out: cuda float64 tensor ((N+1) x d)."""
-        return check(lib().rpr_plan_execute(self._handle, _ptr(u0), _ptr(U_out), _stream(stream)),
+        return check(lib().rpr_plan_execute(self._handle, _dev(u0, "float64", self.d, "u0"),
+                                            _dev(U_out, "float64", (self.N + 1) * self.d, "U_out"), _stream(stream)),
                      allow=(RPR_OK, RPR_NOT_CONVERGED))
 
     def info(self) -> dict:
@@ -256,7 +299,8 @@ class BatchPlan:
     """Many independent IVPs solved together (rpr_plan_create_batch / execute_batch)."""
 
     def __init__(self, problems, *, tol=1e-6, precision: int = RPR_FP64, correction: int = RPR_CORR_RANDNET,
-                 k_max: int = 0, poll_every: int = 0, features: int = RPR_FEAT_AUTO, seed: int = 0, graph: int = 0):
+                 k_max: int = 0, poll_every: int = 0, features: int = RPR_FEAT_AUTO, seed: int = 0, graph: int = 0,
+                 stability: int = 0):
         """problems: list of dicts with keys h, d, t0, tN, N, F, G, M, activation, lam, A, zeta
         (and m_nn for RPR_CORR_RANDNET_NN, default 4)."""
         import numpy as np
@@ -287,7 +331,7 @@ class BatchPlan:
                 self._keep += [a, z]
                 Ap[b], Zp[b] = a.ctypes.data, z.ctypes.data
         opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features), 0, int(graph),
-                          0)
+                          int(stability))
         self._handle = C.c_void_p()
         check(lib().rpr_plan_create_batch(C.byref(self._handle), n, H, D, T0, TN, NN, F, G, TOL, NET,
                                           Ap if have else None, Zp if have else None, C.c_uint64(seed),
@@ -295,8 +339,11 @@ class BatchPlan:
 
     def execute(self, u0s, U_outs, stream=None) -> int:
         n = self.n
-        U0 = (C.c_void_p * n)(*[_ptr(u) for u in u0s])
-        UO = (C.c_void_p * n)(*[_ptr(u) for u in U_outs])
+        if len(u0s) != n or len(U_outs) != n:
+            raise ValueError(f"need {n} initial states and {n} outputs")
+        U0 = (C.c_void_p * n)(*[_dev(u, "float64", self.ds[b], f"u0[{b}]") for b, u in enumerate(u0s)])
+        UO = (C.c_void_p * n)(*[_dev(u, "float64", (self.Ns[b] + 1) * self.ds[b], f"U_out[{b}]")
+                                for b, u in enumerate(U_outs)])
         return check(lib().rpr_plan_execute_batch(self._handle, U0, UO, _stream(stream)),
                      allow=(RPR_OK, RPR_NOT_CONVERGED))
 

@@ -32,7 +32,7 @@ def _units():
             for real in REALS:
                 obj = os.path.join(BUILD, f"{src}_{kname}_{real}.o")
                 units.append((os.path.join(CSRC, src + ".hip"), obj, [f"-DRPR_KIND={k}", f"-DRPR_REAL={real}"]))
-    for src in ("randnet", "dispatch", "api"):
+    for src in ("randnet", "dispatch", "api", "autotune", "batch", "blocks", "stability"):
         units.append((os.path.join(CSRC, src + ".hip"), os.path.join(BUILD, src + ".o"), []))
     return units
 

@@ -372,8 +372,11 @@ __device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src
     if (a.G_method == RPR_RK1) {
         // forward Euler: up to EH steps per pass without a grid barrier
         // (euler_tile_multi); the state alternates between the work arrays
-        // u and ya between passes, the FP32 compensation stays in cmp
+        // u and ya between passes, the FP32 compensation between cmp and
+        // acc (forward Euler has no slope sum), so that no tile reads a
+        // value another tile of the same pass has already replaced
         T *buf[2] = {a.gw.u, a.gw.ya};
+        T *cbuf[2] = {a.gw.cmp, a.gw.acc};
         int pass = 0;
         for (long long s = 0; s < a.G_steps; s += EH, ++pass) {
             const int n = (int)(a.G_steps - s < EH ? a.G_steps - s : EH);
@@ -381,8 +384,8 @@ __device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src
             const T *in = s == 0 ? src : buf[(pass - 1) & 1];
             T *out = last ? dst : buf[pass & 1];
             for (int tile = wg; tile < nt; tile += nwg)
-                euler_tile_multi<KIND, T>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr, a.gw.cmp,
-                                          s == 0 ? 1 : 0, lds);
+                euler_tile_multi<KIND, T>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr,
+                                          cbuf[(pass + 1) & 1], cbuf[pass & 1], s == 0 ? 1 : 0, lds);
             sync();
         }
         return;

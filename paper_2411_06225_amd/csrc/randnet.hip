@@ -89,10 +89,12 @@ template rpr_status launch_features<float>(int, int, int, int, double, const dou
                                            const float *, double *, double *, const int *, hipStream_t);
 
 // ------------------------------------------------- reduced-precision features ---
-// Mixed-precision hidden layer: inputs x/s and weights rounded to bfloat16
-// (round to nearest even), products accumulated in FP32 on the matrix cores
-// (v_mfma_f32_16x16x32_bf16), zeta and sigma in FP32, result rounded to bf16
-// and stored as a double (exactly representable) for the FP64 statistics.
+// Mixed-precision hidden layer: inputs x/s and weights split into three
+// bfloat16 pieces each (round to nearest even), the six leading products of
+// the pieces accumulated in FP32 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16) over K chunks; the chunks' partial sums, zeta
+// and sigma are taken in double, and Phi is stored in double for the FP64
+// statistics.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
@@ -432,7 +434,9 @@ __global__ __launch_bounds__(256) void k_gram(int n, int M, const double *__rest
 }
 
 // B[a][j] += sum_r ok_r Phi[r][a] Y[r][j]: a block of 16 neurons x 256 columns;
-// the 16 Phi columns of the block are staged in LDS.
+// the 16 Phi columns of the block are staged in LDS, BSTAT_ROWS rows at a
+// time (any row count; rows are summed in order).
+constexpr int BSTAT_ROWS = 256;
 template <typename TY>
 __global__ __launch_bounds__(256) void k_bstat(int n, int M, int d, const double *__restrict__ Phi,
                                                const TY *__restrict__ Y, const int *__restrict__ ok,
@@ -440,22 +444,28 @@ __global__ __launch_bounds__(256) void k_bstat(int n, int M, int d, const double
 {
     const int nr = nrows_dev ? *nrows_dev : n;
     const int a0 = blockIdx.y * 16, j = blockIdx.x * 256 + threadIdx.x;
-    extern __shared__ double sphi[];  // n x 16
-    for (int i = threadIdx.x; i < nr * 16; i += 256) {
-        const int r = i / 16, aa = i % 16;
-        const bool use = (ok == nullptr || ok[r]) && a0 + aa < M;
-        sphi[i] = use ? Phi[(size_t)r * M + a0 + aa] : 0.0;
-    }
-    __syncthreads();
-    if (j >= d) return;
+    __shared__ double sphi[BSTAT_ROWS * 16];
     double acc[16];
 #pragma unroll
     for (int aa = 0; aa < 16; ++aa) acc[aa] = 0.0;
-    for (int r = 0; r < nr; ++r) {
-        const double yv = (ok == nullptr || ok[r]) ? double(Y[(size_t)r * d + j]) : 0.0;
+    for (int r0 = 0; r0 < nr; r0 += BSTAT_ROWS) {
+        const int rn = min(BSTAT_ROWS, nr - r0);
+        __syncthreads();  // the previous chunk's reads are done
+        for (int i = threadIdx.x; i < rn * 16; i += 256) {
+            const int r = r0 + i / 16, aa = i % 16;
+            const bool use = (ok == nullptr || ok[r]) && a0 + aa < M;
+            sphi[i] = use ? Phi[(size_t)r * M + a0 + aa] : 0.0;
+        }
+        __syncthreads();
+        if (j < d) {
+            for (int r = 0; r < rn; ++r) {
+                const double yv = (ok == nullptr || ok[r0 + r]) ? double(Y[(size_t)(r0 + r) * d + j]) : 0.0;
 #pragma unroll
-        for (int aa = 0; aa < 16; ++aa) acc[aa] = fma(sphi[r * 16 + aa], yv, acc[aa]);
+                for (int aa = 0; aa < 16; ++aa) acc[aa] = fma(sphi[r * 16 + aa], yv, acc[aa]);
+            }
+        }
     }
+    if (j >= d) return;
 #pragma unroll
     for (int aa = 0; aa < 16; ++aa)
         if (a0 + aa < M) Bm[(size_t)(a0 + aa) * d + j] += acc[aa];
@@ -469,8 +479,7 @@ rpr_status launch_stats(int n, int M, int d, const double *Phi, const TY *Y, con
     hipLaunchKernelGGL(k_gram, dim3((M + 15) / 16, (M + 15) / 16), dim3(256), 0, st, n, M, Phi, ok, G,
                        nrows_dev);
     RPR_HIP(hipGetLastError());
-    const size_t lds = (size_t)n * 16 * sizeof(double);
-    hipLaunchKernelGGL(k_bstat<TY>, dim3((d + 255) / 256, (M + 15) / 16), dim3(256), lds, st, n, M, d, Phi,
+    hipLaunchKernelGGL(k_bstat<TY>, dim3((d + 255) / 256, (M + 15) / 16), dim3(256), 0, st, n, M, d, Phi,
                        Y, ok, Bm, nrows_dev);
     RPR_HIP(hipGetLastError());
     return RPR_OK;

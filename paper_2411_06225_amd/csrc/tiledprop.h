@@ -405,8 +405,12 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int tile, const 
 // tile's own cells are exact and go to dst (and dst2).  A cell at a wall
 // takes itself as the missing neighbour, as the one-step form does.  Per
 // cell and step the arithmetic is that of stage_tile<KIND, T, 0>, FP32 state
-// compensation included (cmp in memory between calls; cmp_zero: start from
-// zero).
+// compensation included: read from cmp_in (the halo included; cmp_zero: start
+// from zero) and written for the tile's own cells to cmp_out.  The two must
+// differ: the tiles of one pass run without a barrier between them, so a
+// tile may read a neighbour's compensation while that neighbour writes its
+// own; alternating the arrays between passes, as the state alternates, keeps
+// every read on the previous pass's values.
 constexpr int EH = 8;
 constexpr int ERX = TT_X + 2 * EH, ERY = TT_Y + 2 * EH;
 
@@ -418,8 +422,8 @@ __host__ __device__ inline size_t euler_multi_lds(const Geom &g, size_t elem)
 template <int KIND, typename T>
 __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, const int steps, const double dt,
                                                  const T *__restrict__ src, T *__restrict__ dst,
-                                                 T *__restrict__ dst2, T *__restrict__ cmp, const int cmp_zero,
-                                                 T *__restrict__ lds)
+                                                 T *__restrict__ dst2, const T *__restrict__ cmp_in,
+                                                 T *__restrict__ cmp_out, const int cmp_zero, T *__restrict__ lds)
 {
     constexpr int NS = kind_ns<KIND>();
     constexpr int RN = ERX * ERY;
@@ -445,7 +449,7 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
         for (int sp = 0; sp < NS; ++sp) {
             const int idx = sp * nc + gy * nx + gx;
             buf[0][sp * RN + e] = src[idx];
-            if constexpr (KAHAN) cm[sp * RN + e] = cmp_zero ? T(0) : cmp[idx];
+            if constexpr (KAHAN) cm[sp * RN + e] = cmp_zero ? T(0) : cmp_in[idx];
         }
     }
     __syncthreads();
@@ -502,7 +506,7 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
             const T v = buf[cur][sp * RN + r];
             dst[idx] = v;
             if (dst2) dst2[idx] = v;
-            if constexpr (KAHAN) cmp[idx] = cm[sp * RN + r];
+            if constexpr (KAHAN) cmp_out[idx] = cm[sp * RN + r];
         }
     }
     __syncthreads();  // the region buffers are reused by the next tile

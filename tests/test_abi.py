@@ -103,7 +103,7 @@ def test_plan_create_rejects_bad_options():
     assert create(opt=rpr.rpr_options(0, 0, 0, 0, 5, 0, 0, 0)) == -1
     assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 2, 0, 0)) == -1
     assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 3, 0)) == -1
-    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 1)) == -1
+    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 2)) == -1
     assert create(opt=rpr.rpr_options(0, 3, 0, 0, 0, 0, 0, 0)) == -1
     # nearest-neighbour correction: 1 <= m_nn <= 32, reserved field zero
     nn = rpr.rpr_options(0, rpr.RPR_CORR_RANDNET_NN, 0, 0, 0, 0, 0, 0)
@@ -140,3 +140,49 @@ def test_building_blocks_reject_bad_sizes():
     assert L.rpr_uniform_pm1(0, 0, -1, 1, None) == -1
     # zero-sized work is a no-op that needs no device
     assert L.rpr_randnet_readout(4, 4, 0, 1, 2, 3, None) == rpr.RPR_OK
+
+
+def test_strict_stability_check_rejects_unstable_coarse_solver_before_any_device_call():
+    # heat-like Brusselator (A = B = 0) on 32 x 32 cells of (-1, 1)^2, D = 0.1:
+    # rho_r = D (4/dx^2 + 4/dy^2) + 1 = 0.1 * 8 * 256 + 1 = 205.8; one forward
+    # Euler step over a slice of 0.25 is far outside |1 + z| <= 1
+    h = rpr.make_rhs(rpr.RPR_BRUSS2D, 32, 32, params=(0.0, 0.0, 0.1, 0.1))
+    F, G = _prop(4, 200), _prop(1, 1)
+    net = rpr.rpr_randnet(10, 0, 1e-6, 0.0, 0, 0)
+    handle = C.c_void_p()
+    strict = rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 1)
+    st = rpr.lib().rpr_plan_create(C.byref(handle), C.byref(h), 2 * 32 * 32, 0.0, 1.0, 4, C.byref(F), C.byref(G),
+                                   1e-6, C.byref(net), None, None, 0, C.byref(strict))
+    assert st == rpr.RPR_ERR_UNSTABLE
+    assert "stability" in rpr.last_error()
+    assert handle.value is None
+
+
+def test_stability_ratio_closed_forms():
+    # forward Euler on the periodic heat equation: dt_max = 2 / (D (4/dx^2 + 4/dy^2) + B + 1)
+    # with A = B = 0: 2 / (0.1 * 2048 + 1)
+    h = rpr.make_rhs(rpr.RPR_BRUSS2D, 32, 32, params=(0.0, 0.0, 0.1, 0.05))
+    rho = 0.1 * 8 * 256 + 1.0
+    assert rpr.rpr_stability(h, 2048, 1, 1, 1e-3, 0.0) == pytest.approx(1e-3 * rho / 2, rel=1e-15)
+    assert rpr.rpr_stability(h, 2048, 4, 1, 1e-3, 0.0) == pytest.approx(1e-3 * rho / 2.78, rel=1e-15)
+    # Burgers: rho_r = 4 nu / dx^2, rho_i = umax / dx; forward Euler needs
+    # dt <= 2 / rho_r and dt <= rho_r / (2 rho_i^2) (= 2 nu / umax^2)
+    hb = rpr.make_rhs(rpr.RPR_BURGERS1D, 128, 1, params=(0.01,))
+    dx = 2.0 / 128
+    rr, ri = 4 * 0.01 / dx ** 2, 1.5 / dx
+    dt = 5.0 / 16 / 40
+    want = max(dt * rr / 2, dt * 2 * ri * ri / rr)
+    assert rpr.rpr_stability(hb, 128, 1, 40, dt, 1.5) == pytest.approx(want, rel=1e-14)
+    assert want == pytest.approx(dt * 1.5 ** 2 / (2 * 0.01), rel=1e-14)
+    # the stated Burgers workload's G (4 steps per slice) is unstable, 40 steps are not
+    assert rpr.rpr_stability(hb, 128, 1, 4, 5.0 / 16 / 4, 1.5) > 1
+    assert rpr.rpr_stability(hb, 128, 1, 40, 5.0 / 16 / 40, 1.5) < 1
+    # shallow water, 192 x 192 on [0, 1]^2: rho_r = 2 a (1/dx + 1/dy)
+    hs = rpr.make_rhs(rpr.RPR_SWE2D, 192, 192, domain=(0.0, 1.0, 0.0, 1.0), params=(9.81,))
+    a = (9.81 * 1.1) ** 0.5
+    r = rpr.rpr_stability(hs, 3 * 192 * 192, 1, 8, 1.0 / 256 / 8, 1.1, a)
+    assert r == pytest.approx(1.0 / 256 / 8 * 2 * a * 384 / 2, rel=1e-14)
+    assert r < 1
+    # bad arguments
+    with pytest.raises(rpr.RprError):
+        rpr.rpr_stability(hs, 3 * 192 * 192, 1, 8, 1e-3, -1.0)

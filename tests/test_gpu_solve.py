@@ -322,23 +322,48 @@ MIXED_CASES = [("burgers", W.BURGERS_D128_STABLE), ("diffreact", DR_SMALL), ("bu
                ("diffreact_24x20_tiled", tiled(DR_RAGGED)), ("bruss_32x32_tiled", tiled(BRUSS_SMALL))]
 
 
+def E_err(U, Uref):
+    """The paper's accuracy measure: mean over slices i = 1..N of max_j |U_i[j] - Uref_i[j]|."""
+    return float(np.mean(np.abs(U[1:] - Uref[1:]).max(axis=1)))
+
+
+def gpu_serial_fine_fp32(w):
+    """F in single precision slice after slice on the GPU (the FP32 floor)."""
+    h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+    dt = (w.tN - w.t0) / w.N / w.F[1]
+    cur = torch.tensor(W.initial_condition(w), dtype=torch.float32, device="cuda")[None].contiguous()
+    out = [cur[0].double().cpu().numpy()]
+    threads = w.F[2] if len(w.F) > 2 else 0
+    for _ in range(w.N):
+        nxt = torch.empty_like(cur)
+        rpr.rpr_propagate(h, w.d, w.F[0], w.F[1], rpr.RPR_MIXED, dt, 1, cur, nxt, threads=threads)
+        cur = nxt
+        out.append(cur[0].double().cpu().numpy())
+    return np.stack(out)
+
+
 @pytest.mark.parametrize("name,w", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
 def test_mixed_precision_solve_stays_within_fp32_error_of_oracle(orc, name, w):
     # FP32 states change the run itself: with eps near the FP32 error floor of
-    # the fine solver the iteration count can grow, so the check is on accuracy.
-    # Bound: the FP64 oracle's serial fine solution is matched to 1e-4 relative,
-    # a hundred times the FP32 floor of these runs (~1e-6).  The FP32 sweep
-    # reads its weights in adjacent pairs where d (readout) and M (hidden
-    # layer) are even, one value per lane otherwise; tiled plans take the
-    # one-pass RK4 kernel for the Laplacian systems.
+    # the fine solver the iteration count can grow, so the check is on
+    # accuracy, with the paper's measure E (mean over slices of the max error)
+    # against the FP64 oracle's serial fine solution.  tau = 10 x E of the GPU's
+    # FP32 serial fine solution (the FP32 floor of the fine solver); the
+    # reduced-precision solve may exceed the FP64 solve's own Parareal error
+    # (the oracle's run) by at most tau.  The FP32 sweep reads its weights in
+    # adjacent pairs where d (readout) and M (hidden layer) are even, one value
+    # per lane otherwise; tiled plans take the one-pass RK4 kernel for the
+    # Laplacian systems.
     Ug, ig = gpu_solve(w, prec=rpr.RPR_MIXED)
     pb = orc.problem(w.kind, w.nx, w.ny, w.domain, w.params)
     T = (w.tN - w.t0) / w.N
     Uf = orc.serial_fine(pb, w.F[0], w.F[1], T / w.F[1], w.N, W.initial_condition(w))
+    Uo, io = orc_solve(orc, w)
+    tau = 10.0 * E_err(gpu_serial_fine_fp32(w), Uf)
     assert ig["converged"] == 1 and 1 <= ig["K"] <= w.N
-    err = np.abs(Ug - Uf).max() / np.abs(Uf).max()
-    print("mixed K", ig["K"], "rel err vs FP64 serial fine %.2e" % err)
-    assert err <= 1e-4
+    E_mixed, E_fp64 = E_err(Ug, Uf), E_err(Uo, Uf)
+    print(f"mixed K {ig['K']} E {E_mixed:.2e}; FP64 K {io['K']} E {E_fp64:.2e}; tau {tau:.2e}")
+    assert E_mixed <= E_fp64 + tau
 
 
 # ---- nearest-neighbour correction (eq. "randnet"): refit per prediction ----
