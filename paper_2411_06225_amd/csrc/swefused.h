@@ -1,0 +1,277 @@
+// swefused.h -- one classical RK4 step of shallow-water slot states in a
+// single pass over each tile (Sec. 5.3 system: first-order finite volumes,
+// Rusanov flux, reflective walls).
+//
+// Layout.  A wavefront holds a region row of 64 cells in its 64 lanes (lane l
+// = column x0 - 4 + l) and R consecutive rows in registers; NW wavefronts
+// stack to a region of 64 x RY cells, RY = NW R.  The region is the tile (56
+// columns, RY - 8 rows) with a 4-cell halo, one cell per RK stage: stage s
+// produces valid values on the region shrunk by s cells, so after stage 4
+// the tile's own cells are exact.
+//
+// Walls.  Beyond a wall the halo holds the mirror image of the cells inside
+// it (h and the tangential momentum even, the normal momentum odd).  The
+// Rusanov flux and the finite-volume update map mirrored inputs to mirrored
+// results operation by operation (every operation used is odd or even under
+// the reflection, rounding included), so a ghost cell evolves as the mirror
+// of its partner and the face at the wall sees exactly the mirrored ghost
+// that the per-cell form builds from the wall cell itself.  No wall branch
+// is needed inside the stages.
+//
+// Neighbours.  x: the lane to the east by a DPP rotation of the wavefront
+// (one instruction per value); each x face flux is computed once, by the
+// lane west of it, and rotated to the lane east of it.  y: registers within
+// a wavefront's R rows; the rows next to another wavefront's come through
+// LDS (6 values per cell of the first and last row, double-buffered by stage
+// so that one barrier per stage suffices).
+//
+// Traffic per RK4 step and degree of freedom: read u, write u (and read and
+// write the FP32 compensation), plus the halo re-reads that L2 serves.
+#pragma once
+
+#include "common.h"
+#include "slotprop.h"
+
+namespace rpr {
+
+constexpr int SWF_HALO = 4;                    // one cell per RK stage
+constexpr int SWF_X = 64 - 2 * SWF_HALO;       // tile columns (56)
+
+template <int R, int NW>
+struct SweFused {
+    static constexpr int RY = R * NW;          // region rows
+    static constexpr int TY = RY - 2 * SWF_HALO;  // tile rows
+    static constexpr int NT = 64 * NW;         // threads
+};
+
+__host__ __device__ inline int swf_tiles_x(const Geom &g) { return (g.nx + SWF_X - 1) / SWF_X; }
+template <int R, int NW>
+__host__ __device__ inline int swf_tiles_of(const Geom &g)
+{
+    return swf_tiles_x(g) * ((g.ny + SweFused<R, NW>::TY - 1) / SweFused<R, NW>::TY);
+}
+// LDS: two stage buffers x NW wavefronts x 2 edge rows x 6 values x 64 lanes
+template <int R, int NW>
+__host__ __device__ inline size_t swf_lds(size_t elem)
+{
+    return (size_t)2 * NW * 2 * 6 * 64 * elem;
+}
+
+// Domain index of region coordinate v (cells -4 .. n+3 around a wall-bounded
+// axis of n cells): the cell itself, or its mirror partner beyond a wall
+// (flip set); positions further out are clamped (never used for a tile cell).
+__device__ __forceinline__ int swf_mirror(int v, int n, bool &flip)
+{
+    flip = false;
+    if (v < 0) {
+        v = -1 - v;
+        flip = true;
+    } else if (v >= n) {
+        v = 2 * n - 1 - v;
+        flip = true;
+    }
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+// 1/h and sqrt(v) of the per-cell quantities.  Single precision takes the
+// hardware reciprocal and square root (about 1 ulp; the IEEE sequences
+// cost several instructions each and would be a fifth of the step), double
+// precision the IEEE operations.
+template <typename T>
+__device__ __forceinline__ T swf_rcp(T v)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(v);
+    else return T(1) / v;
+}
+template <typename T>
+__device__ __forceinline__ T swf_sqrt(T v)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_sqrtf(v);
+    else return sqrt(v);
+}
+
+// Rusanov flux across one face between left state (h, m = normal momentum,
+// q = tangential momentum, f = m^2/h + g h^2/2, e = q m/h, s = |m/h| + sqrt(g h))
+// and right state: (mass, normal, tangential) components.
+template <typename T>
+__device__ __forceinline__ void swf_face(T hL, T mL, T qL, T fL, T eL, T sL, T hR, T mR, T qR, T fR, T eR, T sR,
+                                         T &Fh, T &Fm, T &Fq)
+{
+    const T half = T(0.5);
+    const T a = sL > sR ? sL : sR;
+    Fh = half * (mL + mR) - half * a * (hR - hL);
+    Fm = half * (fL + fR) - half * a * (mR - mL);
+    Fq = half * (eL + eR) - half * a * (qR - qL);
+}
+
+// One RK4 step of one tile: src -> dst, both full slot states (d values);
+// cmp: the FP32 compensation of the own cells (read and written in place;
+// cmp_zero: start from zero), null in FP64.
+template <typename T, int R, int NW>
+__device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, const double dt, const T *__restrict__ src,
+                                             T *__restrict__ dst, T *__restrict__ cmp, const int cmp_zero,
+                                             T *__restrict__ lds)
+{
+    using S = SweFused<R, NW>;
+    constexpr int RY = S::RY, H = SWF_HALO;
+    constexpr bool KAHAN = sizeof(T) == 4;
+    const int nx = g.nx, ny = g.ny, nc = g.nc;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int tx = tile % swf_tiles_x(g), ty = tile / swf_tiles_x(g);
+    const int x0 = tx * SWF_X, y0 = ty * S::TY;
+    const T gg = T(g.p[0]), idx = T(g.idx), idy = T(g.idy), half = T(0.5);
+    const T dtT = T(dt), hdt = T(0.5 * dt), dt6 = T(dt / 6.0);
+
+    // ---- load: the region with mirror ghosts beyond the walls
+    bool fx;
+    const int gx = swf_mirror(x0 - H + lane, nx, fx);
+    const bool own_x = lane >= H && lane < H + SWF_X && x0 - H + lane < nx;
+    T u[R][3], y[R][3], acc[R][3], cm[R][3];
+    int gyq[R];
+    bool own[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = wv * R + q;
+        bool fy;
+        const int gy = swf_mirror(y0 - H + r, ny, fy);
+        gyq[q] = gy;
+        own[q] = own_x && r >= H && r < RY - H && y0 - H + r < ny;
+        const int c = gy * nx + gx;
+        const T h = src[c], m = src[nc + c], n = src[2 * nc + c];
+        u[q][0] = h;
+        u[q][1] = fx ? -m : m;
+        u[q][2] = fy ? -n : n;
+        if constexpr (KAHAN) {
+            // only the tile's own cells take the compensated last stage
+            const bool rd = own[q] && !cmp_zero;
+            cm[q][0] = rd ? cmp[c] : T(0);
+            cm[q][1] = rd ? cmp[nc + c] : T(0);
+            cm[q][2] = rd ? cmp[2 * nc + c] : T(0);
+        } else {
+            cm[q][0] = cm[q][1] = cm[q][2] = T(0);
+        }
+#pragma unroll
+        for (int sp = 0; sp < 3; ++sp) {
+            y[q][sp] = u[q][sp];
+            acc[q][sp] = T(0);
+        }
+    }
+
+#pragma unroll
+    for (int s = 1; s <= 4; ++s) {
+        T *eb = lds + (size_t)(s & 1) * NW * 2 * 6 * 64;  // this stage's edge-row buffer
+        // per-cell quantities of the rows whose values are still valid
+        T xf[R], xe[R], xs[R], yf[R], ye[R], ys[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = wv * R + q;
+            xf[q] = xe[q] = xs[q] = yf[q] = ye[q] = ys[q] = T(0);
+            if (r >= s - 1 && r < RY - s + 1) {
+                const T h = y[q][0], m = y[q][1], n = y[q][2];
+                const T rh = swf_rcp(h);
+                const T vx = m * rh, vy = n * rh, c = swf_sqrt(gg * h), P = half * gg * h * h;
+                xf[q] = m * vx + P;
+                xe[q] = n * vx;
+                xs[q] = fabs(vx) + c;
+                yf[q] = n * vy + P;
+                ye[q] = m * vy;
+                ys[q] = fabs(vy) + c;
+            }
+        }
+        // edge rows to LDS: [wave][row 0 | row R-1][h, m, n, yf, ye, ys][lane]
+        {
+            T *e0 = eb + (size_t)(wv * 2 + 0) * 6 * 64 + lane;
+            T *e1 = eb + (size_t)(wv * 2 + 1) * 6 * 64 + lane;
+            e0[0] = y[0][0];
+            e0[64] = y[0][1];
+            e0[128] = y[0][2];
+            e0[192] = yf[0];
+            e0[256] = ye[0];
+            e0[320] = ys[0];
+            e1[0] = y[R - 1][0];
+            e1[64] = y[R - 1][1];
+            e1[128] = y[R - 1][2];
+            e1[192] = yf[R - 1];
+            e1[256] = ye[R - 1];
+            e1[320] = ys[R - 1];
+        }
+        __syncthreads();
+        // y faces: face f lies below row f (f = 0 .. R); y face components
+        // (mass, normal = hv, tangential = hu)
+        T Gh[R + 1], Gv[R + 1], Gu[R + 1];
+        {
+            const int ws = wv > 0 ? wv - 1 : 0, wn = wv < NW - 1 ? wv + 1 : NW - 1;
+            const T *es = eb + (size_t)(ws * 2 + 1) * 6 * 64 + lane;  // south neighbour wave's last row
+            const T *en = eb + (size_t)(wn * 2 + 0) * 6 * 64 + lane;  // north neighbour wave's first row
+            swf_face<T>(es[0], es[128], es[64], es[192], es[256], es[320], y[0][0], y[0][2], y[0][1], yf[0], ye[0],
+                        ys[0], Gh[0], Gv[0], Gu[0]);
+            swf_face<T>(y[R - 1][0], y[R - 1][2], y[R - 1][1], yf[R - 1], ye[R - 1], ys[R - 1], en[0], en[128],
+                        en[64], en[192], en[256], en[320], Gh[R], Gv[R], Gu[R]);
+        }
+#pragma unroll
+        for (int f = 1; f < R; ++f)
+            swf_face<T>(y[f - 1][0], y[f - 1][2], y[f - 1][1], yf[f - 1], ye[f - 1], ys[f - 1], y[f][0], y[f][2],
+                        y[f][1], yf[f], ye[f], ys[f], Gh[f], Gv[f], Gu[f]);
+
+        // x faces: the east face of each cell with the east lane's values,
+        // then the west face from the west lane; update
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = wv * R + q;
+            if (!(r >= s && r < RY - s)) continue;  // wave-uniform: rows beyond this stage's region
+            const T hE = lane_neighbour<false, true>(y[q][0]);
+            const T mE = lane_neighbour<false, true>(y[q][1]);
+            const T nE = lane_neighbour<false, true>(y[q][2]);
+            const T fE = lane_neighbour<false, true>(xf[q]);
+            const T eE = lane_neighbour<false, true>(xe[q]);
+            const T sE = lane_neighbour<false, true>(xs[q]);
+            T Fh, Fm, Fn;
+            swf_face<T>(y[q][0], y[q][1], y[q][2], xf[q], xe[q], xs[q], hE, mE, nE, fE, eE, sE, Fh, Fm, Fn);
+            const T dh = Fh - lane_neighbour<true, true>(Fh);
+            const T dm = Fm - lane_neighbour<true, true>(Fm);
+            const T dn = Fn - lane_neighbour<true, true>(Fn);
+            T k[3];
+            k[0] = -dh * idx - (Gh[q + 1] - Gh[q]) * idy;
+            k[1] = -dm * idx - (Gu[q + 1] - Gu[q]) * idy;
+            k[2] = -dn * idx - (Gv[q + 1] - Gv[q]) * idy;
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp) {
+                if (s == 1) {
+                    acc[q][sp] = k[sp];
+                    y[q][sp] = u[q][sp] + hdt * k[sp];
+                } else if (s == 2) {
+                    acc[q][sp] = acc[q][sp] + T(2) * k[sp];
+                    y[q][sp] = u[q][sp] + hdt * k[sp];
+                } else if (s == 3) {
+                    acc[q][sp] = acc[q][sp] + T(2) * k[sp];
+                    y[q][sp] = u[q][sp] + dtT * k[sp];
+                } else {
+                    const T inc = dt6 * (acc[q][sp] + k[sp]);
+                    if constexpr (KAHAN) {
+                        const T yk = inc - cm[q][sp];
+                        const T un = u[q][sp] + yk;
+                        cm[q][sp] = (un - u[q][sp]) - yk;
+                        u[q][sp] = un;
+                    } else {
+                        u[q][sp] = u[q][sp] + inc;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- the tile's own cells (never mirrored: a tile cell lies inside the domain)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (!own[q]) continue;
+        const int c = gyq[q] * nx + gx;
+#pragma unroll
+        for (int sp = 0; sp < 3; ++sp) {
+            dst[sp * nc + c] = u[q][sp];
+            if constexpr (KAHAN) cmp[sp * nc + c] = cm[q][sp];
+        }
+    }
+}
+
+}  // namespace rpr

@@ -2,6 +2,7 @@
 // states too large for one work-group: passes over the tiles of every slot
 // state (tiledprop.h), one per RK stage (64 x 16-cell tiles), or one per RK4
 // step for the 5-point Laplacian systems (64 x 32-cell tiles).
+#include "swefused.h"
 #include "tiledprop.h"
 
 namespace rpr {
@@ -56,6 +57,46 @@ __global__ __launch_bounds__(NT) void k_prop_rk4_fused(Geom g, long long step, l
                                     reinterpret_cast<T *>(lds_raw));
 }
 
+// One whole RK4 step of a shallow-water tile (swe_rk4_tile); the state
+// alternates between the work arrays u and ya as in k_prop_rk4_fused.
+template <typename T, int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_prop_swe_fused(Geom g, long long step, long long steps, double dt, int n,
+                                                            const T *__restrict__ in, T *__restrict__ out,
+                                                            TiledWork<T> w, const int *__restrict__ ctrl)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int tile, b;
+    tile_of_block((int)blockIdx.x, swf_tiles_of<R, NW>(g), n, tile, b);
+    if (ctrl != nullptr && (ctrl[2] != 0 || b < ctrl[0])) return;
+    const size_t off = (size_t)b * g.d;
+    T *buf[2] = {w.u + off, w.ya + off};
+    const T *src = step == 0 ? in + off : buf[(step - 1) & 1];
+    T *dst = step == steps - 1 ? out + off : buf[step & 1];
+    swe_rk4_tile<T, R, NW>(g, tile, dt, src, dst, w.cmp ? w.cmp + off : nullptr, step == 0 ? 1 : 0,
+                           reinterpret_cast<T *>(lds_raw));
+}
+
+template <typename T, int R, int NW>
+static rpr_status launch_swe_fused(const Geom &g, int64_t steps, double dt, int n, const T *in, T *out,
+                                   const TiledWork<T> &w, const int *ctrl, hipStream_t st)
+{
+    auto kern = k_prop_swe_fused<T, R, NW>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+        attr_set = true;
+    }
+    if ((long long)swf_tiles_of<R, NW>(g) * n > 0x7fffffffLL)
+        return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 2^31 tiles per launch");
+    const dim3 grid((unsigned)(swf_tiles_of<R, NW>(g) * n));
+    const size_t lds = swf_lds<R, NW>(sizeof(T));
+    for (long long s = 0; s < (long long)steps; ++s) {
+        hipLaunchKernelGGL(kern, grid, dim3(64 * NW), lds, st, g, s, (long long)steps, dt, n, in, out, w, ctrl);
+        RPR_HIP(hipGetLastError());
+    }
+    return RPR_OK;
+}
+
 template <int KIND, typename T>
 rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
                                   const TiledWork<T> &w, const int *ctrl, hipStream_t st)
@@ -69,6 +110,14 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
         const dim3 grid((unsigned)(tiles_of(g) * n));
         const size_t lds = tiled_lds(g, sizeof(T));
         const long long ns = (long long)steps;
+        if constexpr (KIND == RPR_SWE2D) {
+            // a whole RK4 step per pass over 56-column tiles with a 4-cell
+            // halo (mirror ghosts need 4 cells inside each wall)
+            if (method == RPR_RK4 && g.nx >= SWF_HALO && g.ny >= SWF_HALO) {
+                if constexpr (sizeof(T) == 4) return launch_swe_fused<T, 4, 10>(g, steps, dt, n, in, out, w, ctrl, st);
+                else return launch_swe_fused<T, 4, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+            }
+        }
         if constexpr (KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D) {
             if (method == RPR_RK4) {
                 // a whole step per pass: the Laplacian right-hand side is

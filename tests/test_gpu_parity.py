@@ -133,6 +133,14 @@ TILED_CASES = [c for c in PROP_CASES if c[1] != rpr.RPR_BURGERS1D] + [
     ("bruss_80x33_rk1", rpr.RPR_BRUSS2D, 80, 33, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 30, 1e-4, 1),
     ("bruss_70x37", rpr.RPR_BRUSS2D, 70, 37, (-1, 1, -1, 1), (1.0, 3.0, 0.02, 0.01), 30, 1e-4, 4),
     ("diffreact_67x17", rpr.RPR_DIFFREACT2D, 67, 17, (-1, 1, -1, 1), (1e-3, 5e-3, 5e-3), 30, 2e-4, 4),
+    # shallow water, one pass per RK4 step: 56-column tiles (130 = 56 + 56 + 18,
+    # 57 = 56 + 1), several tile rows, the smallest grid the 4-cell mirror halo
+    # allows (4 cells each way), and the 192 x 192 grid (4 x 6 / 4 x 8 tiles)
+    ("swe_130x70", rpr.RPR_SWE2D, 130, 70, (0, 1, 0, 1), (9.81,), 30, 2e-4, 4),
+    ("swe_57x33", rpr.RPR_SWE2D, 57, 33, (0, 1, 0, 1), (9.81,), 30, 2e-4, 4),
+    ("swe_4x4", rpr.RPR_SWE2D, 4, 4, (0, 1, 0, 1), (9.81,), 30, 2e-3, 4),
+    ("swe_5x90", rpr.RPR_SWE2D, 5, 90, (0, 1, 0, 1), (9.81,), 30, 2e-4, 4),
+    ("swe_192x192", rpr.RPR_SWE2D, 192, 192, (0, 1, 0, 1), (9.81,), 10, 2e-5, 4),
 ]
 
 
@@ -160,8 +168,9 @@ def test_tiled_propagate_matches_oracle(orc, case, prec):
 
 @pytest.mark.parametrize("steps", [1, 3])
 @pytest.mark.parametrize("kind,nx,ny,params", [(rpr.RPR_BRUSS2D, 70, 37, (1.0, 3.0, 0.02, 0.01)),
-                                               (rpr.RPR_DIFFREACT2D, 67, 17, (1e-3, 5e-3, 5e-3))],
-                         ids=["bruss_70x37", "diffreact_67x17"])
+                                               (rpr.RPR_DIFFREACT2D, 67, 17, (1e-3, 5e-3, 5e-3)),
+                                               (rpr.RPR_SWE2D, 61, 45, (9.81,))],
+                         ids=["bruss_70x37", "diffreact_67x17", "swe_61x45"])
 @pytest.mark.parametrize("prec", [rpr.RPR_FP64, rpr.RPR_MIXED], ids=["fp64", "fp32"])
 def test_tiled_rk4_single_and_odd_step_counts(orc, kind, nx, ny, params, steps, prec):
     """The one-pass RK4 tiles alternate the state between two work arrays:
@@ -170,10 +179,11 @@ def test_tiled_rk4_single_and_odd_step_counts(orc, kind, nx, ny, params, steps, 
     rng = np.random.default_rng(steps + nx)
     d = rpr.nspecies(kind) * nx * ny
     X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(2)])
-    ref = orc.propagate_many(orc.problem(kind, nx, ny, (-1, 1, -1, 1), params), 4, steps, 2e-4, X)
+    dom = (0, 1, 0, 1) if kind == rpr.RPR_SWE2D else (-1, 1, -1, 1)
+    ref = orc.propagate_many(orc.problem(kind, nx, ny, dom, params), 4, steps, 2e-4, X)
     dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
     xin, xout = dev(X, dtype), torch.empty((2, d), dtype=dtype, device="cuda")
-    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, params=params), d, 4, steps, prec, 2e-4, 2, xin, xout, threads=256)
+    rpr.rpr_propagate(rpr.make_rhs(kind, nx, ny, dom, params), d, 4, steps, prec, 2e-4, 2, xin, xout, threads=256)
     assert rel_err(host(xout), ref) <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
 
 
