@@ -1,42 +1,46 @@
 """Benchmark: RandNet-Parareal on one MI355X.
 
-One step = one complete RandNet-Parareal solve (coarse sweep, then iterations
-of: fine solves of every unfinished slot, training pairs, random features,
-Gram/readout statistics, Cholesky ridge solve, predictor-corrector chain and
-stopping rule, until every slot is final) of the 64 x 64 FitzHugh-Nagumo
-diffusion-reaction workload: d = 8192, N = 64 slices on t in [0, 20], F = RK4
-with 4000 steps per slice, G = RK1 with 10 steps, 200 ReLU neurons,
-lambda = eps = 1e-6, plain FP64.  Inputs are seeded synthetic data already in
-device memory when the timed region starts.
+One step = one complete RandNet-Parareal solve of the 192 x 192 shallow-water
+workload (Rusanov finite volumes, reflective walls, g = 9.81, d = 110592,
+N = 256 slices on t in [0, 1], F = RK4 with 1000 steps per slice, G = RK1
+with 8 steps, 300 ReLU neurons, lambda = 1e-6): coarse sweep, then
+iterations of fine solves of every unfinished slot (one launch over all of
+them), training pairs, random features, ridge statistics, Cholesky solve,
+predictor-corrector sweep and stopping rule, in mixed precision (FP32
+states, split-bfloat16 features on the matrix cores, FP64 statistics,
+Cholesky and change norms), run to the common accuracy tau: the solve stops
+after the first iteration k whose iterate U^k satisfies E <= tau, with
+E = mean over slices of max |U_i - U_ref,i| against the FP64 serial fine
+solution and tau = 10 x E of the FP32 serial fine solution.  Inputs are
+seeded synthetic data already in device memory when the timed region starts.
 
-value = fine state-steps per second of the whole solve: the number of
-(slot, fine RK4 step) pairs the run performs, sum over iterations of the
-unfinished slots times 4000, divided by the wall time of the solve.
+value = fine state-steps per second of that solve: (slot, fine RK4 step)
+pairs it performs, sum over its iterations of the unfinished slots times
+1000, divided by its wall time.  Beside it: the same accuracy reached by the
+plain FP64 solve (time, k, E) and the ratio of the two times, both solves run
+to the stopping rule eps = 1e-6, the roofline of the dominant kernel (the
+one-pass RK4 fine propagator, timed live with HIP events on its launch
+stream), the 64 x 64 diffusion-reaction workload in FP64, and the CPU oracle
+timed on the host cores.
 
-Also reported: the roofline of the dominant kernel (the fine propagator,
-timed live with HIP events on its launch stream), the same solve in mixed
-precision (FP32 states) with its accuracy, the time each precision takes to
-reach a common accuracy tau = 10 x the error of an FP32 serial fine solve
-(solves stopped after k iterations, k increased until the mean slot error
-against the FP64 serial fine solution is <= tau), and the CPU oracle timed
-on the host cores on the same workload.
-
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline] [--no-mixed]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
                     [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128]
+                    [--solve-only NAME] [--gemm] [--robustness]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
-(Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems;
-shallow water 192 x 192), which takes minutes.  --copy-calibration runs a
-device copy of 256 MiB, the reference a hardware-counter run uses to scale
-its byte counters.  --f-only times only the fine propagator of the named
-workload (all N slot states, --steps RK4 steps, FP64 and FP32) and prints
-its roofline, for counter runs.
+(Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems),
+which takes minutes.  --copy-calibration runs a device copy of 256 MiB, the
+reference a hardware-counter run uses to scale its byte counters.  --f-only
+times only the fine propagator of the named workload (all N slot states,
+--steps RK4 steps, FP64 and FP32) and prints its roofline, for counter runs.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -45,23 +49,34 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (AMD specification)
+HBM_PEAK = 8.0e12            # MI355X HBM3E bytes/s (AMD specification)
+FP64_VECTOR_PEAK = 78.6e12   # MI355X FP64 vector FLOP/s (AMD specification)
+FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (AMD specification; packed FP32)
 # Algorithmic FP64 operations per degree of freedom and classical RK4 step of
 # the diffusion-reaction stencil, counted from the formulas (a fused
 # multiply-add counts as two): per cell and stage, two 5-point Laplacians
 # 2 x 9, the u reaction 7, the v reaction 3, the stage updates 2 x 3.25 on
 # average over the four stages = 34.5 per cell-stage = 17.25 per DOF-stage.
-FLOPS_PER_DOF_STEP = {"diffreact": 4 * 17.25}
+# Shallow water, per cell and stage (3 DOF): per-cell quantities 16 (1/h, two
+# velocities, sqrt(g h) 2, g h^2 / 2 2, three flux terms and a wave speed per
+# direction 8), one x face and one y face 13 each (speed max 1, three
+# components of (f_L + f_R)/2 - a (q_R - q_L)/2 at 4), flux differences and
+# slopes 15, stage update 12 = 69 per cell-stage = 92 per DOF-step.
+FLOPS_PER_DOF_STEP = {"diffreact": 4 * 17.25, "swe": 4 * 69 / 3}
+# Algorithmic HBM bytes per DOF and RK4 step of the fine propagator: read the
+# state and write it once (the minimum of any F); the FP32 compensation the
+# one-pass kernels also carry is traffic beyond it.
+ALGO_BYTES_PER_DOF_STEP = {8: 16, 4: 8}
 
-# HBM bytes per 64-slot launch of the fine propagator, from one FETCH_SIZE and
-# one WRITE_SIZE hardware-counter run (KiB per dispatch), each scaled by what
-# the counter reads for a device copy of known size (FETCH x 2, WRITE x 1).
-# Valid only for the kernel sources they were taken on (hash below); any
-# change to them makes the field null until the counters are taken again.
-PROP_SOURCES = ("paper_2411_06225_amd/csrc/slotprop.h", "paper_2411_06225_amd/csrc/propagate.hip",
-                "paper_2411_06225_amd/csrc/common.h")
-PROP_TRAFFIC = {"sources": "e46de50c3020989d", "fetch_kib": 2359.1, "fetch_scale": 2.0, "write_kib": 4608.0,
-                "write_scale": 1.0}
+# HBM bytes per launch (one RK4 step of the 256 FP32 shallow-water states) of
+# the one-pass fine propagator, from one FETCH_SIZE and one WRITE_SIZE
+# hardware-counter run (KiB per dispatch), each scaled by what the counter
+# reads for a device copy of known size.  Valid only for the kernel sources
+# they were taken on (hash below); any change to them makes the field null
+# until the counters are taken again.
+PROP_SOURCES = ("paper_2411_06225_amd/csrc/swefused.h", "paper_2411_06225_amd/csrc/tiled.hip",
+                "paper_2411_06225_amd/csrc/slotprop.h", "paper_2411_06225_amd/csrc/common.h")
+PROP_TRAFFIC = {"sources": None, "fetch_kib": None, "fetch_scale": None, "write_kib": None, "write_scale": None}
 
 
 def sources_hash(paths):
@@ -72,9 +87,9 @@ def sources_hash(paths):
 
 
 def measured_traffic():
-    if sources_hash(PROP_SOURCES) != PROP_TRAFFIC["sources"]:
-        return None
     t = PROP_TRAFFIC
+    if t["sources"] is None or sources_hash(PROP_SOURCES) != t["sources"]:
+        return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
@@ -84,7 +99,6 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--solve-only", choices=["burgers_d128", "bruss_128x128", "swe_192x192"], default=None,
@@ -98,6 +112,10 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,7 +126,6 @@ def main():
     import paper_2411_06225_amd as rpr
     from paper_2411_06225_amd import workloads as W
 
-    w = W.DIFFREACT_64
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.gemm:
@@ -130,15 +147,20 @@ def main():
             res["copy_calibration_bytes"] = copy_calibration(torch, dev)
         print(json.dumps(res))
         return
+
+    w = W.SWE_192
     h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
     u0h = W.initial_condition(w)
     A, zeta = W.random_weights(w)
     u0 = torch.tensor(u0h, dtype=torch.float64, device=dev)
     T = (w.tN - w.t0) / w.N
+    plans = []
 
-    def make_plan(prec, k_max=0, correction=rpr.RPR_CORR_RANDNET, m_nn=4):
-        return rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
-                        A=A, zeta=zeta, precision=prec, correction=correction, autotune=1, k_max=k_max, m_nn=m_nn)
+    def make_plan(prec, k_max=0):
+        p = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
+                     A=A, zeta=zeta, precision=prec, autotune=1, k_max=k_max)
+        plans.append(p)
+        return p
 
     def timed_solves(plan, steps, warmup):
         U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
@@ -146,21 +168,18 @@ def main():
             plan.execute(u0, U)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(max(steps, 1)):
             plan.execute(u0, U)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / max(steps, 1), U
 
-    plan = make_plan(rpr.RPR_FP64)
-    sec, U = timed_solves(plan, args.steps, args.warmup)
-    info = plan.info()
-    Lh, _ = plan.history()
-    K = info["K"]
-    active = [w.N - int(Lh[k - 1]) for k in range(1, K + 1)]
-    state_steps = sum(active) * w.F[1]
-    value = state_steps / sec
+    def fine_state_steps(plan):
+        Lh, _ = plan.history()
+        K = plan.info()["K"]
+        return sum(w.N - int(Lh[k - 1]) for k in range(1, K + 1)) * w.F[1]
 
-    # serial fine reference on the GPU (same F kernel, slot after slot) for the accuracy E
+    # serial fine reference on the GPU (same F kernel, slot after slot) in
+    # FP64 (the reference of E) and FP32 (its error sets tau)
     def serial_fine(prec_dtype, prec_code):
         cur = u0.to(prec_dtype)[None].contiguous()
         out = [cur[0].double().clone()]
@@ -172,33 +191,71 @@ def main():
         torch.cuda.synchronize()
         return torch.stack(out)
 
-    serial_fine(torch.float64, rpr.RPR_FP64)  # warm-up
     t_sf = time.perf_counter()
     Uf = serial_fine(torch.float64, rpr.RPR_FP64)
     t_sf = time.perf_counter() - t_sf
-    E = float((U[1:] - Uf[1:]).abs().amax(dim=1).mean())
+    E = lambda U: float((U[1:] - Uf[1:]).abs().amax(dim=1).mean())
+    E32floor = E(serial_fine(torch.float32, rpr.RPR_MIXED))
+    tau = 10.0 * E32floor
+    log(f"serial fine {t_sf:.2f} s; FP32 floor E = {E32floor:.3e}, tau = {tau:.3e}")
 
-    # roofline of the dominant kernel: the fine propagator over all N slots
-    # (the first iteration's launch), HIP events on the stream it runs on
-    X = U[:-1].contiguous()
+    # both precisions to the stopping rule (eps = 1e-6): K, E, time
+    natural = {}
+    for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
+        p = make_plan(prec)
+        t, U = timed_solves(p, 1, 1)
+        natural[name] = {"s": t, "K": p.info()["K"], "E": E(U)}
+        log(f"{name} to eps: {t:.3f} s, K = {natural[name]['K']}, E = {natural[name]['E']:.3e}")
+
+    def first_k_to_tau(prec, k_stop):
+        """First k whose iterate U^k has E <= tau (a solve stopped after k
+        iterations does exactly the work of the first k)."""
+        for k in range(1, k_stop + 1):
+            p = make_plan(prec, k_max=k)
+            _, Uk = timed_solves(p, 1, 0)
+            if E(Uk) <= tau:
+                return k, p
+        return None, None
+
+    k64, p64 = first_k_to_tau(rpr.RPR_FP64, natural["fp64"]["K"])
+    k32, p32 = first_k_to_tau(rpr.RPR_MIXED, natural["mixed"]["K"])
+    if k32 is None:
+        print(json.dumps({"error": f"the mixed-precision solve does not reach tau = {tau:.3e}"}))
+        sys.exit(1)
+    # the timed steps: the mixed solve to tau
+    sec, Um = timed_solves(p32, args.steps, args.warmup)
+    info = p32.info()
+    value = fine_state_steps(p32) / sec
+    log(f"mixed to tau: k = {k32}, {sec * 1e3:.1f} ms per solve")
+    t64 = None
+    if k64 is not None:
+        t64, U64 = timed_solves(p64, 2, 1)
+        log(f"fp64 to tau: k = {k64}, {t64 * 1e3:.1f} ms per solve")
+
+    # roofline of the dominant kernel: the fine propagator over all N FP32
+    # slot states (one launch per RK4 step), HIP events on its stream
+    X = Um[:-1].float().contiguous()
     Y = torch.empty_like(X)
     stream = torch.cuda.current_stream()
-    reps = 3
+    f_steps = 20
+    rpr.rpr_propagate(h, w.d, w.F[0], 2, rpr.RPR_MIXED, T / w.F[1], w.N, X, Y, stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    rpr.rpr_propagate(h, w.d, w.F[0], w.F[1], rpr.RPR_FP64, T / w.F[1], w.N, X, Y, stream)
     ev[0].record(stream)
-    for _ in range(reps):
-        rpr.rpr_propagate(h, w.d, w.F[0], w.F[1], rpr.RPR_FP64, T / w.F[1], w.N, X, Y, stream)
+    rpr.rpr_propagate(h, w.d, w.F[0], f_steps, rpr.RPR_MIXED, T / w.F[1], w.N, X, Y, stream)
     ev[1].record(stream)
     torch.cuda.synchronize()
-    f_sec = ev[0].elapsed_time(ev[1]) / 1e3 / reps
-    f_flops = w.N * w.F[1] * w.d * FLOPS_PER_DOF_STEP["diffreact"]
-    achieved = f_flops / f_sec
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK, "traffic": measured_traffic(),
-                "kernel": "k_prop_onchip (fine RK4, diffusion-reaction 64x64, FP64)",
-                "launch": {"slots": w.N, "steps": w.F[1], "flops_per_dof_step": FLOPS_PER_DOF_STEP["diffreact"],
-                           "ms": f_sec * 1e3, "active_cu_fraction": w.N / 256}}
+    f_launch = ev[0].elapsed_time(ev[1]) / 1e3 / f_steps
+    algo_bytes = ALGO_BYTES_PER_DOF_STEP[4] * w.N * w.d
+    achieved = algo_bytes / f_launch
+    flops = FLOPS_PER_DOF_STEP["swe"] * w.N * w.d
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
+                "kernel": "k_prop_swe_fused (fine RK4, one launch per step, shallow water 192x192, FP32)",
+                "launch": {"slots": w.N, "dof": w.d, "algorithmic_bytes": algo_bytes,
+                           "bytes_per_dof_step": ALGO_BYTES_PER_DOF_STEP[4], "ms": f_launch * 1e3,
+                           "alu_TFLOPs": flops / f_launch / 1e12,
+                           "alu_frac_of_fp32_peak": flops / f_launch / FP32_VECTOR_PEAK,
+                           "flops_per_dof_step": FLOPS_PER_DOF_STEP["swe"]}}
 
     out = {
         "metric": "time-to-tolerance (s) & fine state-steps/s, mixed vs FP64 plain, 1 MI355X",
@@ -211,92 +268,146 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "d": w.d, "N": w.N, "t": [w.t0, w.tN], "F": f"RK4x{w.F[1]}",
                    "G": f"RK1x{w.G[1]}", "M": w.M, "activation": "relu", "lambda": w.lam, "eps": w.eps,
-                   "precision": "fp64"},
+                   "precision": "mixed (FP32 states, split-bf16 MFMA features, FP64 ridge and norms)",
+                   "stop": "first iterate with E <= tau"},
         "time_to_tolerance_s": sec,
-        "K": K,
-        "L_hist": [int(v) for v in Lh],
-        "E_vs_serial_fine": E,
-        # the fine solver slice after slice on the same GPU (one launch per
-        # slice), and the speed-up of the solve over it (N T_F / T_alg, Sec. 5)
-        "serial_fine_s": t_sf,
+        "tau": tau,
+        "fp32_serial_fine_error_floor": E32floor,
+        "mixed": {"k": k32, "s": sec, "E": E(Um), "dof_steps_per_s": value * w.d,
+                  "phases_s": {"total": info["t_total"], "fine": info["t_fine"], "model": info["t_model"],
+                               "sweep": info["t_sweep"]}},
+        "fp64": {"k": k64, "s": t64, "E": E(U64) if t64 else None},
+        "fp64_over_mixed_time_to_tau": (t64 / sec) if t64 else None,
+        "to_eps": natural,
+        "serial_fine_fp64_s": t_sf,
         "speedup_vs_serial_fine": t_sf / sec,
-        "dof_steps_per_s": value * w.d,
-        # device time of the last timed solve by phase (events between the phases)
-        "phases_s": {"total": info["t_total"], "fine": info["t_fine"], "model": info["t_model"],
-                     "sweep": info["t_sweep"]},
         "roofline": roofline,
     }
+    for p in plans:
+        p.close()
+    plans.clear()
 
-    def time_to_tau(prec, tau, k_stop):
-        """First iteration k whose U^k is within tau of the FP64 serial fine
-        solution (E as above), and the time of a solve stopped after k
-        iterations: the solve runs with k_max = k, so it does exactly the
-        work of the first k iterations; E is taken outside the timed part."""
-        for k in range(1, k_stop + 1):
-            p = make_plan(prec, k_max=k)
-            t, Uk = timed_solves(p, 2, 1)
-            p.close()
-            Ek = float((Uk[1:] - Uf[1:]).abs().amax(dim=1).mean())
-            if Ek <= tau:
-                return {"k": k, "s": t, "E": Ek}
-        return {"k": None, "s": None, "E": None}
-
-    if not args.no_mixed:
-        mplan = make_plan(rpr.RPR_MIXED)
-        msec, Um = timed_solves(mplan, args.steps, 1)
-        minfo = mplan.info()
-        Em = float((Um[1:] - Uf[1:]).abs().amax(dim=1).mean())
-        Uf32 = serial_fine(torch.float32, rpr.RPR_MIXED)
-        E32floor = float((Uf32[1:] - Uf[1:]).abs().amax(dim=1).mean())
-        out["mixed"] = {"ms_per_solve": msec * 1e3, "K": minfo["K"], "E_vs_fp64_serial_fine": Em,
-                        "fp32_serial_fine_error_floor": E32floor, "fp64_over_mixed_time": sec / msec}
-        mplan.close()
-        # time to the common accuracy tau = 10 x the FP32 serial fine error
-        tau = 10.0 * E32floor
-        t64 = time_to_tau(rpr.RPR_FP64, tau, K)
-        t32 = time_to_tau(rpr.RPR_MIXED, tau, minfo["K"])
-        out["time_to_tau"] = {"tau": tau, "fp64": t64, "mixed": t32,
-                              "fp64_over_mixed": (t64["s"] / t32["s"]) if t64["s"] and t32["s"] else None}
-        # the correction of the paper's experiments: a refit per prediction on
-        # the m = 4 nearest stored pairs
-        nn = {"m_nn": 4}
-        for name, prec in (("fp64", rpr.RPR_FP64), ("mixed", rpr.RPR_MIXED)):
-            pn = make_plan(prec, correction=rpr.RPR_CORR_RANDNET_NN)
-            tn, Un = timed_solves(pn, 2, 1)
-            nn[name] = {"ms_per_solve": tn * 1e3, "K": pn.info()["K"],
-                        "E_vs_fp64_serial_fine": float((Un[1:] - Uf[1:]).abs().amax(dim=1).mean())}
-            pn.close()
-        out["nearest_neighbour"] = nn
-    plan.close()
+    # the 64 x 64 diffusion-reaction workload, plain FP64, to the stopping rule
+    out["diffreact_64x64_fp64"] = diffreact_line(torch, rpr, W, dev)
 
     if args.copy_calibration:
         out["copy_calibration_bytes"] = copy_calibration(torch, dev)
-
     if args.extra:
         out["extra"] = extra_workloads(torch, rpr, W, dev)
-
     if not args.no_cpu_baseline:
-        # bounded sample: the fine solves of 32 x threads slots (the part of
-        # a solve that dominates it, about 10 s), by the oracle
-        import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
-        n_sample = 32 * threads
-        pb = oracle.problem(w.kind, w.nx, w.ny, w.domain, w.params)
-        X = np.tile(u0h, (n_sample, 1))
-        t0 = time.perf_counter()
-        oracle.propagate_many(pb, w.F[0], w.F[1], T / w.F[1], X, nthreads=threads)
-        csec = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": n_sample * w.F[1] / csec, "unit": "fine state-steps/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"{n_sample} fine slot solves (RK4 x {w.F[1]} on d = {w.d}) of the same "
-                                         f"workload by the FP64 C oracle on {threads} threads, {csec:.1f} s; the "
-                                         f"fine solves are the bulk of an oracle solve, so the rate bounds its "
-                                         f"whole-solve rate from above"}
+        out["cpu_baseline"] = cpu_baseline(w, u0h, T, natural["fp64"]["K"], k64)
     print(json.dumps(out))
+
+
+def diffreact_line(torch, rpr, W, dev):
+    """One FP64 solve of the diffusion-reaction workload (d = 8192, N = 64):
+    time, K, fine state-steps/s and E against its FP64 serial fine solution."""
+    w = W.DIFFREACT_64
+    h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+    A, zeta = W.random_weights(w)
+    u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
+    T = (w.tN - w.t0) / w.N
+    def timed(graph):
+        plan = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam,
+                        A=A, zeta=zeta, autotune=1, graph=graph)
+        U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
+        plan.execute(u0, U)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.execute(u0, U)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        Lh, _ = plan.history()
+        K = plan.info()["K"]
+        plan.close()
+        return sec, U, K, sum(w.N - int(Lh[k - 1]) for k in range(1, K + 1)) * w.F[1]
+
+    sec, U, K, steps = timed(0)
+    # the same solve with each block of iterations captured as a graph (the
+    # sweeps as segment kernels on the same grid: bitwise the same result)
+    gsec, Ug, gK, _ = timed(1)
+    same = bool(torch.equal(Ug, U))
+    cur = u0[None].contiguous()
+    ref = [cur[0].clone()]
+    for _ in range(w.N):
+        nxt = torch.empty_like(cur)
+        rpr.rpr_propagate(h, w.d, w.F[0], w.F[1], rpr.RPR_FP64, T / w.F[1], 1, cur, nxt)
+        cur = nxt
+        ref.append(cur[0].clone())
+    Uf = torch.stack(ref)
+    E = float((U[1:] - Uf[1:]).abs().amax(dim=1).mean())
+    return {"s": sec, "K": K, "fine_state_steps_per_s": steps / sec, "E_vs_serial_fine": E,
+            "graph": {"s": gsec, "K": gK, "bitwise_equal_to_plain_launches": same}}
+
+
+def host_cpus():
+    """CPUs this process may run on, the OpenMP-style thread cap the host
+    sets (if any), and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(cap)) if cap and cap.isdigit() and int(cap) > 0 else avail
+    model = platform.processor() or ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": avail, "threads": threads, "model": model}
+
+
+def cpu_baseline(w, u0h, T, K64, k64):
+    """The FP64 C oracle on the host: fine slot solves of the benchmark
+    workload (RK4 x 1000 steps on d = 110592), on every CPU the process may
+    use (one slot per thread, as the paper runs one fine solve per core) and
+    on one thread; bounded samples, scaled to fine state-steps/s.  A whole
+    oracle solve is extrapolated from the measured rates: per iteration k the
+    fine solves of the unfinished slots on all threads, plus the coarse sweep
+    (N forward-Euler slices, one thread, timed on one slice)."""
+    import oracle
+    cpus = host_cpus()
+    threads = cpus["threads"]
+    pb = oracle.problem(w.kind, w.nx, w.ny, w.domain, w.params)
+    dtF, dtG = T / w.F[1], T / w.G[1]
+    # all threads: one slot each, 250 RK4 steps
+    steps_all = 250
+    X = np.tile(u0h, (threads, 1))
+    t0 = time.perf_counter()
+    oracle.propagate_many(pb, w.F[0], steps_all, dtF, X, nthreads=threads)
+    t_all = time.perf_counter() - t0
+    rate_all = threads * steps_all / t_all
+    # one thread: one slot, 100 RK4 steps
+    steps_one = 100
+    t0 = time.perf_counter()
+    oracle.propagate(pb, w.F[0], steps_one, dtF, u0h)
+    t_one = time.perf_counter() - t0
+    rate_one = steps_one / t_one
+    t0 = time.perf_counter()
+    oracle.propagate(pb, w.G[0], w.G[1], dtG, u0h)
+    t_g = time.perf_counter() - t0
+    # whole solve to the stopping rule and to tau (no slot final before its
+    # exact iteration: at most N - k + 1 slots at iteration k)
+    def solve_s(K):
+        fine = sum(w.N - k + 1 for k in range(1, K + 1)) * w.F[1] / rate_all
+        return fine + (K + 1) * w.N * t_g
+    return {"value": rate_all, "unit": "fine state-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} fine slot solves of {steps_all} RK4 steps (d = {w.d}) by the FP64 C oracle on "
+                      f"{threads} threads, {t_all:.1f} s; one thread: 1 slot x {steps_one} steps, {t_one:.1f} s",
+            "one_thread": {"value": rate_one, "unit": "fine state-steps/s"},
+            "host": cpus,
+            "extrapolated_solve_s": {"to_eps_K": K64, "to_eps": solve_s(K64),
+                                     "to_tau_k": k64, "to_tau": solve_s(k64) if k64 else None,
+                                     "note": "extrapolated from the sampled rates, not run whole; the fine "
+                                             "solves bound it from below"}}
 
 
 def copy_calibration(torch, dev):
@@ -326,25 +437,13 @@ def copy_bandwidth(torch, dev, mib=1024, reps=5):
     return 2 * a.numel() * 8 * reps / (ev[0].elapsed_time(ev[1]) / 1e3)
 
 
-HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s (AMD specification)
-# Array accesses per degree of freedom and classical RK4 step of the tiled
-# (through-memory) propagator, one pass per stage:
-#   stage 1: read y (= u), write acc, write y_out            3
-#   stage 2, 3: read y, u, acc, write acc, write y_out       5 + 5
-#   stage 4: read y, u, acc, write u_out (+ read and write
-#            the FP32 compensation)                          4 (FP32: 6)
-# The one-cell halo rows and columns a tile re-reads are not counted.
-TILED_ACCESSES_PER_DOF_STEP = {8: 17, 4: 19}
-# The 5-point Laplacian systems take one pass per RK4 step instead: read u,
-# write u (+ read and write the FP32 compensation); the 4-cell halo a tile
-# re-reads is not counted.
-FUSED_ACCESSES_PER_DOF_STEP = {8: 2, 4: 4}
-
-
 def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
     """Time one launch of the fine propagator over all N slot states of
-    workload w (steps RK4 steps) with HIP events on its stream and relate the
-    algorithmic bytes of the tiled form to the HBM peak."""
+    workload w (steps RK4 steps, one launch per step: the one-pass RK4 tile
+    kernels of the Laplacian systems and of shallow water) with HIP events on
+    its stream, and relate its algorithmic bytes (read and write the state
+    once per step) to the HBM peak; the FP32 compensation the kernels also
+    read and write, and the halo re-reads, are traffic beyond them."""
     h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
     from paper_2411_06225_amd import workloads as W
     dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
@@ -361,18 +460,17 @@ def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
     ev[1].record(stream)
     torch.cuda.synchronize()
     sec = ev[0].elapsed_time(ev[1]) / 1e3
-    fused = w.kind != rpr.RPR_SWE2D and w.F[0] == 4
-    acc = (FUSED_ACCESSES_PER_DOF_STEP if fused else TILED_ACCESSES_PER_DOF_STEP)[esz]
-    bytes_ = w.N * w.d * steps * acc * esz
+    bpd = ALGO_BYTES_PER_DOF_STEP[esz]
+    bytes_ = w.N * w.d * steps * bpd
     achieved = bytes_ / sec
-    kernel = ("k_prop_rk4_fused (fine RK4, one launch per step)" if fused
-              else "k_prop_tiled (fine RK4, one launch per stage)")
+    kernel = ("k_prop_swe_fused" if w.kind == rpr.RPR_SWE2D else "k_prop_rk4_fused") + \
+        " (fine RK4, one launch per step)"
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "kernel": kernel,
             "measured_copy_GBps": copy_bw / 1e9 if copy_bw else None,
             "frac_of_copy": achieved / copy_bw if copy_bw else None,
             "launch": {"slots": w.N, "steps": steps, "ms_per_step": sec * 1e3 / steps,
-                       "bytes_per_dof_step": acc * esz}}
+                       "algorithmic_bytes_per_dof_step": bpd}}
 
 
 BF16_MFMA_PEAK = 2.5e15  # MI355X dense bf16 matrix FLOP/s (AMD specification)
@@ -569,7 +667,7 @@ def extra_workloads(torch, rpr, W, dev, only=None):
         return r
 
     singles = {"burgers_d128": (W.BURGERS_D128, False), "bruss_128x128": (W.BRUSS_128, False),
-               "swe_192x192": (W.SWE_192, True)}
+               "swe_192x192": (W.SWE_192, False)}
     if only is not None:
         return {only: single(*singles[only])}
     for name, (w, tau) in singles.items():

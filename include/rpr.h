@@ -168,6 +168,14 @@ typedef struct {
                                   state-independent part of the bound) and from
                                   rpr_plan_execute, before anything is enqueued,
                                   when it exceeds 1 at u0 */
+    int32_t chain_wgs;         /* work-groups of the predictor-corrector sweep
+                                  (0: automatic, or the autotuner's choice); more
+                                  than the device holds at once are cut to that
+                                  number.  The results do not depend on it except
+                                  through the summation order of the hidden
+                                  layer's partial sums, which follow the column
+                                  blocks of the work-groups. */
+    int32_t reserved;          /* must be 0 */
 } rpr_options;
 
 /* ---- plans: one IVP solved by RandNet-Parareal -------------------------- */

@@ -12,9 +12,12 @@ the plan calls for torch tensors.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import sys
+import weakref
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpr.so")
@@ -61,7 +64,7 @@ class rpr_randnet(C.Structure):
 class rpr_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("correction", C.c_int32), ("k_max", C.c_int32),
                 ("poll_every", C.c_int32), ("features", C.c_int32), ("autotune", C.c_int32),
-                ("graph", C.c_int32), ("stability", C.c_int32)]
+                ("graph", C.c_int32), ("stability", C.c_int32), ("chain_wgs", C.c_int32), ("reserved", C.c_int32)]
 
 
 class rpr_info(C.Structure):
@@ -72,6 +75,23 @@ class rpr_info(C.Structure):
 
 
 _lib = None
+# Plans still open: closed before the interpreter shuts down, so that no plan
+# is released from a finaliser after the HIP runtime has begun its own
+# teardown.
+_live = weakref.WeakSet()
+
+
+_exiting = [False]
+
+
+@atexit.register
+def _close_live_plans():
+    _exiting[0] = True
+    for plan in list(_live):
+        try:
+            plan.close()
+        except Exception:
+            pass
 
 
 def lib() -> C.CDLL:
@@ -233,7 +253,7 @@ class Plan:
                  input_scale: float = 0.0, A=None, zeta=None, seed: int = 0, precision: int = RPR_FP64,
                  correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0,
                  features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0, m_nn: int = 4,
-                 stability: int = 0):
+                 stability: int = 0, chain_wgs: int = 0):
         import numpy as np
         self.d, self.N = int(d), int(N)
         # F, G: (method, steps) or (method, steps, threads)
@@ -241,13 +261,14 @@ class Plan:
         self._G = rpr_propagator(int(G[0]), int(G[2]) if len(G) > 2 else 0, int(G[1]))
         self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale), int(m_nn), 0)
         self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features),
-                                int(autotune), int(graph), int(stability))
+                                int(autotune), int(graph), int(stability), int(chain_wgs), 0)
         self._h = h
         Ah = zh = None
         if A is not None:
             Ah = np.ascontiguousarray(A, dtype=np.float64)
             zh = np.ascontiguousarray(zeta, dtype=np.float64)
         self._handle = C.c_void_p()
+        _live.add(self)
         check(lib().rpr_plan_create(C.byref(self._handle), C.byref(h), self.d, float(t0), float(tN), self.N,
                                     C.byref(self._F), C.byref(self._G), float(tol), C.byref(self._net),
                                     None if Ah is None else Ah.ctypes.data, None if zh is None else zh.ctypes.data,
@@ -280,8 +301,10 @@ class Plan:
 
     def __del__(self):
         try:
+            if _exiting[0]:
+                return  # the exit hook has closed every plan already
             self.close()
-        except Exception:
+        except Exception:  # module globals already torn down
             pass
 
 
@@ -331,8 +354,9 @@ class BatchPlan:
                 self._keep += [a, z]
                 Ap[b], Zp[b] = a.ctypes.data, z.ctypes.data
         opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features), 0, int(graph),
-                          int(stability))
+                          int(stability), 0, 0)
         self._handle = C.c_void_p()
+        _live.add(self)
         check(lib().rpr_plan_create_batch(C.byref(self._handle), n, H, D, T0, TN, NN, F, G, TOL, NET,
                                           Ap if have else None, Zp if have else None, C.c_uint64(seed),
                                           C.byref(opt)))
@@ -359,8 +383,10 @@ class BatchPlan:
 
     def __del__(self):
         try:
+            if _exiting[0]:
+                return  # the exit hook has closed every plan already
             self.close()
-        except Exception:
+        except Exception:  # module globals already torn down
             pass
 
 

@@ -312,6 +312,8 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     if (opt->autotune != 0 && opt->autotune != 1) return fail(RPR_ERR_INVALID_ARG, "opt.autotune must be 0 or 1");
     if (opt->graph != 0 && opt->graph != 1) return fail(RPR_ERR_INVALID_ARG, "opt.graph must be 0 or 1");
     if (opt->stability != 0 && opt->stability != 1) return fail(RPR_ERR_INVALID_ARG, "opt.stability must be 0 or 1");
+    if (opt->chain_wgs < 0) return fail(RPR_ERR_INVALID_ARG, "opt.chain_wgs must be >= 0");
+    if (opt->reserved != 0) return fail(RPR_ERR_INVALID_ARG, "opt.reserved must be 0");
     const bool use_net = opt->correction == RPR_CORR_RANDNET || opt->correction == RPR_CORR_RANDNET_NN;
     if (use_net) {
         if (!net) return fail(RPR_ERR_INVALID_ARG, "net is NULL");
@@ -424,6 +426,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const double work = (double)g.d * (use_net ? p->M : 1);
     int nwg = (work < 65536.0 && p->shG.maxt != TILED_THREADS) ? 1 : cus;  // the tiled coarse solver needs the grid
+    if (opt->chain_wgs > 0) nwg = opt->chain_wgs;
     if (nwg > max_wg) nwg = max_wg;
     if (nwg > 4096) nwg = 4096;
     p->nwg = nwg < 1 ? 1 : nwg;
@@ -439,6 +442,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
             return st;
         }
     }
+    p->fixed_nwg = opt->chain_wgs > 0;
     if (p->autotune) {
         st = p->esz == 8 ? autotune_plan<double>(p, max_wg, cus) : autotune_plan<float>(p, max_wg, cus);
         if (st != RPR_OK) {
@@ -495,18 +499,19 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     // one iteration: fine solves of the unfinished slots (Fv[i] = F(U[i-1])),
     // the model, the predictor-corrector sweep with the stopping rule
     // `s` is the stream the iteration is enqueued on (the caller's, or the
-    // capture stream); inside a graph the chain runs as one work-group with
-    // plain barriers, so the graph holds no grid-wide barrier
+    // capture stream); inside a graph the sweep is a sequence of segment
+    // kernels on the plan's grid (the kernel boundaries are its barriers), so
+    // the graph holds no grid-wide barrier
     // (ev: the first of the iteration's three phase events, or -1)
     auto iteration = [&](hipStream_t s, bool graph, int ev) -> rpr_status {
         const TiledWork<T> fw = tiled_work<T>(p->fwork, (size_t)N * d);
         RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, s, p->shF.maxt,
-                                    p->fwork ? &fw : nullptr));
+                                    p->fwork ? &fw : nullptr, p->fvar));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev], s));
         RPR_TRY(phase_model<T>(p, a.inv_s, s));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 1], s));
         if (graph)
-            RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->gchain), 1, g, p->shG, p->M, s));
+            RPR_TRY(launch_chain_graph<T>(static_cast<const ChainArgs<T> *>(p->gchain), a, p->shG, p->nwg, s));
         else
             RPR_TRY(launch_chain<T>(a, p->shG, p->nwg, s));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 2], s));

@@ -71,6 +71,16 @@ int tuned_prop_threads(const Geom &g, int esz, int method)
     return it == g_tune.end() ? 1024 : it->second;
 }
 
+// Tile shape of the one-pass RK4 form the autotuner chose for this
+// propagator class (0, the default, when it has not run for it).
+int tuned_variant(const Geom &g, int esz, int method)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    const auto it = g_tune.find(prop_key(g, esz, method) + ":v");
+    return it == g_tune.end() ? 0 : it->second;
+}
+
 // Device memory released when it goes out of scope.
 struct DevBuf {
     void *p = nullptr;
@@ -100,37 +110,55 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
     if (p->Wf) RPR_TRY(zero(p->Wf, (size_t)p->M * d, st));
 
     // fine propagator: on chip with 1024-thread (short strips) or 512-thread
-    // (long strips) work-groups, or tiled through memory (2D grids)
+    // (long strips) work-groups, or tiled through memory (2D grids) in each
+    // tile shape of its one-pass form; every candidate's time (microseconds
+    // per launch of min(steps, 32) steps) is kept in the table under
+    // "<class>:t:<threads>:<shape>"
     const bool forced_tiled = p->shF.maxt == TILED_THREADS;
-    if (!haveF && p->F.threads == 0 && !forced_tiled) {
+    const std::string kv = kf + ":v";
+    const bool haveV = g_tune.count(kv) != 0;
+    const int nvar = fused_variants(g.kind, p->esz);
+    if ((!haveF && p->F.threads == 0 && !forced_tiled) || (forced_tiled && !haveV)) {
         const int64_t steps = p->F.steps < 32 ? p->F.steps : 32;
         float best = 1e30f;
-        int best_mt = p->shF.maxt;
+        int best_mt = p->shF.maxt, best_v = 0;
         DevBuf trial;  // work arrays of the tiled candidate
         for (int mt : {1024, 512, TILED_THREADS}) {
+            if (forced_tiled && mt != TILED_THREADS) continue;
             if (check_threads(g, p->esz, mt) != RPR_OK) continue;
             TiledWork<T> w{};
             if (mt == TILED_THREADS) {
-                if (hipMalloc(&trial.p, 5 * (size_t)N * d * p->esz) != hipSuccess) {
-                    (void)hipGetLastError();
-                    trial.p = nullptr;
-                    continue;
+                if (p->fwork) {
+                    w = tiled_work<T>(p->fwork, (size_t)N * d);
+                } else {
+                    if (hipMalloc(&trial.p, 5 * (size_t)N * d * p->esz) != hipSuccess) {
+                        (void)hipGetLastError();
+                        trial.p = nullptr;
+                        continue;
+                    }
+                    w = tiled_work<T>(trial.p, (size_t)N * d);
                 }
-                w = tiled_work<T>(trial.p, (size_t)N * d);
             }
             const TiledWork<T> *wp = mt == TILED_THREADS ? &w : nullptr;
-            RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp));
-            float ms = 0.f;
-            RPR_HIP(hipEventRecord(e0, st));
-            for (int r = 0; r < 3; ++r)
-                RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp));
-            RPR_HIP(hipEventRecord(e1, st));
-            RPR_HIP(hipEventSynchronize(e1));
-            RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; best_mt = mt; }
+            for (int v = 0; v < (mt == TILED_THREADS ? nvar : 1); ++v) {
+                RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp, v));
+                float ms = 0.f;
+                RPR_HIP(hipEventRecord(e0, st));
+                for (int r = 0; r < 3; ++r)
+                    RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp, v));
+                RPR_HIP(hipEventRecord(e1, st));
+                RPR_HIP(hipEventSynchronize(e1));
+                RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                std::ostringstream kt;
+                kt << kf << ":t:" << mt << ":" << (mt == TILED_THREADS ? fused_variant_name(g.kind, p->esz, v) : "onchip");
+                g_tune[kt.str()] = (int)(ms * 1000.f / 3.f);
+                if (ms < best) { best = ms; best_mt = mt; best_v = mt == TILED_THREADS ? v : 0; }
+            }
         }
-        g_tune[kf] = best_mt;
+        if (!forced_tiled) g_tune[kf] = best_mt;
+        g_tune[kv] = best_v;
     }
+    p->fvar = g_tune.count(kv) ? g_tune[kv] : 0;
     if (!forced_tiled) {
         const int mt = p->F.threads ? p->F.threads : g_tune[kf];
         if (mt == TILED_THREADS) {
@@ -231,8 +259,8 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
             }
         }
     }
-    p->nwg = g_tune[kc.str()] < max_wg ? g_tune[kc.str()] : max_wg;
-    if (!haveF || !haveC) tune_store();
+    if (!p->fixed_nwg) p->nwg = g_tune[kc.str()] < max_wg ? g_tune[kc.str()] : max_wg;
+    if (!haveF || !haveC || !haveV) tune_store();
     return RPR_OK;
 }
 

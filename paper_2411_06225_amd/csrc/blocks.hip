@@ -2,6 +2,7 @@
 // a plan runs, one call each.
 #include "plan.h"
 
+
 // ------------------------------------------------------- building blocks --
 extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propagator *P, int32_t precision,
                                     double dt, int32_t n_states, const void *in, void *out, void *stream)
@@ -34,7 +35,10 @@ extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propa
         return launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
                                        static_cast<float *>(out), nullptr, st, mt);
     }
-    // tiled: five work arrays of n_states x d values, released on the stream
+    // tiled: five work arrays of n_states x d values, released on the
+    // stream; the one-pass form in the tile shape the autotuner chose for
+    // this class of propagators in this process (else the default)
+    const int var = tuned_variant(g, esz, P->method);
     const size_t nd = (size_t)n_states * d;
     void *ws = nullptr;
     RPR_HIP(hipMallocAsync(&ws, 5 * nd * esz, st));
@@ -43,12 +47,12 @@ extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propa
         double *b = static_cast<double *>(ws);
         const TiledWork<double> w{b, b + nd, b + 2 * nd, b + 3 * nd, nullptr};
         rc = launch_propagate<double>(g, P->method, P->steps, dt, n_states, static_cast<const double *>(in),
-                                      static_cast<double *>(out), nullptr, st, mt, &w);
+                                      static_cast<double *>(out), nullptr, st, mt, &w, var);
     } else {
         float *b = static_cast<float *>(ws);
         const TiledWork<float> w{b, b + nd, b + 2 * nd, b + 3 * nd, b + 4 * nd};
         rc = launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
-                                     static_cast<float *>(out), nullptr, st, mt, &w);
+                                     static_cast<float *>(out), nullptr, st, mt, &w, var);
     }
     RPR_HIP(hipFreeAsync(ws, st));
     return rc;

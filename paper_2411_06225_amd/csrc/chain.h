@@ -65,6 +65,20 @@ template <int KIND, typename T>
 rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,
                              int *max_wg);
 
+// One sweep as a sequence of kernels, one per segment (prologue; phase 1 of
+// every slot i = 2..N, the tiled coarse solver's passes one kernel each;
+// phase 2 of every slot; stopping rule), on nwg work-groups, for capture in
+// a graph: the kernel boundaries take the place of the grid barriers, and a
+// segment of a final slot returns at once.  args_dev: device copy of a (read
+// by the kernels when they run); a: the host copy (sizes, mode, coarse
+// propagator).  Same arithmetic as launch_chain with nwg work-groups.
+template <typename T>
+rpr_status launch_chain_graph(const ChainArgs<T> *args_dev, const ChainArgs<T> &a, const OnchipShape &sh, int nwg,
+                              hipStream_t st);
+template <int KIND, typename T>
+rpr_status launch_chain_graph_kind(const ChainArgs<T> *args_dev, const ChainArgs<T> &a, const OnchipShape &sh,
+                                   int nwg, hipStream_t st);
+
 // Independent instances in one launch, one work-group each (nwg = 1 sweeps).
 // args_dev: device array of n_inst argument blocks; every instance must be
 // served by the generic kernel instance of shape sh (built for geometry gmax).

@@ -361,51 +361,311 @@ __device__ __forceinline__ int nn_refit(const ChainArgs<T> &a, const int n, cons
     return m_sh;
 }
 
-// Coarse propagation src -> dst (and dst2) of a state too large for one
-// work-group, by the whole grid: the tiles of each RK stage are spread over
-// the work-groups, a grid barrier separates the stages.
+// ---- the predictor-corrector sweep, segment by segment ----
+// A sweep is a prologue, then for every predicted slot i = L+2..N a phase 1
+// (coarse solve, hidden layer of U_{i-1}) and a phase 2 (readout, update,
+// change norm, hidden-layer partial sums of U_i), then the stopping rule.
+// The segments are separated by a barrier over the work-groups sharing the
+// instance: a grid barrier inside one cooperative launch (chain_body), or
+// the boundary between kernels of a captured graph (k_chain_seg).  Every
+// segment reads L and the done flag from the control block, which only the
+// stopping rule changes, so both forms take the same decisions and compute
+// the same values bit for bit.  wg / nwg: this work-group and the number of
+// work-groups sharing the instance.  TILED: the slot state does not fit one
+// work-group; the coarse solver then runs on the whole grid in passes
+// (tiled_coarse_pass) instead of on work-group 0.  NN_OK: the nearest-
+// neighbour refit is compiled in (otherwise a kernel for the other modes
+// carries none of its code or registers).
+
+// Columns [j0, j1) of a slot state owned by work-group wg of nwg (an even
+// count, so that FP32 rows of even length start 8-byte aligned).
+__device__ __forceinline__ void chain_columns(const int d, const int wg, const int nwg, int &j0, int &j1)
+{
+    const int chunk = (((d + nwg - 1) / nwg) + 1) & ~1;
+    j0 = min(d, wg * chunk);
+    j1 = min(d, j0 + chunk);
+}
+
+// Passes of the tiled coarse solver per slot: forward Euler takes up to EH
+// steps per pass (euler_tile_multi), RK4 one pass per stage.
+__host__ __device__ inline long long coarse_passes(int method, long long steps)
+{
+    return method == RPR_RK1 ? (steps + EH - 1) / EH : 4 * steps;
+}
+
+// Pass `pass` of the tiled coarse propagation src -> dst (and dst2) by the
+// work-groups of the grid (tiles spread over them).  Forward Euler: passes of
+// up to EH steps without a barrier; the state alternates between the work
+// arrays u and ya from pass to pass, the FP32 compensation between cmp and
+// acc (forward Euler has no slope sum), so that no tile reads a value another
+// tile of the same pass has already replaced.  RK4: one pass per stage.
+template <int KIND, typename T>
+__device__ __forceinline__ void tiled_coarse_pass(const ChainArgs<T> &a, const T *src, T *dst, T *dst2,
+                                                  const long long pass, const int wg, const int nwg, T *lds)
+{
+    const int nt = tiles_of(a.g);
+    if (a.G_method == RPR_RK1) {
+        T *buf[2] = {a.gw.u, a.gw.ya};
+        T *cbuf[2] = {a.gw.cmp, a.gw.acc};
+        const long long s = pass * EH;
+        const int n = (int)(a.G_steps - s < EH ? a.G_steps - s : EH);
+        const bool last = s + n >= a.G_steps;
+        const T *in = s == 0 ? src : buf[(pass - 1) & 1];
+        T *out = last ? dst : buf[pass & 1];
+        for (int tile = wg; tile < nt; tile += nwg)
+            euler_tile_multi<KIND, T>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr, cbuf[(pass + 1) & 1],
+                                      cbuf[pass & 1], s == 0 ? 1 : 0, lds);
+        return;
+    }
+    const long long step = pass / 4;
+    const int stage = (int)(pass % 4) + 1;
+    const StageIO<T> io = stage_io<T>(a.G_method, stage, step, a.G_steps, src, dst, dst2, a.gw);
+    for (int tile = wg; tile < nt; tile += nwg) stage_tile_any<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
+}
+
+// The whole tiled coarse propagation, passes separated by sync().
 template <int KIND, typename T, typename Sync>
 __device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src, T *dst, T *dst2, const int wg,
                                              const int nwg, Sync sync, T *lds)
 {
-    const int nt = tiles_of(a.g);
-    if (a.G_method == RPR_RK1) {
-        // forward Euler: up to EH steps per pass without a grid barrier
-        // (euler_tile_multi); the state alternates between the work arrays
-        // u and ya between passes, the FP32 compensation between cmp and
-        // acc (forward Euler has no slope sum), so that no tile reads a
-        // value another tile of the same pass has already replaced
-        T *buf[2] = {a.gw.u, a.gw.ya};
-        T *cbuf[2] = {a.gw.cmp, a.gw.acc};
-        int pass = 0;
-        for (long long s = 0; s < a.G_steps; s += EH, ++pass) {
-            const int n = (int)(a.G_steps - s < EH ? a.G_steps - s : EH);
-            const bool last = s + n >= a.G_steps;
-            const T *in = s == 0 ? src : buf[(pass - 1) & 1];
-            T *out = last ? dst : buf[pass & 1];
-            for (int tile = wg; tile < nt; tile += nwg)
-                euler_tile_multi<KIND, T>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr,
-                                          cbuf[(pass + 1) & 1], cbuf[pass & 1], s == 0 ? 1 : 0, lds);
-            sync();
-        }
-        return;
-    }
-    for (long long s = 0; s < a.G_steps; ++s) {
-        for (int stage = a.G_method == RPR_RK4 ? 1 : 0; stage <= (a.G_method == RPR_RK4 ? 4 : 0); ++stage) {
-            const StageIO<T> io = stage_io<T>(a.G_method, stage, s, a.G_steps, src, dst, dst2, a.gw);
-            for (int tile = wg; tile < nt; tile += nwg) stage_tile_any<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
-            sync();
-        }
+    const long long np = coarse_passes(a.G_method, a.G_steps);
+    for (long long pass = 0; pass < np; ++pass) {
+        tiled_coarse_pass<KIND, T>(a, src, dst, dst2, pass, wg, nwg, lds);
+        sync();
     }
 }
 
-// One sweep of one instance.  wg / nwg: this work-group and the number of
-// work-groups sharing the instance; sync(): a barrier over those work-groups
+// Prologue: the exact slot U_{L+1} = F(U_L), and the hidden-layer (and
+// distance) partial sums of its columns.
+template <typename T, bool NN_OK>
+__device__ __forceinline__ void chain_seg_pro(const ChainArgs<T> &a, const int wg, const int nwg, double *scratch)
+{
+    const int t = threadIdx.x, B = blockDim.x, d = a.g.d;
+    const Ctrl *ctrl = a.ctrl;
+    const int L = ctrl->L, N = a.N;
+    int j0, j1;
+    chain_columns(d, wg, nwg, j0, j1);
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
+    const bool net = a.mode == CHAIN_RANDNET || nn;
+    const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
+    for (int j = j0 + t; j < j1; j += B) a.U[(size_t)(L + 1) * d + j] = a.Fv[(size_t)(L + 1) * d + j];
+    if (net && L + 2 <= N) {
+        __syncthreads();
+        hidden_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, scratch);
+        if (nn) dist_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, n_store);
+    }
+}
+
+// Phase 1 of slot i, on-chip coarse solver: work-group 0 propagates U_{i-1}
+// into gtmp, the others (all, if there is one work-group) finish the hidden
+// layer (and distances) of U_{i-1}.
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, bool NN_OK>
+__device__ __forceinline__ void chain_seg_p1_onchip(const ChainArgs<T> &a, const int i, const int wg, const int nwg,
+                                                    T *lds)
+{
+    const int d = a.g.d;
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
+    const bool net = a.mode == CHAIN_RANDNET || nn;
+    const int n_store = nn ? a.ctrl->nn_rows + *a.nrows : 0;
+    if (wg == 0) {
+        slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(a.g, a.G_method, a.G_steps, a.dtG, a.U + (size_t)(i - 1) * d,
+                                                         a.gtmp, lds);
+        __syncthreads();
+    }
+    if (net && (wg > 0 || nwg == 1)) hidden_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg);
+    if (nn && (wg > 0 || nwg == 1)) dist_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg, n_store);
+}
+
+// The hidden layer (and distances) of U_{i-1} on every work-group (the part
+// of phase 1 beside the tiled coarse solver).
+template <typename T, bool NN_OK>
+__device__ __forceinline__ void chain_seg_hidden_all(const ChainArgs<T> &a, const int wg, const int nwg)
+{
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
+    const bool net = a.mode == CHAIN_RANDNET || nn;
+    if (net) hidden_finish(a, wg, nwg, nwg);
+    if (nn) dist_finish(a, wg, nwg, nwg, a.ctrl->nn_rows + *a.nrows);
+}
+
+// Phase 2 of slot i: readout, update, change norm on this work-group's
+// columns of U_i, and the hidden-layer partial sums of U_i for slot i + 1.
+template <typename T, bool NN_OK>
+__device__ __forceinline__ void chain_seg_p2(const ChainArgs<T> &a, const int i, const int wg, const int nwg,
+                                             double *scratch)
+{
+    const int t = threadIdx.x, B = blockDim.x, d = a.g.d, N = a.N;
+    int j0, j1;
+    chain_columns(d, wg, nwg, j0, j1);
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
+    const bool net = a.mode == CHAIN_RANDNET || nn;
+    const int n_store = nn ? a.ctrl->nn_rows + *a.nrows : 0;
+    double emax = 0.0;
+    const T *Fvi = a.Fv + (size_t)i * d;
+    T *Ui = a.U + (size_t)i * d;
+    T *Gci = a.Gc + (size_t)i * d;
+    if (nn) {
+        // refit on the nearest stored pairs, then U_i = G + Y~^T alpha on
+        // columns j0 .. j1
+        double *K = scratch;                          // NN_MAX x NN_MAX
+        double *alpha = scratch + NN_MAX * NN_MAX;    // NN_MAX
+        int *sel = reinterpret_cast<int *>(alpha + NN_MAX);
+        const int m = nn_refit(a, n_store, wg, sel, alpha, K);
+        for (int j = j0 + t; j < j1; j += B) {
+            double c = 0.0;
+            for (int r = 0; r < m; ++r) c = fma(alpha[r], double(a.Ys[(size_t)sel[r] * d + j]), c);
+            const T gv = a.gtmp[j];
+            const T unew = T(double(gv) + c);
+            emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
+            Ui[j] = unew;
+            Gci[j] = gv;
+        }
+        if (i < N) {
+            __syncthreads();
+            hidden_partial(a, Ui, j0, j1, wg, scratch);
+            dist_partial(a, Ui, j0, j1, wg, n_store);
+        }
+    } else if (net) {
+        // readout W^T phi on columns j0 .. j1: wavefront w sums the neurons
+        // m = w, w + nw, ... for 2 tiles of 64 columns at a time, then
+        // wavefront q < 2 adds the nw partial sums of tile q in order
+        constexpr int TPT = 2;
+        const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;  // whole wavefronts, as above
+        const int lane = t & 63, wv = t >> 6;
+        double *sphi = scratch;                                        // M
+        double *red = scratch + ((a.M + 63) / 64) * 64;                // nw x TPT x WL
+        for (int m = t; m < a.M; m += B) sphi[m] = a.phi[m];
+        __syncthreads();
+        // FP32 weights with d even: lane l takes the adjacent columns
+        // jb + 2l, jb + 2l + 1 (one 8-byte load per neuron) instead of
+        // jb + l and jb + WL + l; the chunk bounds are even, so is d
+        bool pair = false;
+        if constexpr (sizeof(T) == 4) pair = d % 2 == 0;
+        auto tile = [&](const int jb, auto pair_tag) {
+            constexpr bool PAIR = decltype(pair_tag)::value;
+            static_assert(TPT == 2 || !PAIR, "a pair is two tiles");
+            double acc[TPT];
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
+            // batches of NB neurons x TPT columns (twice the batch for
+            // the FP32 pairs moved no faster and cost registers that the
+            // coarse solver's step loop then spilled)
+            constexpr int NB = 8;
+            for (int m0 = wv; m0 < a.M; m0 += NB * nw) {
+                double wr[NB][TPT];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int m = m0 + u * nw;
+                    if constexpr (PAIR) {
+                        const int j = jb + 2 * lane;
+                        float2 v = make_float2(0.0f, 0.0f);
+                        if (m < a.M && j < j1) v = *reinterpret_cast<const float2 *>(a.W + (size_t)m * d + j);
+                        wr[u][0] = v.x;
+                        wr[u][1] = v.y;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < TPT; ++q) {
+                            const int j = jb + WL * q + lane;
+                            wr[u][q] = (m < a.M && j < j1) ? double(a.W[(size_t)m * d + j]) : 0.0;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int m = m0 + u * nw;
+                    const double ph = m < a.M ? sphi[m] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < TPT; ++q) acc[q] = fma(wr[u][q], ph, acc[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) red[(wv * TPT + q) * WL + lane] = acc[q];
+        };
+        for (int jb = j0; jb < j1; jb += WL * TPT) {
+            if (wv < nw) {
+                if constexpr (sizeof(T) == 4) {
+                    if (pair) tile(jb, std::true_type{});
+                    else tile(jb, std::false_type{});
+                } else {
+                    tile(jb, std::false_type{});
+                }
+            }
+            __syncthreads();
+            for (int q = wv; q < TPT && wv < nw; q += nw) {
+                const int j = jb + WL * q + lane;
+                if (j < j1) {
+                    // partial sums of column j: tile q, lane l, or the pair layout
+                    const int x = j - jb, qq = pair ? (x & 1) : q, ll = pair ? (x >> 1) : lane;
+                    double c = 0.0;
+                    for (int w = 0; w < nw; ++w) c += red[(w * TPT + qq) * WL + ll];
+                    const T gv = a.gtmp[j];
+                    const T unew = T(double(gv) + c);
+                    emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
+                    Ui[j] = unew;
+                    Gci[j] = gv;
+                }
+            }
+            __syncthreads();
+        }
+        // hidden-layer partial sums of the new state's columns, for slot i + 1
+        if (i < N) hidden_partial(a, Ui, j0, j1, wg, scratch);
+    } else {
+        for (int j = j0 + t; j < j1; j += B) {
+            const T gv = a.gtmp[j];
+            const T unew = gv + (Fvi[j] - Gci[j]);
+            emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
+            Ui[j] = unew;
+            Gci[j] = gv;
+        }
+    }
+    // work-group maximum (order-free, NaN already mapped to +inf); only
+    // lanes that exist in a partial wavefront take part
+    {
+        const int wl = min(64, B - (t & ~63));
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(emax, off, 64);
+            if ((t & 63) + off < wl) emax = nan_max(emax, o);
+        }
+    }
+    __syncthreads();
+    if ((t & 63) == 0) scratch[t >> 6] = emax;
+    __syncthreads();
+    if (t == 0) {
+        double m = 0.0;
+        for (int w = 0; w < (B + 63) / 64; ++w) m = nan_max(m, scratch[w]);
+        a.part[(size_t)i * nwg + wg] = m;
+    }
+}
+
+// Stopping rule (eq. "stop_crit"), by work-group 0, thread 0.
+template <typename T, bool NN_OK>
+__device__ __forceinline__ void chain_seg_epi(const ChainArgs<T> &a, const int wg, const int nwg)
+{
+    if (wg != 0 || threadIdx.x != 0) return;
+    Ctrl *ctrl = a.ctrl;
+    const int L = ctrl->L, N = a.N;
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
+    const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
+    double chg = 0.0;
+    int Lnew = L + 1;
+    bool run = true;
+    for (int i = L + 2; i <= N; ++i) {
+        double e = 0.0;
+        for (int w = 0; w < nwg; ++w) e = nan_max(e, a.part[(size_t)i * nwg + w]);
+        chg = nan_max(chg, e);
+        if (run && e < a.eps) Lnew = i;
+        else run = false;
+    }
+    const int k = ctrl->k + 1;
+    ctrl->k = k;
+    ctrl->L = Lnew;
+    if (nn) ctrl->nn_rows = n_store;
+    if (Lnew >= N || k >= a.k_max) ctrl->done = 1;  // converged, or iteration cap reached
+    if (a.L_hist) a.L_hist[k] = Lnew;
+    if (a.chg_hist) a.chg_hist[k] = chg;
+}
+
+// One sweep of one instance in one launch: the segments separated by sync()
 // (a grid barrier, or a work-group barrier when nwg == 1).
-// TILED: the slot state does not fit one work-group; the coarse solver is
-// then run by the whole grid (tiled_coarse) instead of work-group 0.
-// NN_OK: the nearest-neighbour refit is compiled in (otherwise a kernel for
-// the other modes carries none of its code or registers).
 template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, bool TILED, bool NN_OK,
           typename Sync>
 __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, const int nwg, Sync sync,
@@ -413,10 +673,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
 {
     T *lds = reinterpret_cast<T *>(lds_raw);
     double *scratch = reinterpret_cast<double *>(lds_raw);
-    const int t = threadIdx.x, B = blockDim.x;
-    const Geom &g = a.g;
-    const int d = g.d;
-    Ctrl *ctrl = a.ctrl;
+    const int d = a.g.d;
 
     if (a.mode == CHAIN_SWEEP) {
         if constexpr (TILED) {
@@ -428,7 +685,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
             // k = 0 (single work-group): the state stays on chip from slot to slot
             if (wg != 0) return;
             for (int i = 1; i <= a.N; ++i) {
-                slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG,
+                slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(a.g, a.G_method, a.G_steps, a.dtG,
                                                                  a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d,
                                                                  lds, a.Gc + (size_t)i * d);
                 __syncthreads();
@@ -437,204 +694,53 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
         return;
     }
 
-    if (ctrl->done) return;  // same value in every work-group: nobody reaches a barrier
-    const int L = ctrl->L;
-    const int N = a.N;
-
-    // columns of this work-group
-    // (an even count, so that FP32 rows of even length start 8-byte aligned)
-    const int chunk = (((d + nwg - 1) / nwg) + 1) & ~1;
-    const int j0 = min(d, wg * chunk), j1 = min(d, j0 + chunk);
-
-    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
-    const bool net = a.mode == CHAIN_RANDNET || nn;
-    // stored pairs (this iteration's included)
-    const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
-    // exact slot, and the hidden-layer partial sums of its columns
-    for (int j = j0 + t; j < j1; j += B) a.U[(size_t)(L + 1) * d + j] = a.Fv[(size_t)(L + 1) * d + j];
-    if (net && L + 2 <= N) {
-        __syncthreads();
-        hidden_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, scratch);
-        if (nn) dist_partial(a, a.U + (size_t)(L + 1) * d, j0, j1, wg, n_store);
-    }
+    if (a.ctrl->done) return;  // same value in every work-group: nobody reaches a barrier
+    const int L = a.ctrl->L;
+    chain_seg_pro<T, NN_OK>(a, wg, nwg, scratch);
     sync();
-
-    for (int i = L + 2; i <= N; ++i) {
-        const T *x = a.U + (size_t)(i - 1) * d;
-        // ---- phase 1: coarse solve (work-group 0) and hidden layer (the others)
+    for (int i = L + 2; i <= a.N; ++i) {
         if constexpr (TILED) {
-            tiled_coarse<KIND, T>(a, x, a.gtmp, (T *)nullptr, wg, nwg, sync, lds);
-            if (net) hidden_finish(a, wg, nwg, nwg);
-            if (nn) dist_finish(a, wg, nwg, nwg, n_store);
+            tiled_coarse<KIND, T>(a, a.U + (size_t)(i - 1) * d, a.gtmp, (T *)nullptr, wg, nwg, sync, lds);
+            chain_seg_hidden_all<T, NN_OK>(a, wg, nwg);
         } else {
-            if (wg == 0) {
-                slot_propagate<KIND, T, CPT, DBUF, FULL, NX, NY>(g, a.G_method, a.G_steps, a.dtG, x, a.gtmp, lds);
-                __syncthreads();
-            }
-            if (net && (wg > 0 || nwg == 1)) hidden_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg);
-            if (nn && (wg > 0 || nwg == 1))
-                dist_finish(a, nwg == 1 ? 0 : wg - 1, nwg == 1 ? 1 : nwg - 1, nwg, n_store);
+            chain_seg_p1_onchip<KIND, T, CPT, DBUF, FULL, NX, NY, NN_OK>(a, i, wg, nwg, lds);
         }
         sync();
-
-        // ---- phase 2: readout, update and change norm on this block of columns
-        double emax = 0.0;
-        const T *Fvi = a.Fv + (size_t)i * d;
-        T *Ui = a.U + (size_t)i * d;
-        T *Gci = a.Gc + (size_t)i * d;
-        if (nn) {
-            // refit on the nearest stored pairs, then U_i = G + Y~^T alpha on
-            // columns j0 .. j1
-            double *K = scratch;                          // NN_MAX x NN_MAX
-            double *alpha = scratch + NN_MAX * NN_MAX;    // NN_MAX
-            int *sel = reinterpret_cast<int *>(alpha + NN_MAX);
-            const int m = nn_refit(a, n_store, wg, sel, alpha, K);
-            for (int j = j0 + t; j < j1; j += B) {
-                double c = 0.0;
-                for (int r = 0; r < m; ++r) c = fma(alpha[r], double(a.Ys[(size_t)sel[r] * d + j]), c);
-                const T gv = a.gtmp[j];
-                const T unew = T(double(gv) + c);
-                emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
-                Ui[j] = unew;
-                Gci[j] = gv;
-            }
-            if (i < N) {
-                __syncthreads();
-                hidden_partial(a, Ui, j0, j1, wg, scratch);
-                dist_partial(a, Ui, j0, j1, wg, n_store);
-            }
-        } else if (net) {
-            // readout W^T phi on columns j0 .. j1: wavefront w sums the neurons
-            // m = w, w + nw, ... for 2 tiles of 64 columns at a time, then
-            // wavefront q < 2 adds the nw partial sums of tile q in order
-            constexpr int TPT = 2;
-            const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;  // whole wavefronts, as above
-            const int lane = t & 63, wv = t >> 6;
-            double *sphi = scratch;                                        // M
-            double *red = scratch + ((a.M + 63) / 64) * 64;                // nw x TPT x WL
-            for (int m = t; m < a.M; m += B) sphi[m] = a.phi[m];
-            __syncthreads();
-            // FP32 weights with d even: lane l takes the adjacent columns
-            // jb + 2l, jb + 2l + 1 (one 8-byte load per neuron) instead of
-            // jb + l and jb + WL + l; the chunk bounds are even, so is d
-            bool pair = false;
-            if constexpr (sizeof(T) == 4) pair = d % 2 == 0;
-            auto tile = [&](const int jb, auto pair_tag) {
-                constexpr bool PAIR = decltype(pair_tag)::value;
-                static_assert(TPT == 2 || !PAIR, "a pair is two tiles");
-                double acc[TPT];
-#pragma unroll
-                for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
-                // batches of NB neurons x TPT columns (twice the batch for
-                // the FP32 pairs moved no faster and cost registers that the
-                // coarse solver's step loop then spilled)
-                constexpr int NB = 8;
-                for (int m0 = wv; m0 < a.M; m0 += NB * nw) {
-                    double wr[NB][TPT];
-#pragma unroll
-                    for (int u = 0; u < NB; ++u) {
-                        const int m = m0 + u * nw;
-                        if constexpr (PAIR) {
-                            const int j = jb + 2 * lane;
-                            float2 v = make_float2(0.0f, 0.0f);
-                            if (m < a.M && j < j1) v = *reinterpret_cast<const float2 *>(a.W + (size_t)m * d + j);
-                            wr[u][0] = v.x;
-                            wr[u][1] = v.y;
-                        } else {
-#pragma unroll
-                            for (int q = 0; q < TPT; ++q) {
-                                const int j = jb + WL * q + lane;
-                                wr[u][q] = (m < a.M && j < j1) ? double(a.W[(size_t)m * d + j]) : 0.0;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < NB; ++u) {
-                        const int m = m0 + u * nw;
-                        const double ph = m < a.M ? sphi[m] : 0.0;
-#pragma unroll
-                        for (int q = 0; q < TPT; ++q) acc[q] = fma(wr[u][q], ph, acc[q]);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < TPT; ++q) red[(wv * TPT + q) * WL + lane] = acc[q];
-            };
-            for (int jb = j0; jb < j1; jb += WL * TPT) {
-                if (wv < nw) {
-                    if constexpr (sizeof(T) == 4) {
-                        if (pair) tile(jb, std::true_type{});
-                        else tile(jb, std::false_type{});
-                    } else {
-                        tile(jb, std::false_type{});
-                    }
-                }
-                __syncthreads();
-                for (int q = wv; q < TPT && wv < nw; q += nw) {
-                    const int j = jb + WL * q + lane;
-                    if (j < j1) {
-                        // partial sums of column j: tile q, lane l, or the pair layout
-                        const int x = j - jb, qq = pair ? (x & 1) : q, ll = pair ? (x >> 1) : lane;
-                        double c = 0.0;
-                        for (int w = 0; w < nw; ++w) c += red[(w * TPT + qq) * WL + ll];
-                        const T gv = a.gtmp[j];
-                        const T unew = T(double(gv) + c);
-                        emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
-                        Ui[j] = unew;
-                        Gci[j] = gv;
-                    }
-                }
-                __syncthreads();
-            }
-            // hidden-layer partial sums of the new state's columns, for slot i + 1
-            if (i < N) hidden_partial(a, Ui, j0, j1, wg, scratch);
-        } else {
-            for (int j = j0 + t; j < j1; j += B) {
-                const T gv = a.gtmp[j];
-                const T unew = gv + (Fvi[j] - Gci[j]);
-                emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
-                Ui[j] = unew;
-                Gci[j] = gv;
-            }
-        }
-        // work-group maximum (order-free, NaN already mapped to +inf); only
-        // lanes that exist in a partial wavefront take part
-        {
-            const int wl = min(64, B - (t & ~63));
-            for (int off = 32; off > 0; off >>= 1) {
-                const double o = __shfl_down(emax, off, 64);
-                if ((t & 63) + off < wl) emax = nan_max(emax, o);
-            }
-        }
-        __syncthreads();
-        if ((t & 63) == 0) scratch[t >> 6] = emax;
-        __syncthreads();
-        if (t == 0) {
-            double m = 0.0;
-            for (int w = 0; w < (B + 63) / 64; ++w) m = nan_max(m, scratch[w]);
-            a.part[(size_t)i * nwg + wg] = m;
-        }
+        chain_seg_p2<T, NN_OK>(a, i, wg, nwg, scratch);
         sync();
     }
+    chain_seg_epi<T, NN_OK>(a, wg, nwg);
+}
 
-    // ---- stopping rule (eq. "stop_crit"), work-group 0
-    if (wg == 0 && t == 0) {
-        double chg = 0.0;
-        int Lnew = L + 1;
-        bool run = true;
-        for (int i = L + 2; i <= N; ++i) {
-            double e = 0.0;
-            for (int w = 0; w < nwg; ++w) e = nan_max(e, a.part[(size_t)i * nwg + w]);
-            chg = nan_max(chg, e);
-            if (run && e < a.eps) Lnew = i;
-            else run = false;
+// One segment of a sweep as a kernel of its own (captured graphs): seg 0 the
+// prologue; 1 phase 1 of slot i (tiled coarse solver: pass `pass` of it, the
+// hidden layer with pass 0); 2 phase 2 of slot i; 3 the stopping rule.
+// Work-groups return at once when the run is done or slot i is final.
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT, bool TILED, bool NN_OK>
+__global__ __launch_bounds__(MAXT) void k_chain_seg(const ChainArgs<T> *__restrict__ args, int seg, int i,
+                                                    long long pass)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const ChainArgs<T> &a = *args;
+    if (a.ctrl->done) return;
+    const int L = a.ctrl->L;
+    const int wg = blockIdx.x, nwg = gridDim.x;
+    double *scratch = reinterpret_cast<double *>(lds_raw);
+    if (seg == 0) {
+        chain_seg_pro<T, NN_OK>(a, wg, nwg, scratch);
+    } else if (seg == 3) {
+        chain_seg_epi<T, NN_OK>(a, wg, nwg);
+    } else {
+        if (i < L + 2) return;
+        if (seg == 2) {
+            chain_seg_p2<T, NN_OK>(a, i, wg, nwg, scratch);
+        } else if constexpr (TILED) {
+            tiled_coarse_pass<KIND, T>(a, a.U + (size_t)(i - 1) * a.g.d, a.gtmp, (T *)nullptr, pass, wg, nwg,
+                                       reinterpret_cast<T *>(lds_raw));
+            if (pass == 0) chain_seg_hidden_all<T, NN_OK>(a, wg, nwg);
+        } else {
+            chain_seg_p1_onchip<KIND, T, CPT, DBUF, FULL, NX, NY, NN_OK>(a, i, wg, nwg, reinterpret_cast<T *>(lds_raw));
         }
-        const int k = ctrl->k + 1;
-        ctrl->k = k;
-        ctrl->L = Lnew;
-        if (nn) ctrl->nn_rows = n_store;
-        if (Lnew >= N || k >= a.k_max) ctrl->done = 1;  // converged, or iteration cap reached
-        if (a.L_hist) a.L_hist[k] = Lnew;
-        if (a.chg_hist) a.chg_hist[k] = chg;
     }
 }
 
@@ -796,6 +902,66 @@ rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int n
     ChainLauncher<KIND, T> L{a, sh, nwg, st, max_wg};
     return visit_shape_kind<KIND, T>(a.g, sh, L);
 }
+
+// A sweep as a sequence of segment kernels (for capture in a graph): the
+// prologue, per slot i = 2..N phase 1 (the tiled coarse solver's passes) and
+// phase 2, then the stopping rule, each on nwg work-groups.
+template <int KIND, typename T>
+struct ChainSegLauncher {
+    const ChainArgs<T> *args;
+    const ChainArgs<T> &a;  // host copy: sizes, propagator, mode
+    const OnchipShape &sh;
+    int nwg;
+    hipStream_t st;
+
+    template <typename K>
+    rpr_status sequence(K kern, int block, size_t lds, long long passes)
+    {
+        static bool attr_set = false;
+        if (!attr_set) {
+            RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxLds));
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(block), lds, st, args, 0, 0, 0LL);
+        for (int i = 2; i <= a.N; ++i) {
+            for (long long pass = 0; pass < passes; ++pass)
+                hipLaunchKernelGGL(kern, dim3(nwg), dim3(block), lds, st, args, 1, i, pass);
+            hipLaunchKernelGGL(kern, dim3(nwg), dim3(block), lds, st, args, 2, i, 0LL);
+        }
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(block), lds, st, args, 3, 0, 0LL);
+        RPR_HIP(hipGetLastError());
+        return RPR_OK;
+    }
+
+    template <int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT>
+    rpr_status run()
+    {
+        const size_t lds = chain_lds(sh, a.M);
+        if (a.mode == CHAIN_RANDNET_NN)
+            return sequence(k_chain_seg<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, false, true>, sh.block, lds, 1);
+        return sequence(k_chain_seg<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, false, false>, sh.block, lds, 1);
+    }
+};
+
+template <int KIND, typename T>
+rpr_status launch_chain_graph_kind(const ChainArgs<T> *args_dev, const ChainArgs<T> &a, const OnchipShape &sh,
+                                   int nwg, hipStream_t st)
+{
+    ChainSegLauncher<KIND, T> L{args_dev, a, sh, nwg, st};
+    if (sh.maxt == TILED_THREADS) {
+        if constexpr (KIND == RPR_BURGERS1D) {
+            return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
+        } else {
+            return L.sequence(k_chain_seg<KIND, T, 1, false, false, 0, 0, TT_THREADS, true, true>, TT_THREADS,
+                              chain_lds(sh, a.M), coarse_passes(a.G_method, a.G_steps));
+        }
+    }
+    return visit_shape_kind<KIND, T>(a.g, sh, L);
+}
+
+template rpr_status launch_chain_graph_kind<RPR_KIND, RPR_REAL>(const ChainArgs<RPR_REAL> *, const ChainArgs<RPR_REAL> &,
+                                                                 const OnchipShape &, int, hipStream_t);
 
 // This file is compiled once per (right-hand side, precision) pair.
 template rpr_status launch_chain_kind<RPR_KIND, RPR_REAL>(const ChainArgs<RPR_REAL> &, const OnchipShape &,

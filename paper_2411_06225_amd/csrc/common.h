@@ -235,10 +235,19 @@ struct TiledWork {
 // Work-group size that selects the tiled propagator (states in memory).
 constexpr int TILED_THREADS = 256;
 
-// Tiled propagation of n states, one launch per RK stage (2D grids).
+// Tiled propagation of n states (2D grids): one launch per RK stage, or per
+// RK4 step for the systems with a one-pass form.  variant picks the tile
+// shape of the one-pass form (0 = the built-in default; see
+// fused_variants), ignored otherwise.
 template <int KIND, typename T>
 rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
-                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st);
+                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st, int variant);
+
+// Number of tile shapes of the one-pass RK4 form of right-hand side `kind` at
+// element size elem (1 where the kind has none: the variant is then ignored),
+// and a short name of shape v for the autotuner's records.
+int fused_variants(int kind, size_t elem);
+const char *fused_variant_name(int kind, size_t elem, int v);
 
 // Launch of the propagator: out[b] = P(in[b]) for b in [0, n), where the
 // work of state b is skipped when ctrl != nullptr and b < ctrl[0] (slot b + 1
@@ -248,7 +257,7 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
 template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in,
                             T *out, const int *ctrl, hipStream_t st, int max_threads = 1024,
-                            const TiledWork<T> *tw = nullptr);
+                            const TiledWork<T> *tw = nullptr, int variant = 0);
 
 // One instance of a batch, as the persistent fine-solve kernel sees it.
 template <typename T>

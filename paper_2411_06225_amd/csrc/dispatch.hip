@@ -84,15 +84,15 @@ rpr_status check_threads(const Geom &g, size_t elem, int threads)
 
 template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
-                            const int *ctrl, hipStream_t st, int max_threads, const TiledWork<T> *tw)
+                            const int *ctrl, hipStream_t st, int max_threads, const TiledWork<T> *tw, int variant)
 {
     if (n <= 0) return RPR_OK;
     if (max_threads == TILED_THREADS) {
         if (!tw) return fail(RPR_ERR_INVALID_ARG, "propagate: the tiled form needs work arrays");
         switch (g.kind) {
-        case RPR_DIFFREACT2D: return launch_prop_tiled_kind<RPR_DIFFREACT2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
-        case RPR_BRUSS2D: return launch_prop_tiled_kind<RPR_BRUSS2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
-        case RPR_SWE2D: return launch_prop_tiled_kind<RPR_SWE2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_DIFFREACT2D: return launch_prop_tiled_kind<RPR_DIFFREACT2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st, variant);
+        case RPR_BRUSS2D: return launch_prop_tiled_kind<RPR_BRUSS2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st, variant);
+        case RPR_SWE2D: return launch_prop_tiled_kind<RPR_SWE2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st, variant);
         default: return fail(RPR_ERR_UNSUPPORTED, "propagate: the tiled form serves 2D grids only");
         }
     }
@@ -108,9 +108,33 @@ rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt,
     }
 }
 template rpr_status launch_propagate<double>(const Geom &, int, int64_t, double, int, const double *, double *,
-                                             const int *, hipStream_t, int, const TiledWork<double> *);
+                                             const int *, hipStream_t, int, const TiledWork<double> *, int);
 template rpr_status launch_propagate<float>(const Geom &, int, int64_t, double, int, const float *, float *,
-                                            const int *, hipStream_t, int, const TiledWork<float> *);
+                                            const int *, hipStream_t, int, const TiledWork<float> *, int);
+
+// Tile shapes of the one-pass RK4 kernels (the order of the switches in
+// tiled.hip): shallow water (rows per wavefront R, wavefronts NW), the
+// Laplacian systems (tile rows FY, threads NT).
+namespace {
+const char *const kSweF32[] = {"R5NW8", "R4NW8", "R4NW10", "R8NW5", "R2NW16"};
+const char *const kSweF64[] = {"R4NW8", "R4NW6", "R3NW8", "R2NW12"};
+const char *const kLap[] = {"FY32NT512", "FY16NT256", "FY32NT256", "FY64NT512"};
+}  // namespace
+
+int fused_variants(int kind, size_t elem)
+{
+    if (kind == RPR_SWE2D) return elem == 4 ? 5 : 4;
+    if (kind == RPR_DIFFREACT2D || kind == RPR_BRUSS2D) return 4;
+    return 1;
+}
+
+const char *fused_variant_name(int kind, size_t elem, int v)
+{
+    if (v < 0 || v >= fused_variants(kind, elem)) return "default";
+    if (kind == RPR_SWE2D) return elem == 4 ? kSweF32[v] : kSweF64[v];
+    if (kind == RPR_DIFFREACT2D || kind == RPR_BRUSS2D) return kLap[v];
+    return "default";
+}
 
 size_t chain_lds(const OnchipShape &sh, int M)
 {
@@ -135,6 +159,23 @@ rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, h
 }
 template rpr_status launch_chain<double>(const ChainArgs<double> &, const OnchipShape &, int, hipStream_t, int *);
 template rpr_status launch_chain<float>(const ChainArgs<float> &, const OnchipShape &, int, hipStream_t, int *);
+
+template <typename T>
+rpr_status launch_chain_graph(const ChainArgs<T> *args_dev, const ChainArgs<T> &a, const OnchipShape &sh, int nwg,
+                              hipStream_t st)
+{
+    switch (a.g.kind) {
+    case RPR_BURGERS1D: return launch_chain_graph_kind<RPR_BURGERS1D, T>(args_dev, a, sh, nwg, st);
+    case RPR_DIFFREACT2D: return launch_chain_graph_kind<RPR_DIFFREACT2D, T>(args_dev, a, sh, nwg, st);
+    case RPR_BRUSS2D: return launch_chain_graph_kind<RPR_BRUSS2D, T>(args_dev, a, sh, nwg, st);
+    case RPR_SWE2D: return launch_chain_graph_kind<RPR_SWE2D, T>(args_dev, a, sh, nwg, st);
+    default: return fail(RPR_ERR_INVALID_ARG, "chain: unknown right-hand side");
+    }
+}
+template rpr_status launch_chain_graph<double>(const ChainArgs<double> *, const ChainArgs<double> &,
+                                               const OnchipShape &, int, hipStream_t);
+template rpr_status launch_chain_graph<float>(const ChainArgs<float> *, const ChainArgs<float> &, const OnchipShape &,
+                                              int, hipStream_t);
 
 template <typename T>
 rpr_status launch_prop_persistent(const BatchInst<T> *insts, const int2 *items, int n_items, int *counter,

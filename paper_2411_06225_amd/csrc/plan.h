@@ -95,6 +95,8 @@ struct rpr_plan {
     int autotune = 0;
     int use_graph = 0;
     int strict = 0;                     // opt.stability: 1 rejects solves the pre-check finds unstable
+    int fvar = 0;                       // tile shape of the fine propagator's one-pass form
+    bool fixed_nwg = false;             // opt.chain_wgs set: the autotuner keeps the chain grid
     double stab_F = 0, stab_G = 0;      // pre-check ratios dt / dt_max of the last execute
     hipGraph_t graph = nullptr;         // captured block of `poll` iterations
     hipGraphExec_t graph_exec = nullptr;
@@ -202,6 +204,8 @@ inline void nn_args(const rpr_plan *p, ChainArgs<T> &a)
 // Work-group size the autotuner chose for this propagator class (1024 when
 // it has not run for it).
 int tuned_prop_threads(const Geom &g, int esz, int method);
+// Tile shape of the one-pass RK4 form it chose (0 when it has not run).
+int tuned_variant(const Geom &g, int esz, int method);
 // Times the candidate launch shapes of plan p and keeps the fastest.
 template <typename T>
 rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus);

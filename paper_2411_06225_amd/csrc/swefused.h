@@ -90,18 +90,20 @@ __device__ __forceinline__ T swf_sqrt(T v)
     else return sqrt(v);
 }
 
-// Rusanov flux across one face between left state (h, m = normal momentum,
-// q = tangential momentum, f = m^2/h + g h^2/2, e = q m/h, s = |m/h| + sqrt(g h))
-// and right state: (mass, normal, tangential) components.
+// Twice the Rusanov flux across one face between left state (h, m = normal
+// momentum, q = tangential momentum, f = m^2/h + g h^2/2, e = q m/h,
+// s = |m/h| + sqrt(g h)) and right state: (mass, normal, tangential)
+// components of (f_L + f_R) - a (q_R - q_L).  The factor 1/2 of the flux is
+// folded into the grid factors of the update: halving is exact, so the
+// update equals the one with the halved flux bit for bit.
 template <typename T>
 __device__ __forceinline__ void swf_face(T hL, T mL, T qL, T fL, T eL, T sL, T hR, T mR, T qR, T fR, T eR, T sR,
                                          T &Fh, T &Fm, T &Fq)
 {
-    const T half = T(0.5);
-    const T a = sL > sR ? sL : sR;
-    Fh = half * (mL + mR) - half * a * (hR - hL);
-    Fm = half * (fL + fR) - half * a * (mR - mL);
-    Fq = half * (eL + eR) - half * a * (qR - qL);
+    const T a = fmax(sL, sR);
+    Fh = (mL + mR) - a * (hR - hL);
+    Fm = (fL + fR) - a * (mR - mL);
+    Fq = (eL + eR) - a * (qR - qL);
 }
 
 // One RK4 step of one tile: src -> dst, both full slot states (d values);
@@ -120,7 +122,8 @@ __device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, cons
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int tx = tile % swf_tiles_x(g), ty = tile / swf_tiles_x(g);
     const int x0 = tx * SWF_X, y0 = ty * S::TY;
-    const T gg = T(g.p[0]), idx = T(g.idx), idy = T(g.idy), half = T(0.5);
+    // flux-difference factors with the flux's 1/2 folded in (swf_face)
+    const T gg = T(g.p[0]), idx = T(0.5 * g.idx), idy = T(0.5 * g.idy), half = T(0.5);
     const T dtT = T(dt), hdt = T(0.5 * dt), dt6 = T(dt / 6.0);
 
     // ---- load: the region with mirror ghosts beyond the walls
@@ -161,23 +164,20 @@ __device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, cons
 #pragma unroll
     for (int s = 1; s <= 4; ++s) {
         T *eb = lds + (size_t)(s & 1) * NW * 2 * 6 * 64;  // this stage's edge-row buffer
-        // per-cell quantities of the rows whose values are still valid
+        // per-cell quantities (rows outside this stage's region hold
+        // finite stale values: h stays positive, nothing divides by zero)
         T xf[R], xe[R], xs[R], yf[R], ye[R], ys[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int r = wv * R + q;
-            xf[q] = xe[q] = xs[q] = yf[q] = ye[q] = ys[q] = T(0);
-            if (r >= s - 1 && r < RY - s + 1) {
-                const T h = y[q][0], m = y[q][1], n = y[q][2];
-                const T rh = swf_rcp(h);
-                const T vx = m * rh, vy = n * rh, c = swf_sqrt(gg * h), P = half * gg * h * h;
-                xf[q] = m * vx + P;
-                xe[q] = n * vx;
-                xs[q] = fabs(vx) + c;
-                yf[q] = n * vy + P;
-                ye[q] = m * vy;
-                ys[q] = fabs(vy) + c;
-            }
+            const T h = y[q][0], m = y[q][1], n = y[q][2];
+            const T rh = swf_rcp(h);
+            const T vx = m * rh, vy = n * rh, c = swf_sqrt(gg * h), P = half * gg * h * h;
+            xf[q] = m * vx + P;
+            xe[q] = n * vx;
+            xs[q] = fabs(vx) + c;
+            yf[q] = n * vy + P;
+            ye[q] = m * vy;
+            ys[q] = fabs(vy) + c;
         }
         // edge rows to LDS: [wave][row 0 | row R-1][h, m, n, yf, ye, ys][lane]
         {

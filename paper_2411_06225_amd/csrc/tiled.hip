@@ -97,9 +97,33 @@ static rpr_status launch_swe_fused(const Geom &g, int64_t steps, double dt, int 
     return RPR_OK;
 }
 
+template <int KIND, typename T, int FY, int NT>
+static rpr_status launch_lap_fused(const Geom &g, int64_t steps, double dt, int n, const T *in, T *out,
+                                   const TiledWork<T> &w, const int *ctrl, hipStream_t st)
+{
+    auto kern = k_prop_rk4_fused<KIND, T, FY, NT>;
+    const size_t flds = rk4_fused_lds<FY>(g, sizeof(T));
+    if (flds > 64 * 1024) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxLds));
+            attr_set = true;
+        }
+    }
+    if ((long long)fused_tiles_of<FY>(g) * n > 0x7fffffffLL)
+        return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 2^31 tiles per launch");
+    const dim3 fgrid((unsigned)(fused_tiles_of<FY>(g) * n));
+    for (long long s = 0; s < (long long)steps; ++s) {
+        hipLaunchKernelGGL(kern, fgrid, dim3(NT), flds, st, g, s, (long long)steps, dt, n, in, out, w, ctrl);
+        RPR_HIP(hipGetLastError());
+    }
+    return RPR_OK;
+}
+
 template <int KIND, typename T>
 rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
-                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st)
+                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st, int variant)
 {
     if constexpr (KIND == RPR_BURGERS1D) {
         return fail(RPR_ERR_UNSUPPORTED, "the tiled propagator serves 2D grids only");
@@ -114,25 +138,34 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
             // a whole RK4 step per pass over 56-column tiles with a 4-cell
             // halo (mirror ghosts need 4 cells inside each wall)
             if (method == RPR_RK4 && g.nx >= SWF_HALO && g.ny >= SWF_HALO) {
-                if constexpr (sizeof(T) == 4) return launch_swe_fused<T, 4, 10>(g, steps, dt, n, in, out, w, ctrl, st);
-                else return launch_swe_fused<T, 4, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+                if constexpr (sizeof(T) == 4) {
+                    switch (variant) {
+                    case 1: return launch_swe_fused<T, 4, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 2: return launch_swe_fused<T, 4, 10>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 3: return launch_swe_fused<T, 8, 5>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 4: return launch_swe_fused<T, 2, 16>(g, steps, dt, n, in, out, w, ctrl, st);
+                    default: return launch_swe_fused<T, 5, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+                    }
+                } else {
+                    switch (variant) {
+                    case 1: return launch_swe_fused<T, 4, 6>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 2: return launch_swe_fused<T, 3, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 3: return launch_swe_fused<T, 2, 12>(g, steps, dt, n, in, out, w, ctrl, st);
+                    default: return launch_swe_fused<T, 4, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+                    }
+                }
             }
         }
         if constexpr (KIND == RPR_DIFFREACT2D || KIND == RPR_BRUSS2D) {
             if (method == RPR_RK4) {
                 // a whole step per pass: the Laplacian right-hand side is
                 // cheap to recompute on a 4-cell halo
-                constexpr int FY = FUSED_FY, NT = FUSED_NT;
-                if ((long long)fused_tiles_of<FY>(g) * n > 0x7fffffffLL)
-                    return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 2^31 tiles per launch");
-                const dim3 fgrid((unsigned)(fused_tiles_of<FY>(g) * n));
-                const size_t flds = rk4_fused_lds<FY>(g, sizeof(T));
-                for (long long s = 0; s < ns; ++s) {
-                    hipLaunchKernelGGL((k_prop_rk4_fused<KIND, T, FY, NT>), fgrid, dim3(NT), flds, st, g, s, ns, dt,
-                                       n, in, out, w, ctrl);
-                    RPR_HIP(hipGetLastError());
+                switch (variant) {
+                case 1: return launch_lap_fused<KIND, T, 16, 256>(g, steps, dt, n, in, out, w, ctrl, st);
+                case 2: return launch_lap_fused<KIND, T, 32, 256>(g, steps, dt, n, in, out, w, ctrl, st);
+                case 3: return launch_lap_fused<KIND, T, 64, 512>(g, steps, dt, n, in, out, w, ctrl, st);
+                default: return launch_lap_fused<KIND, T, FUSED_FY, FUSED_NT>(g, steps, dt, n, in, out, w, ctrl, st);
                 }
-                return RPR_OK;
             }
         }
         for (long long s = 0; s < ns; ++s) {
@@ -158,6 +191,6 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
 template rpr_status launch_prop_tiled_kind<RPR_KIND, RPR_REAL>(const Geom &, int, int64_t, double, int,
                                                                 const RPR_REAL *, RPR_REAL *,
                                                                 const TiledWork<RPR_REAL> &, const int *,
-                                                                hipStream_t);
+                                                                hipStream_t, int);
 
 }  // namespace rpr
