@@ -333,6 +333,21 @@ rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int32_t activat
                                 void *stream);
 
 /*
+ * rpr_randnet_features for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the split-K partial sums in
+ * a 16 MiB scratch array that the library keeps per device until the
+ * process ends; nothing is allocated or freed.  The partial sums need
+ * ceil(d / 512) (at most 64) x n x M doubles; larger calls return
+ * RPR_ERR_INVALID_ARG before anything is enqueued.  Every call on one device
+ * shares that device's scratch: calls that overlap on one GPU (two streams,
+ * two threads) race and must be serialised by the caller.
+ */
+rpr_status rpr_randnet_features_noalloc(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
+                                        const double *A, const double *zeta, const double *X, double *Phi,
+                                        void *stream);
+
+/*
  * Split-bfloat16 features, the training features of RPR_MIXED plans: x/s and
  * A are each split into three bfloat16 pieces (each the bfloat16 rounding of
  * what the previous pieces leave), the six products of the pieces down to

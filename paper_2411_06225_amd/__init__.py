@@ -37,7 +37,7 @@ RPR_FEAT_AUTO, RPR_FEAT_FP64, RPR_FEAT_BF16 = 0, 1, 2
 EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
             "rpr_plan_history", "rpr_plan_destroy", "rpr_propagate", "rpr_randnet_features", "rpr_ridge_fit",
             "rpr_randnet_readout", "rpr_uniform_pm1", "rpr_randnet_features_bf16", "rpr_plan_create_batch",
-            "rpr_plan_execute_batch", "rpr_plan_instance", "rpr_stability")
+            "rpr_plan_execute_batch", "rpr_plan_instance", "rpr_stability", "rpr_randnet_features_noalloc")
 
 
 class RprError(RuntimeError):
@@ -98,6 +98,14 @@ def lib() -> C.CDLL:
     """The loaded librpr.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system's; importing it first makes the process load that one, and
+        # librpr binds to it (loaded the other way round, torch and librpr
+        # end up with runtimes that do not share the device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_06225_amd.build` "
                               "(there is no CPU fallback)")
@@ -123,6 +131,7 @@ def lib() -> C.CDLL:
                                     vp]),
             "rpr_randnet_features": (i32, [i32, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
             "rpr_randnet_features_bf16": (i32, [i32, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
+            "rpr_randnet_features_noalloc": (i32, [i32, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
             "rpr_ridge_fit": (i32, [i32, i32, i32, vp, vp, dbl, vp, vp]),
             "rpr_randnet_readout": (i32, [i32, i32, i32, vp, vp, vp, vp]),
             "rpr_uniform_pm1": (i32, [u64, u64, i64, vp, vp]),
@@ -209,6 +218,14 @@ def rpr_randnet_features(M: int, d: int, n: int, activation: int, s: float, A, z
                                             _dev(A, "float64", M * d, "A"), _dev(zeta, "float64", M, "zeta"),
                                             _dev(X, "float64", n * d, "X"), _dev(Phi, "float64", n * M, "Phi"),
                                             _stream(stream)))
+
+
+def rpr_randnet_features_noalloc(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi,
+                                 stream=None) -> int:
+    return check(lib().rpr_randnet_features_noalloc(int(M), int(d), int(n), int(activation), float(s),
+                                                    _dev(A, "float64", M * d, "A"), _dev(zeta, "float64", M, "zeta"),
+                                                    _dev(X, "float64", n * d, "X"), _dev(Phi, "float64", n * M, "Phi"),
+                                                    _stream(stream)))
 
 
 def rpr_randnet_features_bf16(M: int, d: int, n: int, activation: int, s: float, A, zeta, X, Phi,

@@ -1,7 +1,41 @@
 // blocks.hip -- the building-block entry points of the C ABI: the same kernels
 // a plan runs, one call each.
+#include <map>
+#include <mutex>
+
 #include "plan.h"
 
+namespace rpr {
+
+// Scratch of the entry points that allocate nothing (16 MiB per device, held
+// until the process ends).  Host code never uses the symbol itself: it is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+constexpr size_t kScratchDoubles = (size_t)2 << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static std::map<int, double *> g_scratch_ptr;
+
+static rpr_status scratch_address(double **out)
+{
+    int dev = 0;
+    RPR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    const auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return RPR_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    *out = static_cast<double *>(ptr);
+    return RPR_OK;
+}
+
+}  // namespace rpr
 
 // ------------------------------------------------------- building blocks --
 extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propagator *P, int32_t precision,
@@ -74,6 +108,27 @@ extern "C" rpr_status rpr_randnet_features(int32_t M, int32_t d, int32_t n, int3
     const rpr_status rc = launch_features<double>(n, M, d, activation, 1.0 / s, A, zeta, X, Phi, part, nullptr, st);
     RPR_HIP(hipFreeAsync(part, st));
     return rc;
+}
+
+extern "C" rpr_status rpr_randnet_features_noalloc(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
+                                                   const double *A, const double *zeta, const double *X,
+                                                   double *Phi, void *stream)
+{
+    if (M < 1 || d < 1 || n < 0) return fail(RPR_ERR_INVALID_ARG, "need M >= 1, d >= 1, n >= 0");
+    if (activation != RPR_TANH && activation != RPR_RELU) return fail(RPR_ERR_INVALID_ARG, "bad activation");
+    if (!(s > 0) || !is_finite(s)) return fail(RPR_ERR_INVALID_ARG, "s must be > 0");
+    if (n == 0) return RPR_OK;
+    if (!A || !zeta || !X || !Phi) return fail(RPR_ERR_INVALID_ARG, "NULL device pointer");
+    const size_t need = (size_t)feat_splits(d) * (size_t)n * (size_t)M;
+    if (need > kScratchDoubles)
+        return fail(RPR_ERR_INVALID_ARG, "rpr_randnet_features_noalloc: the split-K partial sums need " +
+                                             std::to_string(need) + " doubles (K splits x n x M), more than the " +
+                                             std::to_string(kScratchDoubles) + " of the scratch (16 MiB)");
+    RPR_TRY(check_device());
+    double *part = nullptr;
+    RPR_TRY(scratch_address(&part));
+    return launch_features<double>(n, M, d, activation, 1.0 / s, A, zeta, X, Phi, part, nullptr,
+                                   static_cast<hipStream_t>(stream));
 }
 
 extern "C" rpr_status rpr_randnet_features_bf16(int32_t M, int32_t d, int32_t n, int32_t activation, double s,
