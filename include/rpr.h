@@ -63,21 +63,27 @@ typedef enum {
                             p = (Du, Dv, c); d = 2 nx ny, layout [u; v] */
     RPR_BRUSS2D = 2,     /* App. E: Brusselator, periodic; p = (A, B, Du, Dv);
                             d = 2 nx ny, layout [u; v] */
-    RPR_SWE2D = 3        /* Sec. 5.3: shallow water (h, hu, hv), flat bottom, first-order
+    RPR_SWE2D = 3,       /* Sec. 5.3: shallow water (h, hu, hv), flat bottom, first-order
                             finite volumes with the Rusanov flux, reflective walls;
                             p[0] = g; d = 3 nx ny, layout [h; hu; hv] */
+    RPR_BRUSS3D = 4      /* App. E: Brusselator in three dimensions, periodic, seven-point
+                            Laplacian on the box (x0, x1) x (y0, y1) x (x0, x1);
+                            p = (A, B, Du, Dv); d = 2 nx ny nz, layout [u; v] with
+                            cell (i, j, l) at i + nx (j + ny l) */
 } rpr_rhs_kind;
 
 typedef struct {
     int32_t kind;              /* rpr_rhs_kind */
-    int32_t nx, ny;            /* points (1D) or cells (2D) per direction; ny = 1 in 1D */
-    int32_t reserved;          /* must be 0 */
+    int32_t nx, ny;            /* points (1D) or cells (2D, 3D) per direction; ny = 1 in 1D */
+    int32_t nz;                /* cells along z: >= 1 for RPR_BRUSS3D, 0 or 1 otherwise */
     double x0, x1, y0, y1;     /* domain; grid spacing (x1 - x0) / nx, (y1 - y0) / ny */
     double p[6];               /* physical parameters, see rpr_rhs_kind */
 } rpr_rhs;
 
 /* ---- propagators F and G (Sec. 2; App. G setup tables) ------------------ */
-typedef enum { RPR_RK1 = 1, RPR_RK4 = 4 } rpr_method; /* forward Euler, classical RK4 */
+/* forward Euler, classical RK4, and the eighth-order 11-stage method of
+ * Cooper and Verner (1972), the paper's fine solver for the 3D Brusselator */
+typedef enum { RPR_RK1 = 1, RPR_RK4 = 4, RPR_RK8 = 8 } rpr_method;
 
 typedef struct {
     int32_t method;            /* rpr_method */
@@ -91,7 +97,10 @@ typedef struct {
                                   one pass over 64 x 16-cell tiles per RK stage, or
                                   for RK4 on the 5-point Laplacian systems one pass
                                   per step over 64 x 32-cell tiles with a 4-cell
-                                  halo).
+                                  halo); 128 selects the generic form (any
+                                  method, slot states in memory, one pass per
+                                  stage over the cells of all states), the
+                                  only form of RPR_RK8 and of RPR_BRUSS3D.
                                   Other sizes give RPR_ERR_INVALID_ARG, sizes
                                   without a kernel RPR_ERR_UNSUPPORTED.  Batch
                                   plans choose their own and ignore it. */

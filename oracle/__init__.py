@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["rhs.c", "integrate.c", "randnet.c", "parareal.c", "stability.c"]
 
-BURGERS1D, DIFFREACT2D, BRUSS2D, SWE2D = 0, 1, 2, 3
+BURGERS1D, DIFFREACT2D, BRUSS2D, SWE2D, BRUSS3D = 0, 1, 2, 3, 4
 TANH, RELU = 0, 1
 CORR_RANDNET, CORR_PARAREAL, CORR_RANDNET_NN = 0, 1, 2
 
@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 
 
 class Problem(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("p", C.c_double * 6)]
 
@@ -98,6 +98,8 @@ def lib():
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_uniform_pm1.restype = None
         L.orc_uniform_pm1.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, dp]
+        L.orc_rk_tableau.restype = C.c_int32
+        L.orc_rk_tableau.argtypes = [C.c_int32, C.POINTER(C.c_int32), dp, dp, dp]
         L.orc_stability.restype = C.c_double
         L.orc_stability.argtypes = [C.POINTER(Problem), C.c_int32, C.c_double, dp]
         L.orc_input_scale.restype = C.c_double
@@ -117,10 +119,20 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def problem(kind: int, nx: int, ny: int = 1, domain=(-1.0, 1.0, -1.0, 1.0), params=()) -> Problem:
+def problem(kind: int, nx: int, ny: int = 1, domain=(-1.0, 1.0, -1.0, 1.0), params=(), nz: int = 0) -> Problem:
     p = (C.c_double * 6)(*([float(v) for v in params] + [0.0] * (6 - len(params))))
     x0, x1, y0, y1 = (float(v) for v in domain)
-    return Problem(int(kind), int(nx), int(ny), 0, x0, x1, y0, y1, p)
+    return Problem(int(kind), int(nx), int(ny), int(nz), x0, x1, y0, y1, p)
+
+
+def rk_tableau(method: int):
+    """(A, b, c) of the oracle's explicit Runge-Kutta method `method`."""
+    s = C.c_int32(0)
+    A, b, c = np.zeros(256), np.zeros(16), np.zeros(16)
+    if lib().orc_rk_tableau(int(method), C.byref(s), _dp(A), _dp(b), _dp(c)):
+        raise ValueError(f"no tableau for method {method}")
+    n = s.value
+    return A[: n * n].reshape(n, n).copy(), b[:n].copy(), c[:n].copy()
 
 
 def dim(pb: Problem) -> int:

@@ -7,6 +7,7 @@
  * methods with a fixed number of steps per slice (App. G setup tables):
  * forward Euler (RK1) and classical fourth-order Runge-Kutta (RK4).
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
@@ -43,19 +44,139 @@ static int rk4_steps(const orc_problem *pb, int64_t steps, double dt, double *u,
     return 0;
 }
 
+/*
+ * Eighth-order explicit Runge-Kutta method of Cooper and Verner (SIAM J.
+ * Numer. Anal. 9, 1972), 11 stages, with r = sqrt(21):
+ *   c = (0, 1/2, 1/2, (7+r)/14, (7+r)/14, 1/2, (7-r)/14, (7-r)/14, 1/2,
+ *        (7+r)/14, 1),
+ *   b = (1/20, 0, 0, 0, 0, 0, 0, 49/180, 16/45, 49/180, 1/20),
+ * and the coefficients a_ij below (the paper's fine solver of the Burgers
+ * experiments is an RK8; it names no tableau).  Stage i: Y_i = u + dt
+ * sum_j a_ij k_j, k_i = h(Y_i); step: u <- u + dt sum_i b_i k_i.
+ */
+static void cooper_verner(double *A, double *b, double *c)
+{
+    const double r = sqrt(21.0);
+    for (int i = 0; i < 11 * 11; ++i) A[i] = 0.0;
+#define a(i, j) A[(i) * 11 + (j)]
+    a(1, 0) = 1.0 / 2.0;
+    a(2, 0) = 1.0 / 4.0;
+    a(2, 1) = 1.0 / 4.0;
+    a(3, 0) = 1.0 / 7.0;
+    a(3, 1) = (-7.0 - 3.0 * r) / 98.0;
+    a(3, 2) = (21.0 + 5.0 * r) / 49.0;
+    a(4, 0) = (11.0 + r) / 84.0;
+    a(4, 2) = (18.0 + 4.0 * r) / 63.0;
+    a(4, 3) = (21.0 - r) / 252.0;
+    a(5, 0) = (5.0 + r) / 48.0;
+    a(5, 2) = (9.0 + r) / 36.0;
+    a(5, 3) = (-231.0 + 14.0 * r) / 360.0;
+    a(5, 4) = (63.0 - 7.0 * r) / 80.0;
+    a(6, 0) = (10.0 - r) / 42.0;
+    a(6, 2) = (-432.0 + 92.0 * r) / 315.0;
+    a(6, 3) = (633.0 - 145.0 * r) / 90.0;
+    a(6, 4) = (-504.0 + 115.0 * r) / 70.0;
+    a(6, 5) = (63.0 - 13.0 * r) / 35.0;
+    a(7, 0) = 1.0 / 14.0;
+    a(7, 4) = (14.0 - 3.0 * r) / 126.0;
+    a(7, 5) = (13.0 - 3.0 * r) / 63.0;
+    a(7, 6) = 1.0 / 9.0;
+    a(8, 0) = 1.0 / 32.0;
+    a(8, 4) = (91.0 - 21.0 * r) / 576.0;
+    a(8, 5) = 11.0 / 72.0;
+    a(8, 6) = (-385.0 - 75.0 * r) / 1152.0;
+    a(8, 7) = (63.0 + 13.0 * r) / 128.0;
+    a(9, 0) = 1.0 / 14.0;
+    a(9, 4) = 1.0 / 9.0;
+    a(9, 5) = (-733.0 - 147.0 * r) / 2205.0;
+    a(9, 6) = (515.0 + 111.0 * r) / 504.0;
+    a(9, 7) = (-51.0 - 11.0 * r) / 56.0;
+    a(9, 8) = (132.0 + 28.0 * r) / 245.0;
+    a(10, 4) = (-42.0 + 7.0 * r) / 18.0;
+    a(10, 5) = (-18.0 + 28.0 * r) / 45.0;
+    a(10, 6) = (-273.0 - 53.0 * r) / 72.0;
+    a(10, 7) = (301.0 + 53.0 * r) / 72.0;
+    a(10, 8) = (28.0 - 28.0 * r) / 45.0;
+    a(10, 9) = (49.0 - 7.0 * r) / 18.0;
+#undef a
+    const double bb[11] = {1.0 / 20.0, 0, 0, 0, 0, 0, 0, 49.0 / 180.0, 16.0 / 45.0, 49.0 / 180.0, 1.0 / 20.0};
+    for (int i = 0; i < 11; ++i) {
+        b[i] = bb[i];
+        double s = 0.0;
+        for (int j = 0; j < i; ++j) s += A[i * 11 + j];
+        c[i] = s;
+    }
+}
+
+int32_t orc_rk_tableau(int32_t method, int32_t *s, double *A, double *b, double *c)
+{
+    for (int i = 0; i < 16 * 16; ++i) A[i] = 0.0;
+    if (method == 1) {
+        *s = 1;
+        b[0] = 1.0;
+        c[0] = 0.0;
+        return 0;
+    }
+    if (method == 4) {
+        /* classical RK4 (Kutta 1901), as rk4_steps applies it */
+        *s = 4;
+        A[1 * 4 + 0] = 0.5;
+        A[2 * 4 + 1] = 0.5;
+        A[3 * 4 + 2] = 1.0;
+        const double bb[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}, cc[4] = {0.0, 0.5, 0.5, 1.0};
+        for (int i = 0; i < 4; ++i) { b[i] = bb[i]; c[i] = cc[i]; }
+        return 0;
+    }
+    if (method == 8) {
+        *s = 11;
+        cooper_verner(A, b, c);
+        return 0;
+    }
+    return -1;
+}
+
+/* Any explicit tableau: stage i evaluates h at Y_i = u + dt sum_{j<i} a_ij k_j,
+ * the step adds dt sum_i b_i k_i. */
+static int erk_steps(const orc_problem *pb, int s, const double *A, const double *b, int64_t steps, double dt,
+                     double *u, double *work)
+{
+    const int d = orc_dim(pb);
+    double *y = work, *k = work + d;  /* k: s x d */
+    for (int64_t st = 0; st < steps; ++st) {
+        for (int i = 0; i < s; ++i) {
+            for (int j = 0; j < d; ++j) {
+                double acc = 0.0;
+                for (int l = 0; l < i; ++l) acc += A[i * s + l] * k[(size_t)l * d + j];
+                y[j] = u[j] + dt * acc;
+            }
+            if (orc_rhs(pb, y, k + (size_t)i * d)) return -1;
+        }
+        for (int j = 0; j < d; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i < s; ++i) acc += b[i] * k[(size_t)i * d + j];
+            u[j] = u[j] + dt * acc;
+        }
+    }
+    return 0;
+}
+
 int32_t orc_propagate(const orc_problem *pb, int32_t method, int64_t steps, double dt,
                       const double *in, double *out)
 {
     const int d = orc_dim(pb);
     if (d <= 0 || steps < 0) return -1;
     double *u = malloc(sizeof(double) * d);
-    double *work = malloc(sizeof(double) * 5 * d);
+    double *work = malloc(sizeof(double) * 12 * d);
     if (!u || !work) { free(u); free(work); return -4; }
     memcpy(u, in, sizeof(double) * d);
     int rc;
     if (method == 1) rc = euler_steps(pb, steps, dt, u, work);
     else if (method == 4) rc = rk4_steps(pb, steps, dt, u, work);
-    else rc = -1;
+    else if (method == 8) {
+        double A[11 * 11], b[11], c[11];
+        cooper_verner(A, b, c);
+        rc = erk_steps(pb, 11, A, b, steps, dt, u, work);
+    } else rc = -1;
     if (rc == 0) memcpy(out, u, sizeof(double) * d);
     free(u);
     free(work);

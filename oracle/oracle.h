@@ -35,14 +35,14 @@ extern "C" {
 #endif
 
 /* ---- problem definition ------------------------------------------------ */
-enum { ORC_BURGERS1D = 0, ORC_DIFFREACT2D = 1, ORC_BRUSS2D = 2, ORC_SWE2D = 3 };
+enum { ORC_BURGERS1D = 0, ORC_DIFFREACT2D = 1, ORC_BRUSS2D = 2, ORC_SWE2D = 3, ORC_BRUSS3D = 4 };
 
 typedef struct {
     int32_t kind;          /* ORC_* */
     int32_t nx, ny;        /* grid points / cells per direction (ny = 1 in 1D) */
-    int32_t pad;
+    int32_t nz;            /* cells along z (3D Brusselator; ignored otherwise), z in (x0, x1) */
     double x0, x1, y0, y1; /* domain */
-    double p[6];           /* Burgers: nu | DR: Du, Dv, c | Bruss: A, B, Du, Dv | SWE: g */
+    double p[6];           /* Burgers: nu | DR: Du, Dv, c | Bruss (2D, 3D): A, B, Du, Dv | SWE: g */
 } orc_problem;
 
 int32_t orc_nspecies(const orc_problem *pb);
@@ -51,8 +51,14 @@ int32_t orc_dim(const orc_problem *pb);
 /* h(u) written into out (both length orc_dim). Returns 0, or -1 on a bad problem. */
 int32_t orc_rhs(const orc_problem *pb, const double *u, double *out);
 
+/* Butcher tableau of an explicit Runge-Kutta method (method 1, 4 or 8):
+ * *s stages, A (s x s, row-major, strictly lower), b (s), c (s); arrays of
+ * at least 16 x 16, 16, 16.  Returns 0, or -1 for an unknown method. */
+int32_t orc_rk_tableau(int32_t method, int32_t *s, double *A, double *b, double *c);
+
 /* One slice of a fixed-step explicit Runge-Kutta method.
- * method: 1 = forward Euler (RK1), 4 = classical RK4.
+ * method: 1 = forward Euler (RK1), 4 = classical RK4, 8 = the eighth-order
+ * method of Cooper and Verner (11 stages).
  * steps: number of steps; dt: step length.  in and out may alias. */
 int32_t orc_propagate(const orc_problem *pb, int32_t method, int64_t steps, double dt,
                       const double *in, double *out);

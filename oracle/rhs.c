@@ -14,13 +14,20 @@ int32_t orc_nspecies(const orc_problem *pb)
     case ORC_DIFFREACT2D: return 2;
     case ORC_BRUSS2D: return 2;
     case ORC_SWE2D: return 3;
+    case ORC_BRUSS3D: return 2;
     default: return 0;
     }
 }
 
+/* cells along z: pb->nz for the 3D system, 1 otherwise */
+static int zcells(const orc_problem *pb)
+{
+    return pb->kind == ORC_BRUSS3D ? pb->nz : 1;
+}
+
 int32_t orc_dim(const orc_problem *pb)
 {
-    return orc_nspecies(pb) * pb->nx * pb->ny;
+    return orc_nspecies(pb) * pb->nx * pb->ny * zcells(pb);
 }
 
 /*
@@ -109,6 +116,39 @@ static void rhs_bruss(const orc_problem *pb, const double *s, double *h)
 }
 
 /*
+ * Brusselator in three dimensions (App. E): the same reaction as in 2D,
+ *   u_t = Du lap u + A - (B + 1) u + u^2 v,   v_t = Dv lap v + B u - u^2 v,
+ * on the periodic box (x0, x1) x (y0, y1) x (x0, x1) (App. E takes (-1, 1)^3)
+ * with nx x ny x nz cells, the seven-point Laplacian
+ *   (f[x-1] - 2 f + f[x+1]) / dx^2 + (same in y) / dy^2 + (same in z) / dz^2,
+ * and layout [u; v], each field [z][y][x] with x fastest.
+ */
+static void rhs_bruss3d(const orc_problem *pb, const double *s, double *h)
+{
+    const int nx = pb->nx, ny = pb->ny, nz = pb->nz, nc = nx * ny * nz;
+    const double dx = (pb->x1 - pb->x0) / nx, dy = (pb->y1 - pb->y0) / ny, dz = (pb->x1 - pb->x0) / nz;
+    const double A = pb->p[0], B = pb->p[1], Du = pb->p[2], Dv = pb->p[3];
+    for (int f = 0; f < 2; ++f) {
+        const double *q = s + (size_t)f * nc;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int i = (z * ny + y) * nx + x;
+                    const int xm = (z * ny + y) * nx + (x + nx - 1) % nx, xp = (z * ny + y) * nx + (x + 1) % nx;
+                    const int ym = (z * ny + (y + ny - 1) % ny) * nx + x, yp = (z * ny + (y + 1) % ny) * nx + x;
+                    const int zm = (((z + nz - 1) % nz) * ny + y) * nx + x, zp = (((z + 1) % nz) * ny + y) * nx + x;
+                    const double lap = (q[xm] - 2.0 * q[i] + q[xp]) / (dx * dx) +
+                                       (q[ym] - 2.0 * q[i] + q[yp]) / (dy * dy) +
+                                       (q[zm] - 2.0 * q[i] + q[zp]) / (dz * dz);
+                    const double u = s[i], v = s[nc + i];
+                    const double u2v = u * u * v;
+                    if (f == 0) h[i] = Du * lap + A - (B + 1.0) * u + u2v;
+                    else h[nc + i] = Dv * lap + B * u - u2v;
+                }
+    }
+}
+
+/*
  * Shallow water (Sec. 5.3) with a flat bottom, conserved variables
  * q = (h, hu, hv), first-order finite volumes with the Rusanov (local
  * Lax-Friedrichs) numerical flux, reflective walls (ghost cell = mirror of
@@ -176,12 +216,13 @@ static void rhs_swe(const orc_problem *pb, const double *s, double *hdot)
 
 int32_t orc_rhs(const orc_problem *pb, const double *u, double *out)
 {
-    if (pb->nx < 1 || pb->ny < 1) return -1;
+    if (pb->nx < 1 || pb->ny < 1 || zcells(pb) < 1) return -1;
     switch (pb->kind) {
     case ORC_BURGERS1D: rhs_burgers(pb, u, out); return 0;
     case ORC_DIFFREACT2D: rhs_diffreact(pb, u, out); return 0;
     case ORC_BRUSS2D: rhs_bruss(pb, u, out); return 0;
     case ORC_SWE2D: rhs_swe(pb, u, out); return 0;
+    case ORC_BRUSS3D: rhs_bruss3d(pb, u, out); return 0;
     default: return -1;
     }
 }

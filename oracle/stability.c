@@ -12,7 +12,8 @@
  *   forward Euler: |1 + z| <= 1 for z = -a(1 - cos t) + i b sin t, a = rr / 2,
  *     b = ri, holds for all t iff dt <= 2 / rr and dt <= rr / (2 ri^2);
  *   classical RK4: the region reaches -2.785 on the real axis and 2.83 on the
- *     imaginary one; 2.78 / (rr + ri) is used.
+ *     imaginary one; 2.78 / (rr + ri) is used;
+ *   eighth-order RK (Cooper-Verner): -3.71 and 3.00; 2.9 / (rr + ri).
  */
 #include <math.h>
 #include "oracle.h"
@@ -22,9 +23,11 @@ static double dmax(double a, double b) { return a > b ? a : b; }
 double orc_stability(const orc_problem *pb, int32_t method, double dt, const double *u)
 {
     const int d = orc_dim(pb);
-    const int nc = pb->nx * pb->ny;
+    const int nc = pb->nx * pb->ny * (pb->kind == ORC_BRUSS3D ? pb->nz : 1);
     const double dx = (pb->x1 - pb->x0) / pb->nx;
     const double dy = pb->kind == ORC_BURGERS1D ? 1.0 : (pb->y1 - pb->y0) / pb->ny;
+    const double dz = pb->kind == ORC_BRUSS3D ? (pb->x1 - pb->x0) / pb->nz : 0.0;
+    const double lapz = pb->kind == ORC_BRUSS3D ? 4.0 / (dz * dz) : 0.0;  /* seven-point Laplacian in 3D */
     double umax = 0.0;
     for (int j = 0; j < d; ++j) umax = dmax(umax, fabs(u[j]));
     double rr = 0.0, ri = 0.0;
@@ -33,14 +36,15 @@ double orc_stability(const orc_problem *pb, int32_t method, double dt, const dou
          * part at most max|u| / dx */
         rr = 4.0 * pb->p[0] / (dx * dx);
         ri = umax / dx;
-    } else if (pb->kind == ORC_DIFFREACT2D || pb->kind == ORC_BRUSS2D) {
-        /* 5-point Laplacian: eigenvalues in [-(4/dx^2 + 4/dy^2), 0] times the
+    } else if (pb->kind == ORC_DIFFREACT2D || pb->kind == ORC_BRUSS2D || pb->kind == ORC_BRUSS3D) {
+        /* 5-point (7-point in 3D) Laplacian: eigenvalues in
+         * [-(4/dx^2 + 4/dy^2 (+ 4/dz^2)), 0] times the
          * larger diffusion coefficient; the reaction Jacobian's eigenvalues are
          * bounded by its row-sum norm:
          *   FitzHugh-Nagumo  [[1 - 3u^2, -1], [1, -1]]       -> 2 + 3 max u^2
          *   Brusselator [[-(B+1) + 2uv, u^2], [B - 2uv, -u^2]] -> B + 1 + 3 max u^2 */
         const double D = pb->kind == ORC_DIFFREACT2D ? dmax(pb->p[0], pb->p[1]) : dmax(pb->p[2], pb->p[3]);
-        rr = D * (4.0 / (dx * dx) + 4.0 / (dy * dy));
+        rr = D * (4.0 / (dx * dx) + 4.0 / (dy * dy) + lapz);
         rr += pb->kind == ORC_DIFFREACT2D ? 2.0 + 3.0 * umax * umax : pb->p[1] + 1.0 + 3.0 * umax * umax;
     } else if (pb->kind == ORC_SWE2D) {
         /* first-order Rusanov: per direction the linearised scheme has the
@@ -56,6 +60,9 @@ double orc_stability(const orc_problem *pb, int32_t method, double dt, const dou
     }
     if (dt < 0) dt = -dt;
     if (method == 4) return rr + ri > 0.0 ? dt * (rr + ri) / 2.78 : 0.0;
+    /* the Cooper-Verner RK8 region reaches -3.71 on the real axis and 3.00 i
+     * on the imaginary one (its stability function from the tableau) */
+    if (method == 8) return rr + ri > 0.0 ? dt * (rr + ri) / 2.9 : 0.0;
     double r = rr > 0.0 ? dt * rr / 2.0 : 0.0;
     if (ri > 0.0) {
         if (!(rr > 0.0)) return INFINITY;

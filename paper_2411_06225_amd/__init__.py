@@ -27,8 +27,8 @@ RPR_OK, RPR_NOT_CONVERGED = 0, 1
 RPR_ERR_INVALID_ARG, RPR_ERR_NO_DEVICE, RPR_ERR_HIP, RPR_ERR_OOM = -1, -2, -3, -4
 RPR_ERR_NONFINITE, RPR_ERR_NOT_SPD, RPR_ERR_UNSTABLE, RPR_ERR_UNSUPPORTED = -5, -6, -7, -8
 # enums
-RPR_BURGERS1D, RPR_DIFFREACT2D, RPR_BRUSS2D, RPR_SWE2D = 0, 1, 2, 3
-RPR_RK1, RPR_RK4 = 1, 4
+RPR_BURGERS1D, RPR_DIFFREACT2D, RPR_BRUSS2D, RPR_SWE2D, RPR_BRUSS3D = 0, 1, 2, 3, 4
+RPR_RK1, RPR_RK4, RPR_RK8 = 1, 4, 8
 RPR_TANH, RPR_RELU = 0, 1
 RPR_FP64, RPR_MIXED = 0, 1
 RPR_CORR_RANDNET, RPR_CORR_PARAREAL, RPR_CORR_RANDNET_NN = 0, 1, 2
@@ -47,7 +47,7 @@ class RprError(RuntimeError):
 
 
 class rpr_rhs(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("p", C.c_double * 6)]
 
@@ -193,14 +193,14 @@ def _stream(stream) -> int | None:
     return stream if isinstance(stream, int) else stream.cuda_stream
 
 
-def make_rhs(kind: int, nx: int, ny: int = 1, domain=(-1.0, 1.0, -1.0, 1.0), params=()) -> rpr_rhs:
+def make_rhs(kind: int, nx: int, ny: int = 1, domain=(-1.0, 1.0, -1.0, 1.0), params=(), nz: int = 0) -> rpr_rhs:
     p = (C.c_double * 6)(*([float(v) for v in params] + [0.0] * (6 - len(params))))
     x0, x1, y0, y1 = (float(v) for v in domain)
-    return rpr_rhs(int(kind), int(nx), int(ny), 0, x0, x1, y0, y1, p)
+    return rpr_rhs(int(kind), int(nx), int(ny), int(nz), x0, x1, y0, y1, p)
 
 
 def nspecies(kind: int) -> int:
-    return {RPR_BURGERS1D: 1, RPR_DIFFREACT2D: 2, RPR_BRUSS2D: 2, RPR_SWE2D: 3}[kind]
+    return {RPR_BURGERS1D: 1, RPR_DIFFREACT2D: 2, RPR_BRUSS2D: 2, RPR_SWE2D: 3, RPR_BRUSS3D: 2}[kind]
 
 
 # ---- building blocks ---------------------------------------------------------

@@ -21,14 +21,18 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE,
          # no packed FP32 instructions in any kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
-KINDS = {0: "burgers", 1: "diffreact", 2: "bruss", 3: "swe"}
+KINDS = {0: "burgers", 1: "diffreact", 2: "bruss", 3: "swe", 4: "bruss3d"}
+# the on-chip and tiled propagators serve the 1D and 2D systems; the generic
+# one (any tableau) and the chain serve every system
+UNIT_KINDS = {"propagate": (0, 1, 2, 3), "tiled": (0, 1, 2, 3), "chain": (0, 1, 2, 3, 4), "rkgen": (0, 1, 2, 3, 4)}
 REALS = ("double", "float")
 
 
 def _units():
     units = []
-    for src in ("propagate", "tiled", "chain"):
-        for k, kname in KINDS.items():
+    for src, kinds in UNIT_KINDS.items():
+        for k in kinds:
+            kname = KINDS[k]
             for real in REALS:
                 obj = os.path.join(BUILD, f"{src}_{kname}_{real}.o")
                 units.append((os.path.join(CSRC, src + ".hip"), obj, [f"-DRPR_KIND={k}", f"-DRPR_REAL={real}"]))

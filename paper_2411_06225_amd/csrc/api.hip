@@ -40,11 +40,17 @@ rpr_status make_geom(const rpr_rhs *h, int32_t d, Geom *g)
     if (!h) return fail(RPR_ERR_INVALID_ARG, "rhs is NULL");
     const int ns = nspecies(h->kind);
     if (ns == 0) return fail(RPR_ERR_INVALID_ARG, "rhs.kind is not a known right-hand side");
-    if (h->reserved != 0) return fail(RPR_ERR_INVALID_ARG, "rhs.reserved must be 0");
+    if (h->kind == RPR_BRUSS3D) {
+        if (h->nz < 1) return fail(RPR_ERR_INVALID_ARG, "rhs.nz must be >= 1 for the 3D system");
+    } else if (h->nz != 0 && h->nz != 1) {
+        return fail(RPR_ERR_INVALID_ARG, "rhs.nz must be 0 or 1 for the 1D and 2D systems");
+    }
     if (h->nx < 1 || h->ny < 1) return fail(RPR_ERR_INVALID_ARG, "rhs.nx and rhs.ny must be >= 1");
     if (h->kind == RPR_BURGERS1D && h->ny != 1) return fail(RPR_ERR_INVALID_ARG, "1D problem needs ny == 1");
-    if ((int64_t)ns * h->nx * h->ny != d)
-        return fail(RPR_ERR_INVALID_ARG, "d must equal species * nx * ny (" + std::to_string((int64_t)ns * h->nx * h->ny) + ")");
+    const int nz = h->kind == RPR_BRUSS3D ? h->nz : 1;
+    if ((int64_t)ns * h->nx * h->ny * nz != d)
+        return fail(RPR_ERR_INVALID_ARG, "d must equal species * nx * ny * nz (" +
+                                             std::to_string((int64_t)ns * h->nx * h->ny * nz) + ")");
     const double lx = h->x1 - h->x0, ly = h->y1 - h->y0;
     if (!(lx > 0) || !is_finite(lx)) return fail(RPR_ERR_INVALID_ARG, "rhs domain needs x1 > x0");
     if (h->kind != RPR_BURGERS1D && (!(ly > 0) || !is_finite(ly)))
@@ -55,13 +61,16 @@ rpr_status make_geom(const rpr_rhs *h, int32_t d, Geom *g)
     G.kind = h->kind;
     G.nx = h->nx;
     G.ny = h->ny;
-    G.nc = h->nx * h->ny;
+    G.nc = h->nx * h->ny * nz;
+    G.nz = nz;
     G.ns = ns;
     G.d = d;
-    G.periodic = (h->kind == RPR_BURGERS1D || h->kind == RPR_BRUSS2D) ? 1 : 0;
+    G.periodic = (h->kind == RPR_BURGERS1D || h->kind == RPR_BRUSS2D || h->kind == RPR_BRUSS3D) ? 1 : 0;
     const double dx = lx / h->nx, dy = h->kind == RPR_BURGERS1D ? 1.0 : ly / h->ny;
     G.idx2 = 1.0 / (dx * dx);
     G.idy2 = 1.0 / (dy * dy);
+    const double dz = lx / nz;  // the 3D box is a cube in x and z: (x0, x1) along z too
+    G.idz2 = h->kind == RPR_BRUSS3D ? 1.0 / (dz * dz) : 0.0;
     G.i2dx = 1.0 / (2.0 * dx);
     G.idx = 1.0 / dx;
     G.idy = 1.0 / dy;
@@ -86,10 +95,13 @@ rpr_status check_device()
 rpr_status check_prop(const rpr_propagator *P, const char *name)
 {
     if (!P) return fail(RPR_ERR_INVALID_ARG, std::string(name) + " is NULL");
-    if (P->method != RPR_RK1 && P->method != RPR_RK4)
-        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".method must be RPR_RK1 or RPR_RK4");
-    if (P->threads != 0 && P->threads != TILED_THREADS && P->threads != 512 && P->threads != 1024)
-        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".threads must be 0, 256, 512 or 1024");
+    if (P->method != RPR_RK1 && P->method != RPR_RK4 && P->method != RPR_RK8)
+        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".method must be RPR_RK1, RPR_RK4 or RPR_RK8");
+    if (P->threads != 0 && P->threads != GENERIC_THREADS && P->threads != TILED_THREADS && P->threads != 512 &&
+        P->threads != 1024)
+        return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".threads must be 0, 128, 256, 512 or 1024");
+    if (P->method == RPR_RK8 && P->threads != 0 && P->threads != GENERIC_THREADS)
+        return fail(RPR_ERR_UNSUPPORTED, std::string(name) + ": RPR_RK8 runs on the generic propagator (threads 0 or 128)");
     if (P->steps < 1) return fail(RPR_ERR_INVALID_ARG, std::string(name) + ".steps must be >= 1");
     return RPR_OK;
 }
@@ -204,12 +216,12 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
     RPR_TRY(dalloc(&c, sd * p->esz)); p->Fv = c;
     RPR_TRY(dalloc(&c, sd * p->esz)); p->Gc = c;
     RPR_TRY(dalloc(&c, (size_t)d * p->esz)); p->gtmp = c;
-    if (p->shF.maxt == TILED_THREADS) {
-        RPR_TRY(dalloc(&c, 5 * (size_t)N * d * p->esz));
+    if (const size_t fe = work_elems(p->shF, p->F.method, N, d)) {
+        RPR_TRY(dalloc(&c, fe * p->esz));
         p->fwork = c;
     }
-    if (p->shG.maxt == TILED_THREADS) {
-        RPR_TRY(dalloc(&c, 5 * (size_t)d * p->esz));
+    if (const size_t ge = work_elems(p->shG, p->G.method, 1, d)) {
+        RPR_TRY(dalloc(&c, ge * p->esz));
         p->gwork = c;
     }
     RPR_TRY(dalloc(&p->part, (size_t)(N + 1) * 4096));
@@ -373,6 +385,11 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     // else the tiled form
     for (const rpr_propagator *P : {F, G}) {
         OnchipShape &sh = P == F ? p->shF : p->shG;
+        if (P->threads == GENERIC_THREADS || P->method == RPR_RK8 || g.kind == RPR_BRUSS3D) {
+            // any tableau, states in memory, cell by cell
+            sh = generic_shape(g, p->esz);
+            continue;
+        }
         bool tiled = P->threads == TILED_THREADS;
         if (!tiled && !onchip_shape(g, p->esz, &sh, P->threads ? P->threads : 1024)) {
             if (P->threads) {
@@ -425,7 +442,8 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const double work = (double)g.d * (use_net ? p->M : 1);
-    int nwg = (work < 65536.0 && p->shG.maxt != TILED_THREADS) ? 1 : cus;  // the tiled coarse solver needs the grid
+    // the tiled and generic coarse solvers need the grid
+    int nwg = (work < 65536.0 && p->shG.maxt != TILED_THREADS && p->shG.maxt != GENERIC_THREADS) ? 1 : cus;
     if (opt->chain_wgs > 0) nwg = opt->chain_wgs;
     if (nwg > max_wg) nwg = max_wg;
     if (nwg > 4096) nwg = 4096;
@@ -504,7 +522,7 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
     // the graph holds no grid-wide barrier
     // (ev: the first of the iteration's three phase events, or -1)
     auto iteration = [&](hipStream_t s, bool graph, int ev) -> rpr_status {
-        const TiledWork<T> fw = tiled_work<T>(p->fwork, (size_t)N * d);
+        const TiledWork<T> fw = fine_work<T>(p);
         RPR_TRY(launch_propagate<T>(g, p->F.method, p->F.steps, p->dtF, N, U, Fv + d, ctrl_i, s, p->shF.maxt,
                                     p->fwork ? &fw : nullptr, p->fvar));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev], s));

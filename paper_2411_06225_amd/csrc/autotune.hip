@@ -115,10 +115,11 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
     // per launch of min(steps, 32) steps) is kept in the table under
     // "<class>:t:<threads>:<shape>"
     const bool forced_tiled = p->shF.maxt == TILED_THREADS;
+    const bool generic_F = p->shF.maxt == GENERIC_THREADS;  // one form, nothing to choose
     const std::string kv = kf + ":v";
-    const bool haveV = g_tune.count(kv) != 0;
+    const bool haveV = g_tune.count(kv) != 0 || generic_F;
     const int nvar = fused_variants(g.kind, p->esz);
-    if ((!haveF && p->F.threads == 0 && !forced_tiled) || (forced_tiled && !haveV)) {
+    if (!generic_F && ((!haveF && p->F.threads == 0 && !forced_tiled) || (forced_tiled && !haveV))) {
         const int64_t steps = p->F.steps < 32 ? p->F.steps : 32;
         float best = 1e30f;
         int best_mt = p->shF.maxt, best_v = 0;
@@ -158,8 +159,8 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         if (!forced_tiled) g_tune[kf] = best_mt;
         g_tune[kv] = best_v;
     }
-    p->fvar = g_tune.count(kv) ? g_tune[kv] : 0;
-    if (!forced_tiled) {
+    p->fvar = (!generic_F && g_tune.count(kv)) ? g_tune[kv] : 0;
+    if (!forced_tiled && !generic_F) {
         const int mt = p->F.threads ? p->F.threads : g_tune[kf];
         if (mt == TILED_THREADS) {
             p->shF = tiled_shape(g, p->esz);
@@ -193,7 +194,8 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         a.gtmp = static_cast<T *>(p->gtmp);
         a.phi = p->phi;
         a.hpart = p->hpart;
-        a.gw = tiled_work<T>(p->gwork, (size_t)d);
+        a.gw = coarse_work<T>(p);
+        a.tbG = rk_tableau(p->G.method);
         a.A = p->A;
         a.zeta = p->zeta;
         a.W = chain_W<T>(p);

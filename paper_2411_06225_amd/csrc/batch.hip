@@ -49,7 +49,8 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
         if (q->prec != p->prec || q->corr != p->corr)
             return bail(fail(RPR_ERR_INVALID_ARG, "all instances of a batch need the same precision and correction"));
     for (rpr_plan *q : p->sub)
-        if (q->shF.maxt == TILED_THREADS || q->shG.maxt == TILED_THREADS)
+        if (q->shF.maxt == TILED_THREADS || q->shG.maxt == TILED_THREADS || q->shF.maxt == GENERIC_THREADS ||
+            q->shG.maxt == GENERIC_THREADS)
             return bail(fail(RPR_ERR_UNSUPPORTED, "batch instances must fit one work-group each"));
     // the kernel shape of the largest instance serves every instance
     int big = 0;

@@ -55,12 +55,30 @@ extern "C" rpr_status rpr_propagate(const rpr_rhs *h, int32_t d, const rpr_propa
     if (a < b + bytes && b < a + bytes) return fail(RPR_ERR_INVALID_ARG, "in and out must not overlap");
     const int esz = precision == RPR_FP64 ? 8 : 4;
     if (P->threads) RPR_TRY(check_threads(g, esz, P->threads));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (P->threads == GENERIC_THREADS || P->method == RPR_RK8 || g.kind == RPR_BRUSS3D) {
+        // generic form: the work arrays of rkgen_work, released on the stream
+        RPR_TRY(check_device());
+        void *ws = nullptr;
+        RPR_HIP(hipMallocAsync(&ws, rkgen_work_elems(P->method, n_states, d) * esz, st));
+        rpr_status rc;
+        if (precision == RPR_FP64) {
+            const TiledWork<double> w = rkgen_work<double>(ws, n_states, d);
+            rc = launch_propagate<double>(g, P->method, P->steps, dt, n_states, static_cast<const double *>(in),
+                                          static_cast<double *>(out), nullptr, st, GENERIC_THREADS, &w);
+        } else {
+            const TiledWork<float> w = rkgen_work<float>(ws, n_states, d);
+            rc = launch_propagate<float>(g, P->method, P->steps, dt, n_states, static_cast<const float *>(in),
+                                         static_cast<float *>(out), nullptr, st, GENERIC_THREADS, &w);
+        }
+        RPR_HIP(hipFreeAsync(ws, st));
+        return rc;
+    }
     // automatic: on chip when the state fits one work-group, else tiled
     OnchipShape probe;
     const bool fits = onchip_shape(g, esz, &probe, 1024);
     if (!P->threads && !fits) RPR_TRY(check_threads(g, esz, TILED_THREADS));
     RPR_TRY(check_device());
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const int mt = P->threads ? P->threads : (fits ? tuned_prop_threads(g, esz, P->method) : TILED_THREADS);
     if (mt != TILED_THREADS) {
         if (precision == RPR_FP64)

@@ -4,6 +4,7 @@
 
 #include "common.h"
 #include "randnet.h"
+#include "rkgen.h"
 
 namespace rpr {
 
@@ -29,7 +30,8 @@ struct ChainArgs {
     T *gtmp;                   // d: coarse value of the current slot
     double *phi;               // M: hidden layer of the current slot
     double *hpart;             // grid x M: per-work-group partial sums of A x / s
-    TiledWork<T> gw;           // work arrays of the tiled coarse solver (d values each)
+    TiledWork<T> gw;           // work arrays of the tiled or generic coarse solver (d values each)
+    Tableau tbG;               // the coarse solver's tableau (generic form)
     const double *A, *zeta;
     const T *W;                // M x d readout weights (state precision: FP32 copies in reduced plans)
     const T *At;               // d x M: A^T (state precision)

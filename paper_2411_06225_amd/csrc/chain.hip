@@ -386,11 +386,36 @@ __device__ __forceinline__ void chain_columns(const int d, const int wg, const i
     j1 = min(d, j0 + chunk);
 }
 
-// Passes of the tiled coarse solver per slot: forward Euler takes up to EH
-// steps per pass (euler_tile_multi), RK4 one pass per stage.
-__host__ __device__ inline long long coarse_passes(int method, long long steps)
+// Coarse solver of the sweep: on one work-group (CM_ONCHIP), in tiles over
+// the grid (CM_TILED), or cell by cell over the grid by its tableau
+// (CM_GENERIC: the 3D system, the eighth-order method).
+enum { CM_ONCHIP = 0, CM_TILED = 1, CM_GENERIC = 2 };
+
+// Passes of the grid-wide coarse solvers per slot: tiled forward Euler takes
+// up to EH steps per pass (euler_tile_multi), tiled RK4 one pass per stage,
+// the generic form one pass per stage of its tableau (s stages).
+__host__ __device__ inline long long coarse_passes(int cm, int method, long long steps, int s)
 {
+    if (cm == CM_GENERIC) return steps * s;
     return method == RPR_RK1 ? (steps + EH - 1) / EH : 4 * steps;
+}
+
+// Pass `pass` of the generic coarse propagation src -> dst (and dst2): stage
+// pass % s of step pass / s over every cell, the cells spread over all the
+// threads of the grid (work arrays in a.gw as rkgen_work lays them out for
+// one state).
+template <int KIND, typename T>
+__device__ __forceinline__ void generic_coarse_pass(const ChainArgs<T> &a, const T *src, T *dst, T *dst2,
+                                                    const long long pass, const int wg, const int nwg)
+{
+    const int s = a.tbG.s;
+    const long long step = pass / s;
+    const int stage = (int)(pass % s);
+    const RkIO<T> io = rkgen_io<T>(s, stage, step, a.G_steps, src, dst, dst2, a.gw);
+    const int B = blockDim.x;
+    for (int c = wg * B + (int)threadIdx.x; c < a.g.nc; c += nwg * B)
+        rkgen_cell<KIND, T>(a.g, a.tbG, stage, a.dtG, c, io.y, a.gw.acc, (size_t)a.g.d, io.u, io.ynext, io.uout,
+                            io.uout2, a.gw.cmp, step == 0 ? 1 : 0);
 }
 
 // Pass `pass` of the tiled coarse propagation src -> dst (and dst2) by the
@@ -423,14 +448,27 @@ __device__ __forceinline__ void tiled_coarse_pass(const ChainArgs<T> &a, const T
     for (int tile = wg; tile < nt; tile += nwg) stage_tile_any<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
 }
 
-// The whole tiled coarse propagation, passes separated by sync().
-template <int KIND, typename T, typename Sync>
-__device__ __forceinline__ void tiled_coarse(const ChainArgs<T> &a, const T *src, T *dst, T *dst2, const int wg,
-                                             const int nwg, Sync sync, T *lds)
+// One pass of a grid-wide coarse solver.
+template <int KIND, typename T, int CM>
+__device__ __forceinline__ void coarse_pass(const ChainArgs<T> &a, const T *src, T *dst, T *dst2,
+                                            const long long pass, const int wg, const int nwg, T *lds)
 {
-    const long long np = coarse_passes(a.G_method, a.G_steps);
-    for (long long pass = 0; pass < np; ++pass) {
+    if constexpr (CM == CM_GENERIC) {
+        (void)lds;
+        generic_coarse_pass<KIND, T>(a, src, dst, dst2, pass, wg, nwg);
+    } else if constexpr (KIND != RPR_BURGERS1D && KIND != RPR_BRUSS3D) {
         tiled_coarse_pass<KIND, T>(a, src, dst, dst2, pass, wg, nwg, lds);
+    }
+}
+
+// The whole grid-wide coarse propagation, passes separated by sync().
+template <int KIND, typename T, int CM, typename Sync>
+__device__ __forceinline__ void grid_coarse(const ChainArgs<T> &a, const T *src, T *dst, T *dst2, const int wg,
+                                            const int nwg, Sync sync, T *lds)
+{
+    const long long np = coarse_passes(CM, a.G_method, a.G_steps, a.tbG.s);
+    for (long long pass = 0; pass < np; ++pass) {
+        coarse_pass<KIND, T, CM>(a, src, dst, dst2, pass, wg, nwg, lds);
         sync();
     }
 }
@@ -666,8 +704,7 @@ __device__ __forceinline__ void chain_seg_epi(const ChainArgs<T> &a, const int w
 
 // One sweep of one instance in one launch: the segments separated by sync()
 // (a grid barrier, or a work-group barrier when nwg == 1).
-template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, bool TILED, bool NN_OK,
-          typename Sync>
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int CM, bool NN_OK, typename Sync>
 __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, const int nwg, Sync sync,
                                            unsigned char *lds_raw)
 {
@@ -676,11 +713,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     const int d = a.g.d;
 
     if (a.mode == CHAIN_SWEEP) {
-        if constexpr (TILED) {
+        if constexpr (CM != CM_ONCHIP) {
             // k = 0 by the whole grid
             for (int i = 1; i <= a.N; ++i)
-                tiled_coarse<KIND, T>(a, a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d, a.Gc + (size_t)i * d, wg,
-                                      nwg, sync, lds);
+                grid_coarse<KIND, T, CM>(a, a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d, a.Gc + (size_t)i * d, wg,
+                                         nwg, sync, lds);
         } else {
             // k = 0 (single work-group): the state stays on chip from slot to slot
             if (wg != 0) return;
@@ -699,8 +736,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
     chain_seg_pro<T, NN_OK>(a, wg, nwg, scratch);
     sync();
     for (int i = L + 2; i <= a.N; ++i) {
-        if constexpr (TILED) {
-            tiled_coarse<KIND, T>(a, a.U + (size_t)(i - 1) * d, a.gtmp, (T *)nullptr, wg, nwg, sync, lds);
+        if constexpr (CM != CM_ONCHIP) {
+            grid_coarse<KIND, T, CM>(a, a.U + (size_t)(i - 1) * d, a.gtmp, (T *)nullptr, wg, nwg, sync, lds);
             chain_seg_hidden_all<T, NN_OK>(a, wg, nwg);
         } else {
             chain_seg_p1_onchip<KIND, T, CPT, DBUF, FULL, NX, NY, NN_OK>(a, i, wg, nwg, lds);
@@ -716,7 +753,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
 // prologue; 1 phase 1 of slot i (tiled coarse solver: pass `pass` of it, the
 // hidden layer with pass 0); 2 phase 2 of slot i; 3 the stopping rule.
 // Work-groups return at once when the run is done or slot i is final.
-template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT, bool TILED, bool NN_OK>
+template <int KIND, typename T, int CPT, bool DBUF, bool FULL, int NX, int NY, int MAXT, int CM, bool NN_OK>
 __global__ __launch_bounds__(MAXT) void k_chain_seg(const ChainArgs<T> *__restrict__ args, int seg, int i,
                                                     long long pass)
 {
@@ -734,9 +771,9 @@ __global__ __launch_bounds__(MAXT) void k_chain_seg(const ChainArgs<T> *__restri
         if (i < L + 2) return;
         if (seg == 2) {
             chain_seg_p2<T, NN_OK>(a, i, wg, nwg, scratch);
-        } else if constexpr (TILED) {
-            tiled_coarse_pass<KIND, T>(a, a.U + (size_t)(i - 1) * a.g.d, a.gtmp, (T *)nullptr, pass, wg, nwg,
-                                       reinterpret_cast<T *>(lds_raw));
+        } else if constexpr (CM != CM_ONCHIP) {
+            coarse_pass<KIND, T, CM>(a, a.U + (size_t)(i - 1) * a.g.d, a.gtmp, (T *)nullptr, pass, wg, nwg,
+                                     reinterpret_cast<T *>(lds_raw));
             if (pass == 0) chain_seg_hidden_all<T, NN_OK>(a, wg, nwg);
         } else {
             chain_seg_p1_onchip<KIND, T, CPT, DBUF, FULL, NX, NY, NN_OK>(a, i, wg, nwg, reinterpret_cast<T *>(lds_raw));
@@ -749,8 +786,8 @@ __global__ __launch_bounds__(MAXT) void k_chain(ChainArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cg::grid_group grid = cg::this_grid();
-    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false, NN_OK>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); },
-                                                              lds_raw);
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, CM_ONCHIP, NN_OK>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); },
+                                                                  lds_raw);
 }
 
 // Independent instances: work-group b runs the whole sweep of instance b.
@@ -759,7 +796,7 @@ __global__ __launch_bounds__(MAXT) void k_chain_multi(const ChainArgs<T> *__rest
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ChainArgs<T> a = args[blockIdx.x];
-    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, false, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+    chain_body<KIND, T, CPT, DBUF, FULL, NX, NY, CM_ONCHIP, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
 }
 
 // ---------------------------------------------------------- tiled form --
@@ -768,7 +805,8 @@ __global__ __launch_bounds__(TT_THREADS) void k_chain_tiled(ChainArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cg::grid_group grid = cg::this_grid();
-    chain_body<KIND, T, 1, false, false, 0, 0, true, true>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); }, lds_raw);
+    chain_body<KIND, T, 1, false, false, 0, 0, CM_TILED, true>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); },
+                                                               lds_raw);
 }
 
 template <int KIND, typename T>
@@ -776,7 +814,19 @@ __global__ __launch_bounds__(TT_THREADS) void k_chain_multi_tiled(const ChainArg
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ChainArgs<T> a = args[blockIdx.x];
-    chain_body<KIND, T, 1, false, false, 0, 0, true, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+    chain_body<KIND, T, 1, false, false, 0, 0, CM_TILED, true>(a, 0, 1, []() { __syncthreads(); }, lds_raw);
+}
+
+// ---------------------------------------------------------- generic form --
+constexpr int GENERIC_BLOCK = 256;  // work-group of the generic chain
+
+template <int KIND, typename T>
+__global__ __launch_bounds__(GENERIC_BLOCK) void k_chain_generic(ChainArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cg::grid_group grid = cg::this_grid();
+    chain_body<KIND, T, 1, false, false, 0, 0, CM_GENERIC, true>(a, blockIdx.x, gridDim.x, [&]() { grid.sync(); },
+                                                                 lds_raw);
 }
 
 template <int KIND, typename T>
@@ -807,6 +857,10 @@ template <int KIND, typename T>
 rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, const Geom &gmax,
                                    const OnchipShape &sh, int M, hipStream_t st)
 {
+    if (sh.maxt == GENERIC_THREADS) return fail(RPR_ERR_UNSUPPORTED, "batch instances must fit one work-group each");
+    if constexpr (KIND == RPR_BRUSS3D) {
+        return fail(RPR_ERR_UNSUPPORTED, "batch instances must fit one work-group each");
+    } else {
     if (sh.maxt == TILED_THREADS) {
         if constexpr (KIND == RPR_BURGERS1D) {
             return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
@@ -825,6 +879,7 @@ rpr_status launch_chain_multi_kind(const ChainArgs<T> *args_dev, int n_inst, con
     }
     ChainMultiLauncher<KIND, T> L{args_dev, n_inst, sh, M, st};
     return visit_shape_kind<KIND, T>(gmax, sh, L);
+    }
 }
 
 template rpr_status launch_chain_multi_kind<RPR_KIND, RPR_REAL>(const ChainArgs<RPR_REAL> *, int, const Geom &,
@@ -874,6 +929,30 @@ template <int KIND, typename T>
 rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st,
                              int *max_wg)
 {
+    if (sh.maxt == GENERIC_THREADS) {
+        auto kern = k_chain_generic<KIND, T>;
+        static bool attr_set = false;
+        if (!attr_set) {
+            RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxLds));
+            attr_set = true;
+        }
+        const size_t lds = chain_lds(sh, a.M);
+        if (max_wg) {
+            int per_cu = 0, dev = 0, cus = 0;
+            RPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, GENERIC_BLOCK, lds));
+            RPR_HIP(hipGetDevice(&dev));
+            RPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            *max_wg = per_cu * cus;
+            return RPR_OK;
+        }
+        void *args[] = {(void *)&a};
+        RPR_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(nwg), dim3(GENERIC_BLOCK), args, lds, st));
+        return RPR_OK;
+    }
+    if constexpr (KIND == RPR_BRUSS3D) {
+        return fail(RPR_ERR_UNSUPPORTED, "the 3D system takes the generic chain only");
+    } else {
     if (sh.maxt == TILED_THREADS) {
         if constexpr (KIND == RPR_BURGERS1D) {
             return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
@@ -901,6 +980,7 @@ rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int n
     }
     ChainLauncher<KIND, T> L{a, sh, nwg, st, max_wg};
     return visit_shape_kind<KIND, T>(a.g, sh, L);
+    }
 }
 
 // A sweep as a sequence of segment kernels (for capture in a graph): the
@@ -939,8 +1019,8 @@ struct ChainSegLauncher {
     {
         const size_t lds = chain_lds(sh, a.M);
         if (a.mode == CHAIN_RANDNET_NN)
-            return sequence(k_chain_seg<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, false, true>, sh.block, lds, 1);
-        return sequence(k_chain_seg<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, false, false>, sh.block, lds, 1);
+            return sequence(k_chain_seg<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, CM_ONCHIP, true>, sh.block, lds, 1);
+        return sequence(k_chain_seg<KIND, T, CPT, DBUF, FULL, NX, NY, MAXT, CM_ONCHIP, false>, sh.block, lds, 1);
     }
 };
 
@@ -949,15 +1029,23 @@ rpr_status launch_chain_graph_kind(const ChainArgs<T> *args_dev, const ChainArgs
                                    int nwg, hipStream_t st)
 {
     ChainSegLauncher<KIND, T> L{args_dev, a, sh, nwg, st};
-    if (sh.maxt == TILED_THREADS) {
-        if constexpr (KIND == RPR_BURGERS1D) {
-            return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
-        } else {
-            return L.sequence(k_chain_seg<KIND, T, 1, false, false, 0, 0, TT_THREADS, true, true>, TT_THREADS,
-                              chain_lds(sh, a.M), coarse_passes(a.G_method, a.G_steps));
+    if (sh.maxt == GENERIC_THREADS)
+        return L.sequence(k_chain_seg<KIND, T, 1, false, false, 0, 0, GENERIC_BLOCK, CM_GENERIC, true>,
+                          GENERIC_BLOCK, chain_lds(sh, a.M), coarse_passes(CM_GENERIC, a.G_method, a.G_steps, a.tbG.s));
+    if constexpr (KIND == RPR_BRUSS3D) {
+        return fail(RPR_ERR_UNSUPPORTED, "the 3D system takes the generic chain only");
+    } else {
+        if (sh.maxt == TILED_THREADS) {
+            if constexpr (KIND == RPR_BURGERS1D) {
+                return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
+            } else {
+                return L.sequence(k_chain_seg<KIND, T, 1, false, false, 0, 0, TT_THREADS, CM_TILED, true>,
+                                  TT_THREADS, chain_lds(sh, a.M),
+                                  coarse_passes(CM_TILED, a.G_method, a.G_steps, a.tbG.s));
+            }
         }
+        return visit_shape_kind<KIND, T>(a.g, sh, L);
     }
-    return visit_shape_kind<KIND, T>(a.g, sh, L);
 }
 
 template rpr_status launch_chain_graph_kind<RPR_KIND, RPR_REAL>(const ChainArgs<RPR_REAL> *, const ChainArgs<RPR_REAL> &,

@@ -29,7 +29,7 @@ rpr_status hip_fail(hipError_t e, const char *what);
 struct Geom {
     int kind;      // rpr_rhs_kind
     int nx, ny;    // grid
-    int nc;        // cells = nx * ny
+    int nc;        // cells = nx * ny * nz
     int ns;        // species
     int d;         // ns * nc
     int periodic;  // 1: wrap, 0: wall (Neumann mirror / reflective)
@@ -37,6 +37,8 @@ struct Geom {
     double i2dx;         // 1 / (2 dx)            (Burgers advection)
     double idx, idy;     // 1 / dx, 1 / dy         (finite-volume flux differences)
     double p[6];
+    int nz;              // cells along z (3D Brusselator; 1 otherwise)
+    double idz2;         // 1 / dz^2 (3D)
 };
 
 inline int nspecies(int kind)
@@ -46,6 +48,7 @@ inline int nspecies(int kind)
     case RPR_DIFFREACT2D: return 2;
     case RPR_BRUSS2D: return 2;
     case RPR_SWE2D: return 3;
+    case RPR_BRUSS3D: return 2;
     default: return 0;
     }
 }
@@ -145,6 +148,21 @@ template <int KIND>
 constexpr int kind_ns()
 {
     return KIND == RPR_BURGERS1D ? 1 : (KIND == RPR_SWE2D ? 3 : 2);
+}
+
+// Brusselator in three dimensions (App. E): the reaction of rhs_bruss with
+// the seven-point Laplacian; xs, ys, zs: sums of the two neighbours along
+// each axis, D*x = D / dx^2 etc.
+template <typename T>
+__device__ __forceinline__ void rhs_bruss3d(const T *c, const T *xs, const T *ys, const T *zs, T *k, T A, T B, T Dux,
+                                            T Duy, T Duz, T Dvx, T Dvy, T Dvz)
+{
+    const T u = c[0], v = c[1];
+    const T u2v = u * u * v;
+    const T lu = Dux * (xs[0] - T(2) * u) + Duy * (ys[0] - T(2) * u) + Duz * (zs[0] - T(2) * u);
+    const T lv = Dvx * (xs[1] - T(2) * v) + Dvy * (ys[1] - T(2) * v) + Dvz * (zs[1] - T(2) * v);
+    k[0] = lu + ((A - (B + T(1)) * u) + u2v);
+    k[1] = lv + (B * u - u2v);
 }
 
 // Right-hand side of the Laplacian-coupled systems (diffusion-reaction,
@@ -249,11 +267,22 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
 int fused_variants(int kind, size_t elem);
 const char *fused_variant_name(int kind, size_t elem, int v);
 
+// The generic propagator (rkgen.hip): any explicit tableau (method 1, 4 or
+// 8), one launch per stage over the cells of all n states; work arrays as
+// rkgen_work lays them out (rkgen.h).
+template <int KIND, typename T>
+rpr_status launch_rkgen_kind(const Geom &g, int method, int64_t steps, double dt, int n, const T *in, T *out,
+                             const TiledWork<T> &w, const int *ctrl, hipStream_t st);
+
+// Launch shape of the generic propagator (block 256, maxt GENERIC_THREADS).
+OnchipShape generic_shape(const Geom &g, size_t elem);
+
 // Launch of the propagator: out[b] = P(in[b]) for b in [0, n), where the
 // work of state b is skipped when ctrl != nullptr and b < ctrl[0] (slot b + 1
 // is already final) or ctrl[2] != 0 (run finished).  max_threads 512 / 1024
 // selects the on-chip kernel with that work-group size, TILED_THREADS the
-// tiled one, which needs the work arrays tw.
+// tiled one, which needs the work arrays tw, GENERIC_THREADS (rkgen.h) the
+// generic one (work arrays tw laid out by rkgen_work).
 template <typename T>
 rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt, int n, const T *in,
                             T *out, const int *ctrl, hipStream_t st, int max_threads = 1024,

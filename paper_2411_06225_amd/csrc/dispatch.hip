@@ -1,6 +1,7 @@
 // dispatch.hip -- host-side shape selection and the dispatch from a runtime
 // right-hand-side kind to the per-kind kernel objects.
 #include "chain.h"
+#include "rkgen.h"
 #include "slotprop.h"
 #include "tiledprop.h"
 
@@ -17,6 +18,7 @@ bool onchip_shape(const Geom &g, size_t elem, OnchipShape *sh, int max_threads)
 {
     int cpt, block;
     if (max_threads != 512) max_threads = 1024;
+    if (g.kind == RPR_BRUSS3D) return false;  // the generic propagator serves the 3D system
     if (g.kind == RPR_BURGERS1D) {
         cpt = pow2_at_least((g.nc + max_threads - 1) / max_threads);
         if (cpt < 2 && g.nc >= 128) cpt = 2;
@@ -58,6 +60,17 @@ rpr_status has_instance_t(const Geom &g, const OnchipShape &sh)
 }
 }  // namespace
 
+OnchipShape generic_shape(const Geom &g, size_t elem)
+{
+    (void)g;
+    (void)elem;
+    OnchipShape sh{};
+    sh.block = 256;
+    sh.maxt = GENERIC_THREADS;
+    sh.lds = 0;
+    return sh;
+}
+
 OnchipShape tiled_shape(const Geom &g, size_t elem)
 {
     OnchipShape sh{};
@@ -70,6 +83,9 @@ OnchipShape tiled_shape(const Geom &g, size_t elem)
 
 rpr_status check_threads(const Geom &g, size_t elem, int threads)
 {
+    if (threads == GENERIC_THREADS) return RPR_OK;
+    if (g.kind == RPR_BRUSS3D)
+        return fail(RPR_ERR_UNSUPPORTED, "the 3D system runs on the generic propagator only (threads 0 or 128)");
     if (threads == TILED_THREADS)
         return g.kind == RPR_BURGERS1D ? fail(RPR_ERR_UNSUPPORTED, "the tiled propagator serves 2D grids only")
                                        : RPR_OK;
@@ -87,6 +103,18 @@ rpr_status launch_propagate(const Geom &g, int method, int64_t steps, double dt,
                             const int *ctrl, hipStream_t st, int max_threads, const TiledWork<T> *tw, int variant)
 {
     if (n <= 0) return RPR_OK;
+    if (max_threads == GENERIC_THREADS) {
+        if (!tw) return fail(RPR_ERR_INVALID_ARG, "propagate: the generic form needs work arrays");
+        switch (g.kind) {
+        case RPR_BURGERS1D: return launch_rkgen_kind<RPR_BURGERS1D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_DIFFREACT2D: return launch_rkgen_kind<RPR_DIFFREACT2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_BRUSS2D: return launch_rkgen_kind<RPR_BRUSS2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_SWE2D: return launch_rkgen_kind<RPR_SWE2D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        case RPR_BRUSS3D: return launch_rkgen_kind<RPR_BRUSS3D, T>(g, method, steps, dt, n, in, out, *tw, ctrl, st);
+        default: return fail(RPR_ERR_INVALID_ARG, "propagate: unknown right-hand side");
+        }
+    }
+    if (g.kind == RPR_BRUSS3D) return fail(RPR_ERR_UNSUPPORTED, "the 3D system runs on the generic propagator only");
     if (max_threads == TILED_THREADS) {
         if (!tw) return fail(RPR_ERR_INVALID_ARG, "propagate: the tiled form needs work arrays");
         switch (g.kind) {
@@ -154,6 +182,7 @@ rpr_status launch_chain(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, h
     case RPR_DIFFREACT2D: return launch_chain_kind<RPR_DIFFREACT2D, T>(a, sh, nwg, st, max_wg);
     case RPR_BRUSS2D: return launch_chain_kind<RPR_BRUSS2D, T>(a, sh, nwg, st, max_wg);
     case RPR_SWE2D: return launch_chain_kind<RPR_SWE2D, T>(a, sh, nwg, st, max_wg);
+    case RPR_BRUSS3D: return launch_chain_kind<RPR_BRUSS3D, T>(a, sh, nwg, st, max_wg);
     default: return fail(RPR_ERR_INVALID_ARG, "chain: unknown right-hand side");
     }
 }
@@ -169,6 +198,7 @@ rpr_status launch_chain_graph(const ChainArgs<T> *args_dev, const ChainArgs<T> &
     case RPR_DIFFREACT2D: return launch_chain_graph_kind<RPR_DIFFREACT2D, T>(args_dev, a, sh, nwg, st);
     case RPR_BRUSS2D: return launch_chain_graph_kind<RPR_BRUSS2D, T>(args_dev, a, sh, nwg, st);
     case RPR_SWE2D: return launch_chain_graph_kind<RPR_SWE2D, T>(args_dev, a, sh, nwg, st);
+    case RPR_BRUSS3D: return launch_chain_graph_kind<RPR_BRUSS3D, T>(args_dev, a, sh, nwg, st);
     default: return fail(RPR_ERR_INVALID_ARG, "chain: unknown right-hand side");
     }
 }
@@ -203,6 +233,7 @@ rpr_status launch_chain_multi(const ChainArgs<T> *args_dev, int n_inst, const Ge
     case RPR_DIFFREACT2D: return launch_chain_multi_kind<RPR_DIFFREACT2D, T>(args_dev, n_inst, gmax, sh, M, st);
     case RPR_BRUSS2D: return launch_chain_multi_kind<RPR_BRUSS2D, T>(args_dev, n_inst, gmax, sh, M, st);
     case RPR_SWE2D: return launch_chain_multi_kind<RPR_SWE2D, T>(args_dev, n_inst, gmax, sh, M, st);
+    case RPR_BRUSS3D: return launch_chain_multi_kind<RPR_BRUSS3D, T>(args_dev, n_inst, gmax, sh, M, st);
     default: return fail(RPR_ERR_INVALID_ARG, "batch: unknown right-hand side");
     }
 }

@@ -149,6 +149,15 @@ inline TiledWork<T> tiled_work(void *base, size_t n)
     return TiledWork<T>{b, b + n, b + 2 * n, b + 3 * n, sizeof(T) == 4 ? b + 4 * n : nullptr};
 }
 
+// Elements of the work arrays of a propagator of shape sh and method over n
+// states of d values (tiled: u, acc, ya, yb, cmp; generic: rkgen_work), or 0.
+inline size_t work_elems(const OnchipShape &sh, int method, size_t n, size_t d)
+{
+    if (sh.maxt == GENERIC_THREADS) return rkgen_work_elems(method, n, d);
+    if (sh.maxt == TILED_THREADS) return 5 * n * d;
+    return 0;
+}
+
 // Releases every buffer of the plan (and of a batch's instances).
 void plan_free(rpr_plan *p);
 
@@ -160,6 +169,23 @@ inline rpr_status dalloc(B **ptr, size_t count)
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
     *ptr = static_cast<B *>(q);
     return RPR_OK;
+}
+
+// Work arrays of the plan's fine (N states) and coarse (one state)
+// propagators in their forms (empty for the on-chip form).
+template <typename T>
+inline TiledWork<T> fine_work(const rpr_plan *p)
+{
+    const size_t N = p->N, d = p->g.d;
+    if (!p->fwork) return TiledWork<T>{};
+    return p->shF.maxt == GENERIC_THREADS ? rkgen_work<T>(p->fwork, N, d) : tiled_work<T>(p->fwork, N * d);
+}
+template <typename T>
+inline TiledWork<T> coarse_work(const rpr_plan *p)
+{
+    const size_t d = p->g.d;
+    if (!p->gwork) return TiledWork<T>{};
+    return p->shG.maxt == GENERIC_THREADS ? rkgen_work<T>(p->gwork, 1, d) : tiled_work<T>(p->gwork, d);
 }
 
 // The chain's weights in state precision: FP64 plans read W and A^T
@@ -231,7 +257,8 @@ inline ChainArgs<T> chain_args(rpr_plan *p, double s)
     a.gtmp = static_cast<T *>(p->gtmp);
     a.phi = p->phi;
     a.hpart = p->hpart;
-    a.gw = tiled_work<T>(p->gwork, (size_t)p->g.d);
+    a.gw = coarse_work<T>(p);
+    a.tbG = rk_tableau(p->G.method);
     a.A = p->A;
     a.zeta = p->zeta;
     a.W = chain_W<T>(p);
@@ -287,9 +314,11 @@ inline rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStr
     }
     ChainArgs<T> a = chain_args<T>(p, s);
     a.mode = CHAIN_SWEEP;
-    // on chip the sweep's state stays in one work-group; the tiled coarse
-    // solver spreads each slot's tiles over the plan's grid
-    RPR_TRY(launch_chain<T>(a, p->shG, p->shG.maxt == TILED_THREADS ? p->nwg : 1, st));
+    // on chip the sweep's state stays in one work-group; the tiled and
+    // generic coarse solvers spread each slot's tiles or cells over the plan's
+    // grid
+    RPR_TRY(launch_chain<T>(a, p->shG, p->shG.maxt == TILED_THREADS || p->shG.maxt == GENERIC_THREADS ? p->nwg : 1,
+                            st));
     a.mode = chain_mode(p);
     *out = a;
     return RPR_OK;

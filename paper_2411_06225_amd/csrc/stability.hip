@@ -11,12 +11,15 @@
 //                   rho_r / (2 rho_i^2) (the classical forward-time
 //                   centred-space condition dt <= 2 nu / u^2);
 //   classical RK4 : dt_max = 2.78 / (rho_r + rho_i) (the region reaches
-//                   -2.785 on the real axis and +-2.83 i on the imaginary).
+//                   -2.785 on the real axis and +-2.83 i on the imaginary);
+//   eighth-order  : dt_max = 2.9 / (rho_r + rho_i) (Cooper and Verner's
+//                   method: -3.71 and +-3.00 i).
 // Bounds per right-hand side, u_max = ||u0||_inf:
 //   Burgers        rho_r = 4 nu / dx^2, rho_i = u_max / dx;
 //   diffusion-reaction  rho_r = max(Du, Dv) (4/dx^2 + 4/dy^2) + 2 + 3 u_max^2
 //                  (the reaction Jacobian's infinity norm);
-//   Brusselator    rho_r = max(Du, Dv) (4/dx^2 + 4/dy^2) + B + 1 + 3 u_max^2;
+//   Brusselator    rho_r = max(Du, Dv) (4/dx^2 + 4/dy^2 (+ 4/dz^2 in 3D))
+//                  + B + 1 + 3 u_max^2;
 //   shallow water  rho_r = 2 a (1/dx + 1/dy), a the largest wave speed
 //                  |velocity| + sqrt(g h) of the initial state.
 // All bounds are estimates at t0 (the nonlinear systems change their
@@ -27,7 +30,7 @@ namespace rpr {
 
 void stability_bounds(const Geom &g, double umax, double speed, double *rho_r, double *rho_i)
 {
-    const double lap = 4.0 * g.idx2 + (g.kind == RPR_BURGERS1D ? 0.0 : 4.0 * g.idy2);
+    const double lap = 4.0 * g.idx2 + (g.kind == RPR_BURGERS1D ? 0.0 : 4.0 * g.idy2) + 4.0 * g.idz2;
     double rr = 0.0, ri = 0.0;
     switch (g.kind) {
     case RPR_BURGERS1D:
@@ -38,6 +41,7 @@ void stability_bounds(const Geom &g, double umax, double speed, double *rho_r, d
         rr = std::max(g.p[0], g.p[1]) * lap + 2.0 + 3.0 * umax * umax;
         break;
     case RPR_BRUSS2D:
+    case RPR_BRUSS3D:
         rr = std::max(g.p[2], g.p[3]) * lap + g.p[1] + 1.0 + 3.0 * umax * umax;
         break;
     case RPR_SWE2D:
@@ -54,9 +58,11 @@ double stability_ratio(const Geom &g, int method, double dt, double umax, double
     double rr, ri;
     stability_bounds(g, umax, speed, &rr, &ri);
     dt = std::fabs(dt);
-    if (method == RPR_RK4) {
+    if (method == RPR_RK4 || method == RPR_RK8) {
+        // RK4 reaches -2.785 and +-2.83 i, the eighth-order method -3.71 and
+        // +-3.00 i (its stability function)
         const double r = rr + ri;
-        return r > 0.0 ? dt * r / 2.78 : 0.0;
+        return r > 0.0 ? dt * r / (method == RPR_RK4 ? 2.78 : 2.9) : 0.0;
     }
     double ratio = rr > 0.0 ? dt * rr / 2.0 : 0.0;
     if (ri > 0.0) {

@@ -17,10 +17,10 @@ import math
 
 import numpy as np
 
-BURGERS1D, DIFFREACT2D, BRUSS2D, SWE2D = 0, 1, 2, 3
-NSPECIES = {BURGERS1D: 1, DIFFREACT2D: 2, BRUSS2D: 2, SWE2D: 3}
+BURGERS1D, DIFFREACT2D, BRUSS2D, SWE2D, BRUSS3D = 0, 1, 2, 3, 4
+NSPECIES = {BURGERS1D: 1, DIFFREACT2D: 2, BRUSS2D: 2, SWE2D: 3, BRUSS3D: 2}
 TANH, RELU = 0, 1
-RK1, RK4 = 1, 4
+RK1, RK4, RK8 = 1, 4, 8
 
 
 @dataclasses.dataclass(frozen=True)
@@ -43,10 +43,11 @@ class Workload:
     ic: str                # initial-condition recipe name
     seed: int
     precision: str = "fp64"  # "fp64" (plain) or "mixed"
+    nz: int = 1              # cells along z (3D Brusselator)
 
     @property
     def d(self) -> int:
-        return NSPECIES[self.kind] * self.nx * self.ny
+        return NSPECIES[self.kind] * self.nx * self.ny * self.nz
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -81,7 +82,16 @@ BRUSS_128 = Workload("bruss_128x128", BRUSS2D, 128, 128, (-1.0, 1.0, -1.0, 1.0),
 SWE_192 = Workload("swe_192x192", SWE2D, 192, 192, (0.0, 1.0, 0.0, 1.0), (9.81,), 256, 0.0, 1.0,
                    (RK4, 1000), (RK1, 8), 300, RELU, 1e-6, 1e-6, "gauss_bumps", 5, "mixed")
 
-WORKLOADS = {w.name: w for w in (BURGERS_D128, BURGERS_D128_STABLE, DIFFREACT_64, BRUSS_128, SWE_192)}
+# App. E: Brusselator in three dimensions, periodic (-1, 1)^3, 20^3 cells
+#    (d = 16000), A = 1, B = 3, Du = 0.1, Dv = 0.01, t in [0, 35], N = 512,
+#    u = A, v ~ N(0, 1); F = the eighth-order method x 20 steps per slice,
+#    G = RK1 x 8 (both inside their stability regions: the setup table's
+#    coarse step 0.052 lies outside forward Euler's for this Laplacian),
+#    100 ReLU neurons.
+BRUSS3D_20 = Workload("bruss3d_20", BRUSS3D, 20, 20, (-1.0, 1.0, -1.0, 1.0), (1.0, 3.0, 0.1, 0.01), 512, 0.0, 35.0,
+                      (RK8, 20), (RK1, 8), 100, RELU, 1e-6, 1e-6, "bruss3d_normal", 6, "fp64", nz=20)
+
+WORKLOADS = {w.name: w for w in (BURGERS_D128, BURGERS_D128_STABLE, DIFFREACT_64, BRUSS_128, SWE_192, BRUSS3D_20)}
 
 
 def cell_centres(n: int, a: float, b: float) -> np.ndarray:
@@ -106,6 +116,11 @@ def initial_condition(w: Workload, seed: int | None = None) -> np.ndarray:
         A, B = w.params[0], w.params[1]
         u = A + 0.1 * rng.uniform(-1.0, 1.0, (w.ny, w.nx))
         v = B / A + 0.1 * rng.uniform(-1.0, 1.0, (w.ny, w.nx))
+        return np.concatenate([u.ravel(), v.ravel()]).astype(np.float64)
+    if w.ic == "bruss3d_normal":
+        # App. E: u = A everywhere, v normally distributed over the grid
+        u = np.full((w.nz, w.ny, w.nx), w.params[0])
+        v = rng.standard_normal((w.nz, w.ny, w.nx))
         return np.concatenate([u.ravel(), v.ravel()]).astype(np.float64)
     if w.ic == "gauss_bumps":
         xc = cell_centres(w.nx, x0, x1)

@@ -61,11 +61,36 @@ def test_propagate_rejects_bad_propagator_and_overlap():
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(method=2)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(steps=0)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 5, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
-    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(threads=128)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(threads=100)), 0, 1e-3, 1, 1 << 20, 1 << 30, None) == -1
     assert "threads" in rpr.last_error()
+    # the eighth-order method runs on the generic propagator only
+    assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop(method=8, threads=256)), 0, 1e-3, 1, 1 << 20, 1 << 30,
+                           None) == rpr.RPR_ERR_UNSUPPORTED
+    assert "generic" in rpr.last_error()
     # in and out overlapping
     assert L.rpr_propagate(C.byref(h), 64, C.byref(_prop()), 0, 1e-3, 2, 4096, 4096 + 512, None) == -1
     assert "overlap" in rpr.last_error()
+
+
+@pytest.mark.parametrize("kind,nx,ny,nz,d,msg", [
+    (rpr.RPR_BRUSS3D, 8, 8, 0, 128, "nz"),            # the 3D system needs nz >= 1
+    (rpr.RPR_BRUSS3D, 8, 8, 4, 2 * 8 * 8, "d must equal"),
+    (rpr.RPR_BRUSS2D, 8, 8, 2, 2 * 8 * 8 * 2, "nz"),  # 2D systems take nz 0 or 1
+])
+def test_propagate_rejects_bad_3d_problem(kind, nx, ny, nz, d, msg):
+    h = rpr.make_rhs(kind, nx, ny, nz=nz)
+    st = rpr.lib().rpr_propagate(C.byref(h), d, C.byref(_prop()), 0, 1e-3, 1, 1 << 20, 1 << 30, None)
+    assert st == rpr.RPR_ERR_INVALID_ARG
+    assert msg in rpr.last_error()
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_3d_system_runs_on_the_generic_propagator_only(threads):
+    h = rpr.make_rhs(rpr.RPR_BRUSS3D, 8, 8, nz=8)
+    st = rpr.lib().rpr_propagate(C.byref(h), 2 * 8 ** 3, C.byref(_prop(threads=threads)), 0, 1e-3, 1, 1 << 20,
+                                 1 << 30, None)
+    assert st == rpr.RPR_ERR_UNSUPPORTED
+    assert "generic" in rpr.last_error()
 
 
 @pytest.mark.parametrize("kind,nx,ny,prec,threads", [(1, 13, 9, 0, 512), (0, 128, 1, 0, 512), (1, 32, 32, 1, 512),
