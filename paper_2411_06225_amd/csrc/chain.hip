@@ -74,83 +74,105 @@ __device__ __forceinline__ double nan_max(double a, double b)
 // No work-group reads another's columns of x.  Sums and sigma in double in
 // both precisions (the training features of reduced-precision plans come
 // from the split-bfloat16 GEMM, accurate to the same order as FP32 states).
+// V consecutive values of a weight row as doubles, in vector loads where the
+// alignment allows (V * sizeof(T) bytes from an address that is a multiple
+// of it, or of 16 for four doubles).
+template <typename T, int V>
+__device__ __forceinline__ void load_run(const T *__restrict__ p, double *v)
+{
+    if constexpr (V == 1) {
+        v[0] = double(p[0]);
+    } else if constexpr (sizeof(T) == 4) {
+        using VT = typename std::conditional<V == 4, float4, float2>::type;
+        const VT r = *reinterpret_cast<const VT *>(p);
+        const float *f = reinterpret_cast<const float *>(&r);
+#pragma unroll
+        for (int u = 0; u < V; ++u) v[u] = f[u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < V; u += 2) {
+            const double2 r = *reinterpret_cast<const double2 *>(p + u);
+            v[u] = r.x;
+            v[u + 1] = r.y;
+        }
+    }
+}
+
+// Partial sums of the hidden layer over columns j0 .. j1 with V neurons per
+// thread: G = M / V neuron groups, R column classes (R x G <= B threads; at
+// most 16 so that the per-class sums fit the LDS the kernels reserve).
+// Thread (q, r) = (t mod G, t / G) sums A[m][j] x_j / s for its neurons
+// m = V q .. V q + V - 1 over the columns j = j0 + r, j0 + r + R, ...: a
+// wavefront reads a contiguous run of each row of A^T, and the loads of a
+// batch of CB columns are in flight together (the column bounds are checked
+// per batch, outside it).  With G > B (odd M above the block size) a thread
+// takes the groups t, t + B, ... of one class.  The class sums meet in LDS
+// (red, R x M doubles) and are added in class order.
+template <typename T, int V>
+__device__ __forceinline__ int hidden_partial_v(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
+                                                const int j1, double *red)
+{
+    constexpr int CB = 8;
+    const int t = threadIdx.x, B = blockDim.x, M = a.M;
+    const int G = M / V;
+    const int R = G <= B ? min(16, B / G) : 1;
+    const int r = G <= B ? t / G : 0;
+    if (r < R) {
+        for (int q = G <= B ? t % G : t; q < G; q += G <= B ? G : B) {
+            double p[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) p[u] = 0.0;
+            const T *base = a.At + (size_t)V * q;
+            int j = j0 + r;
+            for (; j + (CB - 1) * R < j1; j += CB * R) {
+                double w[CB][V], xv[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    load_run<T, V>(base + (size_t)(j + k * R) * M, w[k]);
+                    xv[k] = double(x[j + k * R]) * a.inv_s;
+                }
+#pragma unroll
+                for (int k = 0; k < CB; ++k)
+#pragma unroll
+                    for (int u = 0; u < V; ++u) p[u] = fma(w[k][u], xv[k], p[u]);
+            }
+            for (; j < j1; j += R) {
+                double w[V];
+                load_run<T, V>(base + (size_t)j * M, w);
+                const double xv = double(x[j]) * a.inv_s;
+#pragma unroll
+                for (int u = 0; u < V; ++u) p[u] = fma(w[u], xv, p[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) red[r * M + V * q + u] = p[u];
+        }
+    }
+    return R;
+}
+
 template <typename T>
 __device__ __forceinline__ void hidden_partial(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
                                                const int j1, const int wg, double *red)
 {
-    // whole wavefronts only (a block narrower than a wavefront is one partial
-    // wavefront of WL lanes); a trailing partial wavefront stays idle.
-    // Wavefront w takes columns j0 + w cpw .. j0 + (w+1) cpw, lane l the
-    // neurons l, l + WL, ...; the wavefronts' sums meet in LDS (red, nw x M
-    // doubles) and are added in wavefront order.
-    const int t = threadIdx.x, B = blockDim.x, d = a.g.d;
-    const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
-    const int lane = t & 63, wv = t >> 6;
-    if (wv < nw) {
-        const int cpw = (j1 - j0 + nw - 1) / nw;
-        const int c0 = j0 + wv * cpw, c1 = min(j1, c0 + cpw);
-        constexpr int MPL = 4;  // neurons per lane and pass
-        // FP32 weights with M even: lane l takes the neuron pairs (2l, 2l + 1)
-        // and (2 WL + 2l, 2 WL + 2l + 1) of each pass, one 8-byte load per pair
-        // and column
-        auto pass = [&](auto pair_tag) {
-            constexpr bool PAIR = decltype(pair_tag)::value;
-            constexpr int CB4 = 4;  // columns per load batch
-            auto neuron = [&](int mb, int u) {
-                return PAIR ? mb + 2 * WL * (u >> 1) + 2 * lane + (u & 1) : mb + lane + WL * u;
-            };
-            for (int mb = 0; mb < a.M; mb += WL * MPL) {
-                double p[MPL];
-#pragma unroll
-                for (int u = 0; u < MPL; ++u) p[u] = 0.0;
-                for (int cb = c0; cb < c1; cb += CB4) {
-                    double xv[CB4], wv4[MPL][CB4];
-#pragma unroll
-                    for (int k = 0; k < CB4; ++k) {
-                        const int j = cb + k;
-                        xv[k] = j < c1 ? double(x[j]) * a.inv_s : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < MPL; u += PAIR ? 2 : 1) {
-                        const int m = neuron(mb, u);
-#pragma unroll
-                        for (int k = 0; k < CB4; ++k) {
-                            const int j = cb + k;
-                            const bool ok = m < a.M && j < c1;
-                            if constexpr (PAIR) {
-                                float2 v = make_float2(0.0f, 0.0f);
-                                if (ok) v = *reinterpret_cast<const float2 *>(a.At + (size_t)j * a.M + m);
-                                wv4[u][k] = v.x;
-                                wv4[u + 1][k] = v.y;
-                            } else {
-                                wv4[u][k] = ok ? double(a.At[(size_t)j * a.M + m]) : 0.0;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < MPL; ++u)
-#pragma unroll
-                        for (int k = 0; k < CB4; ++k) p[u] = fma(wv4[u][k], xv[k], p[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < MPL; ++u) {
-                    const int m = neuron(mb, u);
-                    if (m < a.M) red[wv * a.M + m] = p[u];
-                }
-            }
-        };
-        if constexpr (sizeof(T) == 4) {
-            if (a.M % 2 == 0) pass(std::true_type{});
-            else pass(std::false_type{});
-        } else {
-            pass(std::false_type{});
-        }
-    }
+    // neurons per thread: the run length that keeps the most bytes in
+    // flight (busy threads x V; ties to the longer run)
+    const int M = a.M, B = blockDim.x;
+    auto inflight = [&](int v) {
+        const int G = M / v;
+        return (G <= B ? min(16, B / G) * G : B) * v;
+    };
+    int R;
+    if (M % 4 == 0 && inflight(4) >= inflight(2) && inflight(4) >= inflight(1))
+        R = hidden_partial_v<T, 4>(a, x, j0, j1, red);
+    else if (M % 2 == 0 && inflight(2) >= inflight(1))
+        R = hidden_partial_v<T, 2>(a, x, j0, j1, red);
+    else
+        R = hidden_partial_v<T, 1>(a, x, j0, j1, red);
     __syncthreads();
-    for (int m = t; m < a.M; m += B) {
+    for (int m = threadIdx.x; m < M; m += B) {
         double z = 0.0;
-        for (int w = 0; w < nw; ++w) z += red[w * a.M + m];
-        a.hpart[(size_t)wg * a.M + m] = z;
+        for (int w = 0; w < R; ++w) z += red[w * M + m];
+        a.hpart[(size_t)wg * M + m] = z;
     }
 }
 
@@ -563,87 +585,75 @@ __device__ __forceinline__ void chain_seg_p2(const ChainArgs<T> &a, const int i,
             dist_partial(a, Ui, j0, j1, wg, n_store);
         }
     } else if (net) {
-        // readout W^T phi on columns j0 .. j1: wavefront w sums the neurons
-        // m = w, w + nw, ... for 2 tiles of 64 columns at a time, then
-        // wavefront q < 2 adds the nw partial sums of tile q in order
-        constexpr int TPT = 2;
-        const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;  // whole wavefronts, as above
+        // readout W^T phi on columns j0 .. j1: wavefront v takes the tiles
+        // of 2 WL columns jb = j0 + 2 WL (v + nw k), lane l the columns
+        // jb + 2l and jb + 2l + 1, each summed over the M neurons in order.
+        // The column checks sit outside the loop over neurons, so the loads
+        // of a batch of neurons are in flight together (one load per neuron
+        // and pair of columns where d is even)
+        const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
         const int lane = t & 63, wv = t >> 6;
-        double *sphi = scratch;                                        // M
-        double *red = scratch + ((a.M + 63) / 64) * 64;                // nw x TPT x WL
+        double *sphi = scratch;  // M
         for (int m = t; m < a.M; m += B) sphi[m] = a.phi[m];
         __syncthreads();
-        // FP32 weights with d even: lane l takes the adjacent columns
-        // jb + 2l, jb + 2l + 1 (one 8-byte load per neuron) instead of
-        // jb + l and jb + WL + l; the chunk bounds are even, so is d
-        bool pair = false;
-        if constexpr (sizeof(T) == 4) pair = d % 2 == 0;
-        auto tile = [&](const int jb, auto pair_tag) {
-            constexpr bool PAIR = decltype(pair_tag)::value;
-            static_assert(TPT == 2 || !PAIR, "a pair is two tiles");
-            double acc[TPT];
+        const int M = a.M;
+        const bool vec = d % 2 == 0;
+        auto update = [&](const int j, const double c) {
+            const T gv = a.gtmp[j];
+            const T unew = T(double(gv) + c);
+            emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
+            Ui[j] = unew;
+            Gci[j] = gv;
+        };
+        for (int jb = j0 + 2 * WL * wv; wv < nw && jb < j1; jb += 2 * WL * nw) {
+            const int j = jb + 2 * lane;
+            const T *wp = a.W + j;
+            if (j + 1 < j1) {
+                double c0 = 0.0, c1 = 0.0;
+                auto sum = [&](auto vec_tag) {
+                    constexpr bool VEC = decltype(vec_tag)::value;
+                    constexpr int UR = 8;
+                    int m0 = 0;
+                    for (; m0 + UR <= M; m0 += UR) {
+                        double w0[UR], w1[UR];
 #pragma unroll
-            for (int q = 0; q < TPT; ++q) acc[q] = 0.0;
-            // batches of NB neurons x TPT columns (twice the batch for
-            // the FP32 pairs moved no faster and cost registers that the
-            // coarse solver's step loop then spilled)
-            constexpr int NB = 8;
-            for (int m0 = wv; m0 < a.M; m0 += NB * nw) {
-                double wr[NB][TPT];
+                        for (int u = 0; u < UR; ++u) {
+                            const T *q = wp + (size_t)(m0 + u) * d;
+                            if constexpr (VEC) {
+                                double v2[2];
+                                load_run<T, 2>(q, v2);
+                                w0[u] = v2[0];
+                                w1[u] = v2[1];
+                            } else {
+                                w0[u] = double(q[0]);
+                                w1[u] = double(q[1]);
+                            }
+                        }
 #pragma unroll
-                for (int u = 0; u < NB; ++u) {
-                    const int m = m0 + u * nw;
-                    if constexpr (PAIR) {
-                        const int j = jb + 2 * lane;
-                        float2 v = make_float2(0.0f, 0.0f);
-                        if (m < a.M && j < j1) v = *reinterpret_cast<const float2 *>(a.W + (size_t)m * d + j);
-                        wr[u][0] = v.x;
-                        wr[u][1] = v.y;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < TPT; ++q) {
-                            const int j = jb + WL * q + lane;
-                            wr[u][q] = (m < a.M && j < j1) ? double(a.W[(size_t)m * d + j]) : 0.0;
+                        for (int u = 0; u < UR; ++u) {
+                            const double ph = sphi[m0 + u];
+                            c0 = fma(w0[u], ph, c0);
+                            c1 = fma(w1[u], ph, c1);
                         }
                     }
-                }
-#pragma unroll
-                for (int u = 0; u < NB; ++u) {
-                    const int m = m0 + u * nw;
-                    const double ph = m < a.M ? sphi[m] : 0.0;
-#pragma unroll
-                    for (int q = 0; q < TPT; ++q) acc[q] = fma(wr[u][q], ph, acc[q]);
-                }
+                    for (; m0 < M; ++m0) {
+                        const double ph = sphi[m0];
+                        c0 = fma(double(wp[(size_t)m0 * d]), ph, c0);
+                        c1 = fma(double(wp[(size_t)m0 * d + 1]), ph, c1);
+                    }
+                };
+                if (vec) sum(std::true_type{});
+                else sum(std::false_type{});
+                update(j, c0);
+                update(j + 1, c1);
+            } else if (j < j1) {
+                double c0 = 0.0;
+                for (int m0 = 0; m0 < M; ++m0) c0 = fma(double(wp[(size_t)m0 * d]), sphi[m0], c0);
+                update(j, c0);
             }
-#pragma unroll
-            for (int q = 0; q < TPT; ++q) red[(wv * TPT + q) * WL + lane] = acc[q];
-        };
-        for (int jb = j0; jb < j1; jb += WL * TPT) {
-            if (wv < nw) {
-                if constexpr (sizeof(T) == 4) {
-                    if (pair) tile(jb, std::true_type{});
-                    else tile(jb, std::false_type{});
-                } else {
-                    tile(jb, std::false_type{});
-                }
-            }
-            __syncthreads();
-            for (int q = wv; q < TPT && wv < nw; q += nw) {
-                const int j = jb + WL * q + lane;
-                if (j < j1) {
-                    // partial sums of column j: tile q, lane l, or the pair layout
-                    const int x = j - jb, qq = pair ? (x & 1) : q, ll = pair ? (x >> 1) : lane;
-                    double c = 0.0;
-                    for (int w = 0; w < nw; ++w) c += red[(w * TPT + qq) * WL + ll];
-                    const T gv = a.gtmp[j];
-                    const T unew = T(double(gv) + c);
-                    emax = nan_max(emax, fabs(double(unew) - double(Ui[j])));
-                    Ui[j] = unew;
-                    Gci[j] = gv;
-                }
-            }
-            __syncthreads();
         }
+        // the state's columns written by the other wavefronts; sphi free
+        __syncthreads();
         // hidden-layer partial sums of the new state's columns, for slot i + 1
         if (i < N) hidden_partial(a, Ui, j0, j1, wg, scratch);
     } else {
