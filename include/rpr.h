@@ -184,7 +184,17 @@ typedef struct {
                                   through the summation order of the hidden
                                   layer's partial sums, which follow the column
                                   blocks of the work-groups. */
-    int32_t reserved;          /* must be 0 */
+    int32_t sweep_form;        /* how a plan without graph capture launches the
+                                  predictor-corrector sweep (Sec. 2; the same
+                                  values either way): 1 one cooperative kernel
+                                  whose segments (per slot: coarse solve, then
+                                  readout and update) are separated by grid
+                                  barriers; 2 one kernel per segment, the kernel
+                                  boundaries as the barriers (the form graph
+                                  capture records); 0 automatic: 2 when the coarse
+                                  solver runs over the whole grid (tiled and
+                                  generic propagators), else 1.  Graph plans
+                                  always use 2. */
 } rpr_options;
 
 /* ---- plans: one IVP solved by RandNet-Parareal -------------------------- */

@@ -64,7 +64,7 @@ class rpr_randnet(C.Structure):
 class rpr_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("correction", C.c_int32), ("k_max", C.c_int32),
                 ("poll_every", C.c_int32), ("features", C.c_int32), ("autotune", C.c_int32),
-                ("graph", C.c_int32), ("stability", C.c_int32), ("chain_wgs", C.c_int32), ("reserved", C.c_int32)]
+                ("graph", C.c_int32), ("stability", C.c_int32), ("chain_wgs", C.c_int32), ("sweep_form", C.c_int32)]
 
 
 class rpr_info(C.Structure):
@@ -270,7 +270,7 @@ class Plan:
                  input_scale: float = 0.0, A=None, zeta=None, seed: int = 0, precision: int = RPR_FP64,
                  correction: int = RPR_CORR_RANDNET, k_max: int = 0, poll_every: int = 0,
                  features: int = RPR_FEAT_AUTO, autotune: int = 0, graph: int = 0, m_nn: int = 4,
-                 stability: int = 0, chain_wgs: int = 0):
+                 stability: int = 0, chain_wgs: int = 0, sweep_form: int = 0):
         import numpy as np
         self.d, self.N = int(d), int(N)
         # F, G: (method, steps) or (method, steps, threads)
@@ -278,7 +278,7 @@ class Plan:
         self._G = rpr_propagator(int(G[0]), int(G[2]) if len(G) > 2 else 0, int(G[1]))
         self._net = rpr_randnet(int(M), int(activation), float(lam), float(input_scale), int(m_nn), 0)
         self._opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features),
-                                int(autotune), int(graph), int(stability), int(chain_wgs), 0)
+                                int(autotune), int(graph), int(stability), int(chain_wgs), int(sweep_form))
         self._h = h
         Ah = zh = None
         if A is not None:

@@ -285,10 +285,8 @@ static rpr_status plan_alloc(rpr_plan *p, const double *A, const double *zeta, u
     p->ctrl_host = static_cast<Ctrl *>(h);
     RPR_HIP(hipEventCreate(&p->ev0));
     RPR_HIP(hipEventCreate(&p->ev1));
-    if (p->use_graph) {
-        RPR_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-        RPR_HIP(hipMalloc(&p->gchain, sizeof(ChainArgs<double>)));
-    }
+    if (p->use_graph) RPR_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    if (p->use_graph || p->seg_sweep) RPR_HIP(hipMalloc(&p->gchain, sizeof(ChainArgs<double>)));
     return RPR_OK;
 }
 
@@ -325,7 +323,7 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
     if (opt->graph != 0 && opt->graph != 1) return fail(RPR_ERR_INVALID_ARG, "opt.graph must be 0 or 1");
     if (opt->stability != 0 && opt->stability != 1) return fail(RPR_ERR_INVALID_ARG, "opt.stability must be 0 or 1");
     if (opt->chain_wgs < 0) return fail(RPR_ERR_INVALID_ARG, "opt.chain_wgs must be >= 0");
-    if (opt->reserved != 0) return fail(RPR_ERR_INVALID_ARG, "opt.reserved must be 0");
+    if (opt->sweep_form < 0 || opt->sweep_form > 2) return fail(RPR_ERR_INVALID_ARG, "opt.sweep_form must be 0, 1 or 2");
     const bool use_net = opt->correction == RPR_CORR_RANDNET || opt->correction == RPR_CORR_RANDNET_NN;
     if (use_net) {
         if (!net) return fail(RPR_ERR_INVALID_ARG, "net is NULL");
@@ -409,6 +407,11 @@ extern "C" rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t
         delete p;
         return fail(RPR_ERR_UNSUPPORTED, "net.M too large for the ridge solve");
     }
+    // the sweep's form: segment kernels where the coarse solver runs over the
+    // whole grid (its passes need grid-wide barriers, which cost more than
+    // kernel boundaries), or as asked
+    const bool grid_coarse = p->shG.maxt == TILED_THREADS || p->shG.maxt == GENERIC_THREADS;
+    p->seg_sweep = opt->sweep_form == 2 || (opt->sweep_form == 0 && grid_coarse);
     rpr_status st = plan_alloc(p, A, zeta, seed);
     if (st != RPR_OK) {
         const std::string keep = g_err;
@@ -528,14 +531,14 @@ static rpr_status execute_impl(rpr_plan *p, const double *u0, double *U_out, hip
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev], s));
         RPR_TRY(phase_model<T>(p, a.inv_s, s));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 1], s));
-        if (graph)
+        if (graph || p->seg_sweep)
             RPR_TRY(launch_chain_graph<T>(static_cast<const ChainArgs<T> *>(p->gchain), a, p->shG, p->nwg, s));
         else
             RPR_TRY(launch_chain<T>(a, p->shG, p->nwg, s));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 2], s));
         return RPR_OK;
     };
-    if (p->use_graph) RPR_HIP(hipMemcpyAsync(p->gchain, &a, sizeof(a), hipMemcpyHostToDevice, st));
+    if (p->gchain) RPR_HIP(hipMemcpyAsync(p->gchain, &a, sizeof(a), hipMemcpyHostToDevice, st));
     // graph mode: a block of `poll` iterations is captured once (again when
     // the input scale changes) and replayed; iterations after the stop flag
     // is raised return at once

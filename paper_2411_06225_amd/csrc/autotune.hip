@@ -215,6 +215,13 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
             check_threads(g, p->esz, 512) == RPR_OK)
             n_shapes = 2;
         const int cands[] = {1, cus / 16, cus / 8, cus / 4, cus / 2, cus};
+        // the trials run the sweep in the plan's form
+        if (p->seg_sweep) RPR_HIP(hipMemcpy(p->gchain, &a, sizeof(a), hipMemcpyHostToDevice));
+        auto sweep = [&](const OnchipShape &sh, int c) -> rpr_status {
+            if (p->seg_sweep)
+                return launch_chain_graph<T>(static_cast<const ChainArgs<T> *>(p->gchain), a, sh, c, st);
+            return launch_chain<T>(a, sh, c, st);
+        };
         for (int s = 0; s < n_shapes; ++s) {
             const OnchipShape &sh = gshapes[s];
             int mwg = max_wg;  // grids beyond the plan's max_wg have no partial-sum rows
@@ -231,10 +238,10 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
                 if (sh.maxt == TILED_THREADS && c < tiles_of(g)) continue;
                 float ms = 0.f;
                 RPR_TRY(launch_init_ctrl(p->ctrl, p->L_hist, p->chg_hist, st));
-                RPR_TRY(launch_chain<T>(a, sh, c, st));
+                RPR_TRY(sweep(sh, c));
                 RPR_HIP(hipEventRecord(e0, st));
                 RPR_TRY(launch_init_ctrl(p->ctrl, p->L_hist, p->chg_hist, st));
-                RPR_TRY(launch_chain<T>(a, sh, c, st));
+                RPR_TRY(sweep(sh, c));
                 RPR_HIP(hipEventRecord(e1, st));
                 RPR_HIP(hipEventSynchronize(e1));
                 RPR_HIP(hipEventElapsedTime(&ms, e0, e1));

@@ -74,6 +74,14 @@ rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int n
 // segment of a final slot returns at once.  args_dev: device copy of a (read
 // by the kernels when they run); a: the host copy (sizes, mode, coarse
 // propagator).  Same arithmetic as launch_chain with nwg work-groups.
+// The k = 0 sweep (a.mode == CHAIN_SWEEP) of a grid-wide coarse solver
+// (tiled or generic shape) as one kernel per pass of every slot on nwg
+// work-groups; the values of launch_chain's sweep.
+template <typename T>
+rpr_status launch_sweep_segments(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st);
+template <int KIND, typename T>
+rpr_status launch_sweep_segments_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st);
+
 template <typename T>
 rpr_status launch_chain_graph(const ChainArgs<T> *args_dev, const ChainArgs<T> &a, const OnchipShape &sh, int nwg,
                               hipStream_t st);

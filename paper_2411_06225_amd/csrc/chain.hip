@@ -450,7 +450,6 @@ template <int KIND, typename T>
 __device__ __forceinline__ void tiled_coarse_pass(const ChainArgs<T> &a, const T *src, T *dst, T *dst2,
                                                   const long long pass, const int wg, const int nwg, T *lds)
 {
-    const int nt = tiles_of(a.g);
     if (a.G_method == RPR_RK1) {
         T *buf[2] = {a.gw.u, a.gw.ya};
         T *cbuf[2] = {a.gw.cmp, a.gw.acc};
@@ -459,11 +458,18 @@ __device__ __forceinline__ void tiled_coarse_pass(const ChainArgs<T> &a, const T
         const bool last = s + n >= a.G_steps;
         const T *in = s == 0 ? src : buf[(pass - 1) & 1];
         T *out = last ? dst : buf[pass & 1];
-        for (int tile = wg; tile < nt; tile += nwg)
-            euler_tile_multi<KIND, T>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr, cbuf[(pass + 1) & 1],
-                                      cbuf[pass & 1], s == 0 ? 1 : 0, lds);
+        auto run = [&](auto tile_tag) {
+            using ET = decltype(tile_tag);
+            const int nt = ET::tiles(a.g);
+            for (int tile = wg; tile < nt; tile += nwg)
+                euler_tile_multi<KIND, T, ET>(a.g, tile, n, a.dtG, in, out, last ? dst2 : (T *)nullptr,
+                                              cbuf[(pass + 1) & 1], cbuf[pass & 1], s == 0 ? 1 : 0, lds);
+        };
+        if (SweepEulerSmall::tiles(a.g) <= nwg) run(SweepEulerSmall{});
+        else run(SweepEuler{});
         return;
     }
+    const int nt = tiles_of(a.g);
     const long long step = pass / 4;
     const int stage = (int)(pass % 4) + 1;
     const StageIO<T> io = stage_io<T>(a.G_method, stage, step, a.G_steps, src, dst, dst2, a.gw);
@@ -684,25 +690,50 @@ __device__ __forceinline__ void chain_seg_p2(const ChainArgs<T> &a, const int i,
     }
 }
 
-// Stopping rule (eq. "stop_crit"), by work-group 0, thread 0.
+// Stopping rule (eq. "stop_crit") on work-group 0: the change of slot i is
+// the largest of the work-groups' maxima for it (one wavefront per slot;
+// nan_max is order-free), staged in LDS in chunks of EPI_CHUNK slots; thread
+// 0 then walks the slots in order.
+constexpr int EPI_CHUNK = 1024;
+
 template <typename T, bool NN_OK>
-__device__ __forceinline__ void chain_seg_epi(const ChainArgs<T> &a, const int wg, const int nwg)
+__device__ __forceinline__ void chain_seg_epi(const ChainArgs<T> &a, const int wg, const int nwg, double *scratch)
 {
-    if (wg != 0 || threadIdx.x != 0) return;
+    if (wg != 0) return;
+    const int t = threadIdx.x, B = blockDim.x;
+    const int WL = B >= 64 ? 64 : B, nw = B >= 64 ? B / 64 : 1;
+    const int lane = t & 63, wv = t >> 6;
     Ctrl *ctrl = a.ctrl;
     const int L = ctrl->L, N = a.N;
-    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
-    const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
-    double chg = 0.0;
+    double chg = 0.0;  // thread 0's
     int Lnew = L + 1;
     bool run = true;
-    for (int i = L + 2; i <= N; ++i) {
-        double e = 0.0;
-        for (int w = 0; w < nwg; ++w) e = nan_max(e, a.part[(size_t)i * nwg + w]);
-        chg = nan_max(chg, e);
-        if (run && e < a.eps) Lnew = i;
-        else run = false;
+    for (int c0 = L + 2; c0 <= N; c0 += EPI_CHUNK) {
+        const int c1 = min(N + 1, c0 + EPI_CHUNK);
+        for (int i = c0 + wv; wv < nw && i < c1; i += nw) {
+            double e = 0.0;
+            for (int w = lane; w < nwg; w += WL) e = nan_max(e, a.part[(size_t)i * nwg + w]);
+            for (int off = 32; off > 0; off >>= 1) {
+                const double o = __shfl_down(e, off, 64);
+                if (lane + off < WL) e = nan_max(e, o);
+            }
+            if (lane == 0) scratch[i - c0] = e;
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int i = c0; i < c1; ++i) {
+                const double e = scratch[i - c0];
+                chg = nan_max(chg, e);
+                if (run && e < a.eps) Lnew = i;
+                else run = false;
+            }
+        }
+        __syncthreads();
     }
+    __syncthreads();  // every thread has read L before thread 0 moves it
+    if (t != 0) return;
+    const bool nn = NN_OK && a.mode == CHAIN_RANDNET_NN;
+    const int n_store = nn ? ctrl->nn_rows + *a.nrows : 0;
     const int k = ctrl->k + 1;
     ctrl->k = k;
     ctrl->L = Lnew;
@@ -756,7 +787,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs<T> &a, const int wg, 
         chain_seg_p2<T, NN_OK>(a, i, wg, nwg, scratch);
         sync();
     }
-    chain_seg_epi<T, NN_OK>(a, wg, nwg);
+    chain_seg_epi<T, NN_OK>(a, wg, nwg, scratch);
 }
 
 // One segment of a sweep as a kernel of its own (captured graphs): seg 0 the
@@ -776,7 +807,7 @@ __global__ __launch_bounds__(MAXT) void k_chain_seg(const ChainArgs<T> *__restri
     if (seg == 0) {
         chain_seg_pro<T, NN_OK>(a, wg, nwg, scratch);
     } else if (seg == 3) {
-        chain_seg_epi<T, NN_OK>(a, wg, nwg);
+        chain_seg_epi<T, NN_OK>(a, wg, nwg, scratch);
     } else {
         if (i < L + 2) return;
         if (seg == 2) {
@@ -992,6 +1023,52 @@ rpr_status launch_chain_kind(const ChainArgs<T> &a, const OnchipShape &sh, int n
     return visit_shape_kind<KIND, T>(a.g, sh, L);
     }
 }
+
+// The k = 0 sweep of a grid-wide coarse solver as one kernel per pass:
+// U_i = G(U_{i-1}) and Gc_i, i = 1..N, pass `pass` of slot i on the plan's
+// grid (the arithmetic of the cooperative sweep's CHAIN_SWEEP mode, the
+// kernel boundaries as its barriers).
+template <int KIND, typename T, int MAXT, int CM>
+__global__ __launch_bounds__(MAXT) void k_sweep_pass(ChainArgs<T> a, int i, long long pass)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const size_t d = a.g.d;
+    coarse_pass<KIND, T, CM>(a, a.U + (size_t)(i - 1) * d, a.U + (size_t)i * d, a.Gc + (size_t)i * d, pass,
+                             blockIdx.x, gridDim.x, reinterpret_cast<T *>(lds_raw));
+}
+
+template <int KIND, typename T>
+rpr_status launch_sweep_segments_kind(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st)
+{
+    auto run = [&](auto kern, int block, long long passes) -> rpr_status {
+        static bool attr_set = false;
+        if (!attr_set) {
+            RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxLds));
+            attr_set = true;
+        }
+        const size_t lds = chain_lds(sh, a.M);
+        for (int i = 1; i <= a.N; ++i)
+            for (long long pass = 0; pass < passes; ++pass)
+                hipLaunchKernelGGL(kern, dim3(nwg), dim3(block), lds, st, a, i, pass);
+        RPR_HIP(hipGetLastError());
+        return RPR_OK;
+    };
+    if (sh.maxt == GENERIC_THREADS)
+        return run(k_sweep_pass<KIND, T, GENERIC_BLOCK, CM_GENERIC>, GENERIC_BLOCK,
+                   coarse_passes(CM_GENERIC, a.G_method, a.G_steps, a.tbG.s));
+    if constexpr (KIND == RPR_BURGERS1D || KIND == RPR_BRUSS3D) {
+        return fail(RPR_ERR_UNSUPPORTED, "sweep segments: no grid-wide coarse solver of this form");
+    } else {
+        if (sh.maxt != TILED_THREADS)
+            return fail(RPR_ERR_UNSUPPORTED, "sweep segments: the on-chip coarse solver runs in one work-group");
+        return run(k_sweep_pass<KIND, T, TT_THREADS, CM_TILED>, TT_THREADS,
+                   coarse_passes(CM_TILED, a.G_method, a.G_steps, a.tbG.s));
+    }
+}
+
+template rpr_status launch_sweep_segments_kind<RPR_KIND, RPR_REAL>(const ChainArgs<RPR_REAL> &, const OnchipShape &,
+                                                                   int, hipStream_t);
 
 // A sweep as a sequence of segment kernels (for capture in a graph): the
 // prologue, per slot i = 2..N phase 1 (the tiled coarse solver's passes) and

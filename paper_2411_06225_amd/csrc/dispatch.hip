@@ -190,6 +190,21 @@ template rpr_status launch_chain<double>(const ChainArgs<double> &, const Onchip
 template rpr_status launch_chain<float>(const ChainArgs<float> &, const OnchipShape &, int, hipStream_t, int *);
 
 template <typename T>
+rpr_status launch_sweep_segments(const ChainArgs<T> &a, const OnchipShape &sh, int nwg, hipStream_t st)
+{
+    switch (a.g.kind) {
+    case RPR_BURGERS1D: return launch_sweep_segments_kind<RPR_BURGERS1D, T>(a, sh, nwg, st);
+    case RPR_DIFFREACT2D: return launch_sweep_segments_kind<RPR_DIFFREACT2D, T>(a, sh, nwg, st);
+    case RPR_BRUSS2D: return launch_sweep_segments_kind<RPR_BRUSS2D, T>(a, sh, nwg, st);
+    case RPR_SWE2D: return launch_sweep_segments_kind<RPR_SWE2D, T>(a, sh, nwg, st);
+    case RPR_BRUSS3D: return launch_sweep_segments_kind<RPR_BRUSS3D, T>(a, sh, nwg, st);
+    default: return fail(RPR_ERR_INVALID_ARG, "chain: unknown right-hand side");
+    }
+}
+template rpr_status launch_sweep_segments<double>(const ChainArgs<double> &, const OnchipShape &, int, hipStream_t);
+template rpr_status launch_sweep_segments<float>(const ChainArgs<float> &, const OnchipShape &, int, hipStream_t);
+
+template <typename T>
 rpr_status launch_chain_graph(const ChainArgs<T> *args_dev, const ChainArgs<T> &a, const OnchipShape &sh, int nwg,
                               hipStream_t st)
 {

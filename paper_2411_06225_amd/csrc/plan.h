@@ -94,6 +94,7 @@ struct rpr_plan {
     bool feat_bf16 = false;
     int autotune = 0;
     int use_graph = 0;
+    bool seg_sweep = false;             // the sweep as segment kernels (rpr_options.sweep_form)
     int strict = 0;                     // opt.stability: 1 rejects solves the pre-check finds unstable
     int fvar = 0;                       // tile shape of the fine propagator's one-pass form
     bool fixed_nwg = false;             // opt.chain_wgs set: the autotuner keeps the chain grid
@@ -316,9 +317,10 @@ inline rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStr
     a.mode = CHAIN_SWEEP;
     // on chip the sweep's state stays in one work-group; the tiled and
     // generic coarse solvers spread each slot's tiles or cells over the plan's
-    // grid
-    RPR_TRY(launch_chain<T>(a, p->shG, p->shG.maxt == TILED_THREADS || p->shG.maxt == GENERIC_THREADS ? p->nwg : 1,
-                            st));
+    // grid, in one cooperative kernel or one kernel per pass
+    const bool grid = p->shG.maxt == TILED_THREADS || p->shG.maxt == GENERIC_THREADS;
+    if (grid && p->seg_sweep) RPR_TRY(launch_sweep_segments<T>(a, p->shG, p->nwg, st));
+    else RPR_TRY(launch_chain<T>(a, p->shG, grid ? p->nwg : 1, st));
     a.mode = chain_mode(p);
     *out = a;
     return RPR_OK;

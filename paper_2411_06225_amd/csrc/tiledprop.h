@@ -411,26 +411,44 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int tile, const 
 // tile may read a neighbour's compensation while that neighbour writes its
 // own; alternating the arrays between passes, as the state alternates, keeps
 // every read on the previous pass's values.
-constexpr int EH = 8;
-constexpr int ERX = TT_X + 2 * EH, ERY = TT_Y + 2 * EH;
+// The tile: EX x EY cells with an EH-cell halo (so up to EH steps a pass).
+template <int EX_, int EY_, int EH_>
+struct EulerTile {
+    static constexpr int EX = EX_, EY = EY_, EH = EH_;
+    static constexpr int ERX = EX + 2 * EH, ERY = EY + 2 * EH;
+    __host__ __device__ static int tiles_x(const Geom &g) { return (g.nx + EX - 1) / EX; }
+    __host__ __device__ static int tiles(const Geom &g) { return tiles_x(g) * ((g.ny + EY - 1) / EY); }
+    __host__ __device__ static size_t lds(const Geom &g, size_t elem)
+    {
+        return (size_t)(elem == 4 ? 3 : 2) * g.ns * ERY * ERX * elem;
+    }
+};
+// The sweep's tiles: 16 x 16 cells when there are no more of them than
+// work-groups (a 192 x 192 grid: 144 tiles, each a quarter of the halo
+// region's cells per thread of the 64 x 16 form, 28 against 64 us for eight
+// steps), else 64 x 16 (less halo per cell when the tiles take several
+// rounds).  Both give the same values bit for bit: a cell's update depends
+// only on its neighbours at the previous step.
+using SweepEuler = EulerTile<64, 16, 8>;
+using SweepEulerSmall = EulerTile<16, 16, 8>;
+constexpr int EH = SweepEuler::EH;
+static_assert(SweepEulerSmall::EH == EH, "one step count per pass for both tile shapes");
 
-__host__ __device__ inline size_t euler_multi_lds(const Geom &g, size_t elem)
-{
-    return (size_t)(elem == 4 ? 3 : 2) * g.ns * ERY * ERX * elem;
-}
+__host__ __device__ inline size_t euler_multi_lds(const Geom &g, size_t elem) { return SweepEuler::lds(g, elem); }
 
-template <int KIND, typename T>
+template <int KIND, typename T, typename ET = SweepEuler>
 __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, const int steps, const double dt,
                                                  const T *__restrict__ src, T *__restrict__ dst,
                                                  T *__restrict__ dst2, const T *__restrict__ cmp_in,
                                                  T *__restrict__ cmp_out, const int cmp_zero, T *__restrict__ lds)
 {
+    constexpr int EX = ET::EX, EY = ET::EY, EH = ET::EH, ERX = ET::ERX, ERY = ET::ERY;
     constexpr int NS = kind_ns<KIND>();
     constexpr int RN = ERX * ERY;
     constexpr bool KAHAN = sizeof(T) == 4;
     const int nx = g.nx, ny = g.ny, nc = g.nc;
     constexpr bool per = kind_periodic<KIND>();
-    const int x0 = (tile % tiles_x(g)) * TT_X, y0 = (tile / tiles_x(g)) * TT_Y;
+    const int x0 = (tile % ET::tiles_x(g)) * EX, y0 = (tile / ET::tiles_x(g)) * EY;
     const int gx0 = x0 - EH, gy0 = y0 - EH;  // domain cell of region cell (0, 0)
     T *buf[2] = {lds, lds + NS * RN};
     T *cm = lds + 2 * NS * RN;  // FP32 compensation
@@ -495,9 +513,9 @@ __device__ __forceinline__ void euler_tile_multi(const Geom &g, const int tile, 
         cur ^= 1;
     }
     // the tile's own cells
-    for (int e = threadIdx.x; e < TT_X * TT_Y; e += blockDim.x) {
-        const int lx = EH + e % TT_X, ly = EH + e / TT_X;
-        const int gx = x0 + e % TT_X, gy = y0 + e / TT_X;
+    for (int e = threadIdx.x; e < EX * EY; e += blockDim.x) {
+        const int lx = EH + e % EX, ly = EH + e / EX;
+        const int gx = x0 + e % EX, gy = y0 + e / EX;
         if (gx >= nx || gy >= ny) continue;
         const int r = ly * ERX + lx;
 #pragma unroll

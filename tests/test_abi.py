@@ -131,7 +131,8 @@ def test_plan_create_rejects_bad_options():
     assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 2)) == -1
     assert create(opt=rpr.rpr_options(0, 3, 0, 0, 0, 0, 0, 0)) == -1
     assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 0, -1, 0)) == -1  # chain_wgs
-    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 0, 0, 1)) == -1  # reserved
+    assert create(opt=rpr.rpr_options(0, 0, 0, 0, 0, 0, 0, 0, 0, 3)) == -1  # sweep_form
+    assert "sweep_form" in rpr.last_error()
     # nearest-neighbour correction: 1 <= m_nn <= 32, reserved field zero
     nn = rpr.rpr_options(0, rpr.RPR_CORR_RANDNET_NN, 0, 0, 0, 0, 0, 0)
     assert create(net_=rpr.rpr_randnet(10, 0, 1e-6, 0.0, 0, 0), opt=nn) == -1

@@ -144,9 +144,11 @@ def test_bruss3d_reduced_precision_within_tau(orc):
     assert E_err(Ug, Uf) <= E_err(Uo, Uf) + tau
 
 
-def test_bruss3d_captured_sweep_equals_cooperative_sweep():
+@pytest.mark.parametrize("form", ["graph", "segments"])
+def test_bruss3d_sweep_forms_equal_the_cooperative_sweep(form):
     w = BRUSS3D_SMALL
-    Ue, ie = gpu_solve3(w)
-    Ug, ig = gpu_solve3(w, graph=1, poll_every=2)
+    Ue, ie = gpu_solve3(w, sweep_form=1)
+    opt = dict(graph=1, poll_every=2) if form == "graph" else dict(sweep_form=2)
+    Ug, ig = gpu_solve3(w, **opt)
     assert ie["K"] == ig["K"]
     np.testing.assert_array_equal(Ug, Ue)

@@ -244,10 +244,21 @@ def test_captured_sweep_segments_equal_the_cooperative_sweep(name, w, corr, prec
     # on the same grid: same decisions, same values, bit for bit (global fit,
     # nearest-neighbour refit; on chip and tiled coarse solvers, forward
     # Euler in passes of 8 steps and RK4 one pass per stage)
-    Ue, ie = gpu_solve(w, corr=corr, prec=prec)
+    Ue, ie = gpu_solve(w, corr=corr, prec=prec, sweep_form=1)
     Ug, ig = gpu_solve(w, corr=corr, prec=prec, graph=1, poll_every=2)
     assert ie["K"] == ig["K"] and ie["L_hist"].tolist() == ig["L_hist"].tolist()
     np.testing.assert_array_equal(Ug, Ue)
+
+
+@pytest.mark.parametrize("name,w,corr,prec", GRAPH_EQ, ids=[c[0] for c in GRAPH_EQ])
+def test_sweep_as_segment_kernels_equals_the_cooperative_sweep(name, w, corr, prec):
+    # without capture, the sweep as one kernel per segment (and the k = 0
+    # sweep of a tiled coarse solver as one kernel per pass) against one
+    # cooperative kernel: bit for bit
+    Uc, ic = gpu_solve(w, corr=corr, prec=prec, sweep_form=1)
+    Us, is_ = gpu_solve(w, corr=corr, prec=prec, sweep_form=2)
+    assert ic["K"] == is_["K"] and ic["L_hist"].tolist() == is_["L_hist"].tolist()
+    np.testing.assert_array_equal(Us, Uc)
 
 
 def test_state_too_large_for_one_work_group_is_solved_tiled(orc):
