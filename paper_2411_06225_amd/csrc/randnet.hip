@@ -2,23 +2,30 @@
 // (eq. "ridgeless"), in double precision.
 //
 //   features : Phi = sigma(X A^T / s + zeta)      split-K tiled GEMM + epilogue
-//   gram     : G += Phi^T Phi, B += Phi^T Y        over the finite rows only
+//   gram     : G += Phi^T Phi, B += Phi^T Y        over the finite rows only (matrix cores)
 //   cholesky : G + lambda I = L L^T                one work-group, pivot-checked
-//   solve    : W = L^-T L^-1 B                     column blocks of B in LDS
+//   solve    : W = L^-T L^-1 B                     column blocks of B in LDS, updates on
+//                                                   the matrix cores
 //   readout  : Yhat = Phi W
 // Every reduction runs in a fixed order (no floating-point atomics), so
 // results are bitwise reproducible run to run.
+#include <type_traits>
+
 #include "common.h"
+#include "mfma64.h"
 #include "randnet.h"
 
 namespace rpr {
 
 // ------------------------------------------------------------- features ---
-// Z = X A^T with X (n x d) and A (M x d) both K-contiguous.  Work-group tile:
-// 16 rows of X x 16 rows of A, K staged through LDS in chunks of 64; the K
-// range is split over gridDim.z into partial sums reduced in order later.
-// X rows may be FP64 or FP32 (the state precision); the product is FP64.
-constexpr int FT = 16, FK = 64;
+// Z = (X / s) A^T with X (n x d) and A (M x d) both K-contiguous, on the
+// matrix cores: a work-group takes 64 rows of X x 64 neurons, wavefront w
+// the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 tiles of 16 x 16, k in order,
+// 4 per product.  The K range is split over gridDim.z into partial sums
+// reduced in order later.  X rows may be FP64 or FP32 (the state
+// precision); the product is FP64.  Rows past the device row count and
+// neurons past M read as zero (clamped loads, masked after them).
+constexpr int FK = 64;  // K chunks are multiples of this
 
 template <typename TX>
 __global__ __launch_bounds__(256) void k_feat_partial(int n, int M, int d, int kchunk,
@@ -27,24 +34,75 @@ __global__ __launch_bounds__(256) void k_feat_partial(int n, int M, int d, int k
                                                       const int *__restrict__ nrows_dev)
 {
     const int nr = nrows_dev ? *nrows_dev : n;
-    const int r0 = blockIdx.x * FT, m0 = blockIdx.y * FT;
-    if (r0 >= nr) return;
+    if ((int)blockIdx.x * 64 >= nr) return;  // the whole work-group
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 64 + 32 * (w >> 1), m0 = blockIdx.y * 64 + 32 * (w & 1);
     const int k0 = blockIdx.z * kchunk, k1 = min(d, k0 + kchunk);
-    __shared__ double sx[FT][FK + 1], sa[FT][FK + 1];
-    const int tx = threadIdx.x % FT, ty = threadIdx.x / FT;  // output (ty, tx) = (row, neuron)
-    double acc = 0.0;
-    for (int kb = k0; kb < k1; kb += FK) {
-        for (int i = threadIdx.x; i < FT * FK; i += 256) {
-            const int rr = i / FK, kk = i % FK, k = kb + kk;
-            sx[rr][kk] = (r0 + rr < nr && k < k1) ? double(X[(size_t)(r0 + rr) * d + k]) * xs : 0.0;
-            sa[rr][kk] = (m0 + rr < M && k < k1) ? A[(size_t)(m0 + rr) * d + k] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 16
-        for (int kk = 0; kk < FK; ++kk) acc = fma(sx[ty][kk], sa[tx][kk], acc);
-        __syncthreads();
+    const int kq = lane >> 4, li = lane & 15;
+    const TX *xp[2];
+    const double *ap[2];
+    bool xok[2], aok[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = r0 + 16 * q + li, m = m0 + 16 * q + li;
+        xok[q] = r < nr;
+        aok[q] = m < M;
+        xp[q] = X + (size_t)(xok[q] ? r : nr - 1) * d;
+        ap[q] = A + (size_t)(aok[q] ? m : M - 1) * d;
     }
-    if (r0 + ty < nr && m0 + tx < M) part[((size_t)blockIdx.z * n + r0 + ty) * M + m0 + tx] = acc;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    auto product = [&](const double (&xv)[2], const double (&av)[2]) {
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mfma64(xv[ti], av[tj], acc[ti][tj]);
+    };
+    int k = k0;
+    for (; k + 16 <= k1; k += 16) {
+        double xv[4][2], av[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                xv[u][q] = double(xp[q][k + 4 * u + kq]);
+                av[u][q] = ap[q][k + 4 * u + kq];
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                xv[u][q] = xok[q] ? xv[u][q] * xs : 0.0;
+                av[u][q] = aok[q] ? av[u][q] : 0.0;
+            }
+            product(xv[u], av[u]);
+        }
+    }
+    for (; k < k1; k += 4) {
+        const int kk = k + kq;
+        const bool in = kk < k1;
+        const int kc = in ? kk : k;
+        double xv[2], av[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double x = double(xp[q][kc]), a = ap[q][kc];
+            xv[q] = in && xok[q] ? x * xs : 0.0;
+            av[q] = in && aok[q] ? a : 0.0;
+        }
+        product(xv, av);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + 16 * ti + mfma64_row(lane, e), m = m0 + 16 * tj + mfma64_col(lane);
+                if (r < nr && m < M) part[((size_t)blockIdx.z * n + r) * M + m] = acc[ti][tj][e];
+            }
 }
 
 __global__ void k_feat_finish(int n, int M, int nsplit, const double *__restrict__ part,
@@ -73,7 +131,7 @@ rpr_status launch_features(int n, int M, int d, int act, double inv_s, const dou
     if (n <= 0) return RPR_OK;
     const int ns = feat_splits(d);
     const int kchunk = ((d + ns - 1) / ns + FK - 1) / FK * FK;
-    dim3 grid((n + FT - 1) / FT, (M + FT - 1) / FT, ns);
+    dim3 grid((n + 63) / 64, (M + 63) / 64, ns);
     hipLaunchKernelGGL(k_feat_partial<TX>, grid, dim3(256), 0, st, n, M, d, kchunk, X, A, inv_s, part,
                        nrows_dev);
     RPR_HIP(hipGetLastError());
@@ -419,56 +477,93 @@ template rpr_status launch_features_bf16<double>(int, int, int, int, double, con
                                                  uint16_t *);
 
 // ----------------------------------------------------------- statistics ---
-// G[a][b] += sum_r ok_r Phi[r][a] Phi[r][b]; rows in order r = 0..n-1.
-__global__ __launch_bounds__(256) void k_gram(int n, int M, const double *__restrict__ Phi,
-                                              const int *__restrict__ ok, double *__restrict__ G,
-                                              const int *__restrict__ nrows_dev)
-{
-    const int nr = nrows_dev ? *nrows_dev : n;
-    const int a = blockIdx.y * 16 + threadIdx.x / 16, b = blockIdx.x * 16 + threadIdx.x % 16;
-    if (a >= M || b >= M) return;
-    double acc = 0.0;
-    for (int r = 0; r < nr; ++r)
-        if (ok == nullptr || ok[r]) acc = fma(Phi[(size_t)r * M + a], Phi[(size_t)r * M + b], acc);
-    G[(size_t)a * M + b] += acc;
-}
-
-// B[a][j] += sum_r ok_r Phi[r][a] Y[r][j]: a block of 16 neurons x 256 columns;
-// the 16 Phi columns of the block are staged in LDS, BSTAT_ROWS rows at a
-// time (any row count; rows are summed in order).
-constexpr int BSTAT_ROWS = 256;
+// S[a][j] += sum_r ok_r Phi[r][a] Y[r][j] (B = Phi^T Y with Y the targets,
+// and the Gram matrix G = Phi^T Phi with Y = Phi) on the matrix cores: a
+// work-group takes 64 neurons x 64 columns, wavefront w the 32 x 32 quarter
+// (w / 2, w % 2) as 2 x 2 tiles of 16 x 16; the rows r in order, 4 per
+// product.  Rows with ok_r = 0 (dropped pairs) contribute nothing whatever
+// they hold: their values are replaced by zero, not multiplied by it.
+// Loads go to clamped in-range addresses and the masks are applied after
+// them, so that the loads of a batch are in flight together.
 template <typename TY>
-__global__ __launch_bounds__(256) void k_bstat(int n, int M, int d, const double *__restrict__ Phi,
-                                               const TY *__restrict__ Y, const int *__restrict__ ok,
-                                               double *__restrict__ Bm, const int *__restrict__ nrows_dev)
+__global__ __launch_bounds__(256) void k_stat(int n, int M, int d, const double *__restrict__ Phi,
+                                              const TY *__restrict__ Y, const int *__restrict__ ok,
+                                              double *__restrict__ S, const int *__restrict__ nrows_dev)
 {
     const int nr = nrows_dev ? *nrows_dev : n;
-    const int a0 = blockIdx.y * 16, j = blockIdx.x * 256 + threadIdx.x;
-    __shared__ double sphi[BSTAT_ROWS * 16];
-    double acc[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a0 = blockIdx.y * 64 + 32 * (w >> 1), j0 = blockIdx.x * 64 + 32 * (w & 1);
+    const int kq = lane >> 4, li = lane & 15;
+    int ac[2], bc[2];
+    bool aok[2], bok[2];
 #pragma unroll
-    for (int aa = 0; aa < 16; ++aa) acc[aa] = 0.0;
-    for (int r0 = 0; r0 < nr; r0 += BSTAT_ROWS) {
-        const int rn = min(BSTAT_ROWS, nr - r0);
-        __syncthreads();  // the previous chunk's reads are done
-        for (int i = threadIdx.x; i < rn * 16; i += 256) {
-            const int r = r0 + i / 16, aa = i % 16;
-            const bool use = (ok == nullptr || ok[r]) && a0 + aa < M;
-            sphi[i] = use ? Phi[(size_t)r * M + a0 + aa] : 0.0;
-        }
-        __syncthreads();
-        if (j < d) {
-            for (int r = 0; r < rn; ++r) {
-                const double yv = (ok == nullptr || ok[r0 + r]) ? double(Y[(size_t)(r0 + r) * d + j]) : 0.0;
+    for (int q = 0; q < 2; ++q) {
+        ac[q] = a0 + 16 * q + li;
+        bc[q] = j0 + 16 * q + li;
+        aok[q] = ac[q] < M;
+        bok[q] = bc[q] < d;
+        ac[q] = aok[q] ? ac[q] : M - 1;
+        bc[q] = bok[q] ? bc[q] : d - 1;
+    }
+    dbl4 acc[2][2];
 #pragma unroll
-                for (int aa = 0; aa < 16; ++aa) acc[aa] = fma(sphi[r * 16 + aa], yv, acc[aa]);
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    auto product = [&](const double (&av)[2], const double (&bv)[2]) {
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mfma64(av[ti], bv[tj], acc[ti][tj]);
+    };
+    int r = 0;
+    for (; r + 16 <= nr; r += 16) {
+        double av[4][2], bv[4][2];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int rr = r + 4 * u + kq;
+            use[u] = ok == nullptr || ok[rr] != 0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                av[u][q] = Phi[(size_t)rr * M + ac[q]];
+                bv[u][q] = double(Y[(size_t)rr * d + bc[q]]);
             }
         }
-    }
-    if (j >= d) return;
 #pragma unroll
-    for (int aa = 0; aa < 16; ++aa)
-        if (a0 + aa < M) Bm[(size_t)(a0 + aa) * d + j] += acc[aa];
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                av[u][q] = use[u] && aok[q] ? av[u][q] : 0.0;
+                bv[u][q] = use[u] && bok[q] ? bv[u][q] : 0.0;
+            }
+            product(av[u], bv[u]);
+        }
+    }
+    for (; r < nr; r += 4) {
+        const int rr = r + kq;
+        const bool in = rr < nr;
+        const int rc = in ? rr : r;
+        const bool use = in && (ok == nullptr || ok[rc] != 0);
+        double av[2], bv[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double x = Phi[(size_t)rc * M + ac[q]];
+            const double y = double(Y[(size_t)rc * d + bc[q]]);
+            av[q] = use && aok[q] ? x : 0.0;
+            bv[q] = use && bok[q] ? y : 0.0;
+        }
+        product(av, bv);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int a = a0 + 16 * ti + mfma64_row(lane, e), j = j0 + 16 * tj + mfma64_col(lane);
+                if (a < M && j < d) S[(size_t)a * d + j] += acc[ti][tj][e];
+            }
 }
 
 template <typename TY>
@@ -476,11 +571,11 @@ rpr_status launch_stats(int n, int M, int d, const double *Phi, const TY *Y, con
                         double *Bm, const int *nrows_dev, hipStream_t st)
 {
     if (n <= 0) return RPR_OK;
-    hipLaunchKernelGGL(k_gram, dim3((M + 15) / 16, (M + 15) / 16), dim3(256), 0, st, n, M, Phi, ok, G,
-                       nrows_dev);
+    hipLaunchKernelGGL(k_stat<double>, dim3((M + 63) / 64, (M + 63) / 64), dim3(256), 0, st, n, M, M, Phi, Phi, ok,
+                       G, nrows_dev);
     RPR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_bstat<TY>, dim3((d + 255) / 256, (M + 15) / 16), dim3(256), 0, st, n, M, d, Phi,
-                       Y, ok, Bm, nrows_dev);
+    hipLaunchKernelGGL(k_stat<TY>, dim3((d + 63) / 64, (M + 63) / 64), dim3(256), 0, st, n, M, d, Phi, Y, ok, Bm,
+                       nrows_dev);
     RPR_HIP(hipGetLastError());
     return RPR_OK;
 }
@@ -628,37 +723,37 @@ __global__ __launch_bounds__(1024) void k_cholesky(int M, const double *__restri
 // W = (L L^T)^{-1} B = L^-T L^-1 B for a block of 32 columns of B per
 // work-group of 256 threads.  Block forward then backward substitution over
 // 32-row blocks: each block first subtracts the product with the rows already
-// solved (column c = t % 32, rows g + 8 i, i < 4, for g = t / 32; the rows
-// of L or L^T read from memory, shared by the 32 lanes of a column group),
-// then is solved against its
-// diagonal block by substitution along the 32 lanes of a half-wavefront
-// (lane = row; each half-wavefront takes 4 columns).  The M x 32 block of B
-// stays in LDS.  If the factorisation failed (*fail), W is set to zero.
+// solved (a 32 x 32 product over those rows on the matrix cores, one 16 x 16
+// tile per wavefront), then is solved against its diagonal block by
+// substitution along the 32 lanes of a half-wavefront (lane = row; each
+// half-wavefront takes 4 columns).  The M x 32 block of B stays in LDS.  If
+// the factorisation failed (*fail), W is set to zero.
 __global__ __launch_bounds__(256) void k_trsm(int M, int d, const double *__restrict__ L,
                                               const double *__restrict__ Lt, const double *__restrict__ Bm,
                                               double *__restrict__ W, const int *__restrict__ fail,
                                               const int *__restrict__ done)
 {
     if (done && *done) return;
-    extern __shared__ double Y[];  // M x 32, then the 32 x 33 staging tile
-    double *T = Y + (size_t)M * CB;
+    extern __shared__ double Y[];  // M x 32
     const int t = threadIdx.x, c = t % CB, g = t / CB;
     const int j0 = blockIdx.x * CB;
     const bool failed = fail && *fail;
-    for (int i = t; i < M * CB; i += 256) {
-        const int r = i / CB, cc = i % CB;
-        Y[i] = (!failed && j0 + cc < d) ? Bm[(size_t)r * d + j0 + cc] : 0.0;
+    {
+        // thread t fills column t % 32 of the block, rows t / 32 + 8 i, in
+        // batches of 8 loads in flight (clamped addresses, masked after)
+        const int cc = t % CB;
+        const bool colok = !failed && j0 + cc < d;
+        const double *bp = Bm + (colok ? j0 + cc : 0);
+        for (int r = t / CB; r < M; r += 64) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = bp[(size_t)min(r + 8 * u, M - 1) * d];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (r + 8 * u < M) Y[(r + 8 * u) * CB + cc] = colok ? v[u] : 0.0;
+        }
     }
     const int nblk = (M + CB - 1) / CB;
-    // T[rr][p] = src[(r0 + rr) M + pc + p] for rr < rows left, p < pw, else 0
-    auto stage = [&](const double *src, int r0, int pc, int pw) {
-        __syncthreads();
-        for (int e = t; e < CB * CB; e += 256) {
-            const int rr = e / CB, p = e % CB;
-            T[rr * (CB + 1) + p] = (r0 + rr < M && p < pw) ? src[(size_t)(r0 + rr) * M + pc + p] : 0.0;
-        }
-        __syncthreads();
-    };
     if (!failed) {
         for (int pass = 0; pass < 2; ++pass) {
             const bool fwd = pass == 0;
@@ -668,61 +763,81 @@ __global__ __launch_bounds__(256) void k_trsm(int M, int d, const double *__rest
                 // rows already solved: forward rows 0 .. r0 of L, backward rows
                 // r0+32 .. M of L^T (the columns below the block)
                 __syncthreads();  // the previous block's rows of Y are final
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                // Y[block] -= src[block rows][p_lo, p_hi) Y[p_lo, p_hi) on the
+                // matrix cores: wavefront w takes the 16 x 16 tile (rows
+                // 16 (w / 2), columns 16 (w % 2)) of the 32 x 32 block, the
+                // rows of L (or L^T) from memory, the solved rows of Y from
+                // LDS, 4 k per product in order
                 const int p_lo = fwd ? 0 : r0 + CB, p_hi = fwd ? r0 : M;
                 const double *src = fwd ? L : Lt;
-                const double *Lr[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = min(r0 + g + 8 * i, M - 1);  // rows past M compute unused sums
-                    Lr[i] = src + (size_t)r * M;
-                }
-                // batches of 8 columns: 32 independent loads in flight per thread
+                const int lane = t & 63, w = t >> 6, ti = w >> 1, tj = w & 1;
+                const int ar = r0 + 16 * ti + (lane & 15);  // this lane's row of the A tile
+                const bool arow_ok = ar < M;                // rows past M read as zero
+                const double *arow = src + (size_t)(arow_ok ? ar : M - 1) * M;
+                const int kq = lane >> 4, bc = 16 * tj + (lane & 15);
+                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
                 int p = p_lo;
-                for (; p + 8 <= p_hi; p += 8) {
-                    double lv[4][8];
+                for (; p + 16 <= p_hi; p += 16) {
+                    double av[4], bv[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) lv[i][u] = Lr[i][p + u];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const double y = Y[(p + u) * CB + c];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) acc[i] = fma(lv[i][u], y, acc[i]);
+                    for (int u = 0; u < 4; ++u) {
+                        const int pp = p + 4 * u + kq;
+                        av[u] = arow[pp];
+                        bv[u] = Y[pp * CB + bc];
                     }
-                }
-                for (; p < p_hi; ++p) {
-                    const double y = Y[p * CB + c];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[i] = fma(Lr[i][p], y, acc[i]);
+                    for (int u = 0; u < 4; ++u) acc = mfma64(arow_ok ? av[u] : 0.0, bv[u], acc);
+                }
+                for (; p < p_hi; p += 4) {
+                    const int pp = p + kq;
+                    const bool in = pp < p_hi;
+                    const double av = arow[in ? pp : p_lo];
+                    const double bv = Y[(in ? pp : p_lo) * CB + bc];
+                    acc = mfma64(arow_ok && in ? av : 0.0, in ? bv : 0.0, acc);
                 }
                 __syncthreads();
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + g + 8 * i;
-                    if (r < M) Y[r * CB + c] -= acc[i];
+                for (int e = 0; e < 4; ++e) {
+                    const int r = r0 + 16 * ti + mfma64_row(lane, e);
+                    if (r < M) Y[r * CB + 16 * tj + mfma64_col(lane)] -= acc[e];
                 }
-                // the diagonal block of L (lower triangle)
-                stage(L, r0, r0, rb);
+                // the diagonal block of L in registers: lane rr holds row rr of
+                // it (forward: L[r0 + rr][r0 + jj]) or column rr (backward:
+                // L[r0 + jj][r0 + rr]), the 32 loads in flight together
                 const int rr = c;  // lane within the half-wavefront = row of the block
-                const double rinv = rr < rb ? 1.0 / T[rr * (CB + 1) + rr] : 0.0;
+                double lw[CB];
+#pragma unroll
+                for (int jj = 0; jj < CB; ++jj) {
+                    const int ra = min(r0 + (fwd ? rr : jj), M - 1), cb = min(r0 + (fwd ? jj : rr), M - 1);
+                    lw[jj] = L[(size_t)ra * M + cb];
+                }
+                const double dg = L[(size_t)min(r0 + rr, M - 1) * (M + 1)];
+                const double rinv = rr < rb ? 1.0 / dg : 0.0;
                 double z[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) z[i] = rr < rb ? Y[(r0 + rr) * CB + g + 8 * i] : 0.0;
-                for (int s = 0; s < rb; ++s) {
-                    const int jj = fwd ? s : rb - 1 - s;
-                    // forward: x_jj = z_jj / L[jj][jj], then z_rr -= L[rr][jj] x_jj (rr > jj);
-                    // backward: z_rr -= L[jj][rr] x_jj (rr < jj)
-                    const bool upd = fwd ? (rr > jj && rr < rb) : rr < jj;
-                    const double lw = upd ? (fwd ? T[rr * (CB + 1) + jj] : T[jj * (CB + 1) + rr]) : 0.0;
+                // forward: x_jj = z_jj / L[jj][jj], then z_rr -= L[rr][jj] x_jj
+                // (rr > jj), jj = 0 .. rb - 1; backward: z_rr -= L[jj][rr] x_jj
+                // (rr < jj), jj = rb - 1 .. 0.  Unrolled over the 32 positions
+                // (those past rb skipped) so that lw is indexed by constants.
+                auto substitute = [&](auto fwd_tag) {
+                    constexpr bool FWD = decltype(fwd_tag)::value;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (rr == jj) z[i] *= rinv;
-                        const double xb = __shfl(z[i], jj, CB);
-                        if (upd) z[i] = fma(-lw, xb, z[i]);
+                    for (int s2 = 0; s2 < CB; ++s2) {
+                        const int jj = FWD ? s2 : CB - 1 - s2;
+                        if (jj >= rb) continue;  // uniform
+                        const bool upd = FWD ? (rr > jj && rr < rb) : rr < jj;
+                        const double l = upd ? lw[jj] : 0.0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (rr == jj) z[i] *= rinv;
+                            const double xb = __shfl(z[i], jj, CB);
+                            if (upd) z[i] = fma(-l, xb, z[i]);
+                        }
                     }
-                }
+                };
+                if (fwd) substitute(std::true_type{});
+                else substitute(std::false_type{});
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     if (rr < rb) Y[(r0 + rr) * CB + g + 8 * i] = z[i];
@@ -752,7 +867,7 @@ rpr_status launch_ridge_solve(int M, int d, const double *G, double lambda, doub
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CB * CB), top_lds, st, M, G, lambda, L, Lt, fail, fail_count,
                        done);
     RPR_HIP(hipGetLastError());
-    const size_t lds = ((size_t)M * CB + CB * (CB + 1)) * sizeof(double);
+    const size_t lds = (size_t)M * CB * sizeof(double);
     if (lds > kMaxLds) return rpr::fail(RPR_ERR_UNSUPPORTED, "ridge solve: M too large for LDS block");
     static bool attr_set = false;
     if (!attr_set) {
