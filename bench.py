@@ -25,14 +25,17 @@ timed on the host cores.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
                     [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128]
-                    [--solve-only NAME] [--gemm] [--robustness]
+                    [--solve-only NAME] [--gemm] [--robustness] [--model-only]
+                    [--trace-summary KERNEL_TRACE_CSV]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
 (Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems),
 which takes minutes.  --copy-calibration runs a device copy of 256 MiB, the
 reference a hardware-counter run uses to scale its byte counters.  --f-only
 times only the fine propagator of the named workload (all N slot states,
---steps RK4 steps, FP64 and FP32) and prints its roofline, for counter runs.
+--steps RK4 steps, FP64 and FP32) and prints its roofline, for counter runs;
+--model-only times the model phase's FP64 matrix products (features, ridge
+fit) at the shallow-water shape, for counter runs.
 """
 from __future__ import annotations
 
@@ -75,8 +78,10 @@ ALGO_BYTES_PER_DOF_STEP = {8: 16, 4: 8}
 # they were taken on (hash below); any change to them makes the field null
 # until the counters are taken again.
 PROP_SOURCES = ("paper_2411_06225_amd/csrc/swefused.h", "paper_2411_06225_amd/csrc/tiled.hip",
-                "paper_2411_06225_amd/csrc/slotprop.h", "paper_2411_06225_amd/csrc/common.h")
-PROP_TRAFFIC = {"sources": None, "fetch_kib": None, "fetch_scale": None, "write_kib": None, "write_scale": None}
+                "paper_2411_06225_amd/csrc/tiledprop.h", "paper_2411_06225_amd/csrc/slotprop.h",
+                "paper_2411_06225_amd/csrc/common.h")
+PROP_TRAFFIC = {"sources": "22cd509a3460e719", "fetch_kib": 110684.8, "fetch_scale": 2.0, "write_kib": 221324.8,
+                "write_scale": 1.0}
 
 
 def sources_hash(paths):
@@ -109,6 +114,11 @@ def parse():
                     help="only run the sweep over neighbour counts, neurons and weight draws (App. D)")
     ap.add_argument("--f-only", choices=["swe_192x192", "bruss_128x128"], default=None,
                     help="only time the fine propagator of this workload in FP64 and FP32 (for counter runs)")
+    ap.add_argument("--trace-summary", metavar="CSV", default=None,
+                    help="summarise a rocprofv3 kernel trace (CSV) per kernel and grid size, then exit")
+    ap.add_argument("--model-only", action="store_true",
+                    help="only time the model phase's FP64 matrix products at the shallow-water shape "
+                         "(for counter runs)")
     return ap.parse_args()
 
 
@@ -116,8 +126,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def trace_summary(path, top=25):
+    """Per kernel name and grid size of a rocprofv3 kernel trace: dispatches,
+    mean and spread of the duration (the launches of one kernel over slot
+    batches of different sizes have different grids, so a plan's launches
+    and single-state ones are told apart)."""
+    import csv
+    from collections import defaultdict
+    groups = defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            if "Grid_Size" in r:
+                grid = int(r["Grid_Size"])
+            else:
+                grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            groups[(r["Kernel_Name"], grid)].append(dur)
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]
+    print("| kernel | grid (threads) | dispatches | mean us | min us | max us | total ms |")
+    print("|---|---|---|---|---|---|---|")
+    for (name, grid), v in rows:
+        short = name.split("(")[0].replace("void ", "")
+        print(f"| `{short}` | {grid} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | {min(v) / 1e3:.2f} | "
+              f"{max(v) / 1e3:.2f} | {sum(v) / 1e6:.3f} |")
+
+
 def main():
     args = parse()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
@@ -136,6 +174,9 @@ def main():
         return
     if args.robustness:
         print(json.dumps({"robustness": robustness_sweep(torch, rpr, W, dev)}))
+        return
+    if args.model_only:
+        print(json.dumps({"model_fp64": model_roofline(torch, rpr, W, dev, reps=max(args.steps, 1))}))
         return
     if args.f_only:
         wf = W.WORKLOADS[args.f_only]
@@ -482,6 +523,50 @@ def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
 
 
 BF16_MFMA_PEAK = 2.5e15  # MI355X dense bf16 matrix FLOP/s (AMD specification)
+FP64_MFMA_PEAK = 78.6e12  # MI355X dense FP64 matrix FLOP/s (AMD specification)
+
+
+def model_roofline(torch, rpr, W, dev, reps=5):
+    """The model phase's FP64 matrix products at the shallow-water 192 x 192
+    shape (n = N = 256 training rows, M = 300 neurons, d = 110592): the
+    feature GEMM Phi = sigma(X A^T / s + zeta) (rpr_randnet_features, 2 n M d
+    FLOP) and the ridge fit (rpr_ridge_fit: Gram 2 n M^2, B = Phi^T Y 2 n M d,
+    Cholesky M^3 / 3 and the two triangular solves 2 M^2 d FLOP), each
+    timed over `reps` calls with HIP events and related to the FP64
+    matrix-core peak on those algorithmic FLOP.  Whole calls: workspace
+    allocation and the one-work-group Cholesky are included (the kernels'
+    own times are in the profiles)."""
+    w = W.SWE_192
+    n, M, d = w.N, w.M, w.d
+    g = torch.Generator(device="cpu").manual_seed(n + M + d)
+    A = (torch.rand((M, d), generator=g, dtype=torch.float64) * 2 - 1).to(dev)
+    z = (torch.rand((M,), generator=g, dtype=torch.float64) * 2 - 1).to(dev)
+    X = (torch.rand((n, d), generator=g, dtype=torch.float64) * 2).to(dev)
+    Y = (torch.randn((n, d), generator=g, dtype=torch.float64) * 1e-3).to(dev)
+    Phi = torch.empty((n, M), dtype=torch.float64, device=dev)
+    Wt = torch.empty((M, d), dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / 1e3 / reps
+
+    t_feat = timed(lambda: rpr.rpr_randnet_features(M, d, n, rpr.RPR_RELU, 2.0, A, z, X, Phi))
+    t_fit = timed(lambda: rpr.rpr_ridge_fit(M, d, n, Phi, Y, w.lam, Wt))
+    f_feat = 2.0 * n * M * d
+    f_fit = 2.0 * n * M * M + 2.0 * n * M * d + M ** 3 / 3.0 + 2.0 * M * M * d
+    out = {"shape": {"n": n, "M": M, "d": d},
+           "features": {"ms": t_feat * 1e3, "TFLOPs": f_feat / t_feat / 1e12,
+                        "frac_of_fp64_mfma_peak": f_feat / t_feat / FP64_MFMA_PEAK},
+           "ridge_fit": {"ms": t_fit * 1e3, "TFLOPs": f_fit / t_fit / 1e12,
+                         "frac_of_fp64_mfma_peak": f_fit / t_fit / FP64_MFMA_PEAK}}
+    log(f"model shapes: features {t_feat * 1e3:.3f} ms, ridge fit {t_fit * 1e3:.3f} ms")
+    return out
 
 
 def gemm_demo(torch, rpr, dev, reps=5):

@@ -90,6 +90,18 @@ __device__ __forceinline__ T swf_sqrt(T v)
     else return sqrt(v);
 }
 
+// The larger of two wave speeds.  Speeds are |velocity| + sqrt(g h) >= +0
+// (or NaN), and for such values the IEEE order is the integer order of the
+// bit patterns: single precision takes one integer max (fmax would first
+// quiet operands that come from lane moves or LDS, one more instruction
+// each); a NaN speed wins either way.
+template <typename T>
+__device__ __forceinline__ T swf_smax(T a, T b)
+{
+    if constexpr (sizeof(T) == 4) return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+    else return fmax(a, b);
+}
+
 // Twice the Rusanov flux across one face between left state (h, m = normal
 // momentum, q = tangential momentum, f = m^2/h + g h^2/2, e = q m/h,
 // s = |m/h| + sqrt(g h)) and right state: (mass, normal, tangential)
@@ -100,7 +112,7 @@ template <typename T>
 __device__ __forceinline__ void swf_face(T hL, T mL, T qL, T fL, T eL, T sL, T hR, T mR, T qR, T fR, T eR, T sR,
                                          T &Fh, T &Fm, T &Fq)
 {
-    const T a = fmax(sL, sR);
+    const T a = swf_smax(sL, sR);
     Fh = (mL + mR) - a * (hR - hL);
     Fm = (fL + fR) - a * (mR - mL);
     Fq = (eL + eR) - a * (qR - qL);
@@ -122,9 +134,13 @@ __device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, cons
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int tx = tile % swf_tiles_x(g), ty = tile / swf_tiles_x(g);
     const int x0 = tx * SWF_X, y0 = ty * S::TY;
-    // flux-difference factors with the flux's 1/2 folded in (swf_face)
-    const T gg = T(g.p[0]), idx = T(0.5 * g.idx), idy = T(0.5 * g.idy), half = T(0.5);
-    const T dtT = T(dt), hdt = T(0.5 * dt), dt6 = T(dt / 6.0);
+    // the slope of a cell is -idx (dF + rho dG) with dF, dG its x and y
+    // flux differences (twice the fluxes, swf_face: the 1/2 sits in idx),
+    // rho = dy^-1 / dx^-1 (1 on square cells); the stages accumulate
+    // s = dF + rho dG and take the factor -idx in their weights
+    const T gg = T(g.p[0]), half = T(0.5), rho = T(g.idy / g.idx);
+    const double nidx = -0.5 * g.idx;
+    const T c_half = T(0.5 * dt * nidx), c_full = T(dt * nidx), c_sixth = T(dt / 6.0 * nidx);
 
     // ---- load: the region with mirror ghosts beyond the walls
     bool fx;
@@ -172,11 +188,12 @@ __device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, cons
             const T h = y[q][0], m = y[q][1], n = y[q][2];
             const T rh = swf_rcp(h);
             const T vx = m * rh, vy = n * rh, c = swf_sqrt(gg * h), P = half * gg * h * h;
+            const T e = n * vx;  // hu hv / h: the tangential flux term of both directions
             xf[q] = m * vx + P;
-            xe[q] = n * vx;
+            xe[q] = e;
             xs[q] = fabs(vx) + c;
             yf[q] = n * vy + P;
-            ye[q] = m * vy;
+            ye[q] = e;
             ys[q] = fabs(vy) + c;
         }
         // edge rows to LDS: [wave][row 0 | row R-1][h, m, n, yf, ye, ys][lane]
@@ -231,23 +248,23 @@ __device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, cons
             const T dh = Fh - lane_neighbour<true, true>(Fh);
             const T dm = Fm - lane_neighbour<true, true>(Fm);
             const T dn = Fn - lane_neighbour<true, true>(Fn);
-            T k[3];
-            k[0] = -dh * idx - (Gh[q + 1] - Gh[q]) * idy;
-            k[1] = -dm * idx - (Gu[q + 1] - Gu[q]) * idy;
-            k[2] = -dn * idx - (Gv[q + 1] - Gv[q]) * idy;
+            T k[3];  // the slopes divided by -idx
+            k[0] = fma(rho, Gh[q + 1] - Gh[q], dh);
+            k[1] = fma(rho, Gu[q + 1] - Gu[q], dm);
+            k[2] = fma(rho, Gv[q + 1] - Gv[q], dn);
 #pragma unroll
             for (int sp = 0; sp < 3; ++sp) {
                 if (s == 1) {
                     acc[q][sp] = k[sp];
-                    y[q][sp] = u[q][sp] + hdt * k[sp];
+                    y[q][sp] = fma(c_half, k[sp], u[q][sp]);
                 } else if (s == 2) {
-                    acc[q][sp] = acc[q][sp] + T(2) * k[sp];
-                    y[q][sp] = u[q][sp] + hdt * k[sp];
+                    acc[q][sp] = fma(T(2), k[sp], acc[q][sp]);
+                    y[q][sp] = fma(c_half, k[sp], u[q][sp]);
                 } else if (s == 3) {
-                    acc[q][sp] = acc[q][sp] + T(2) * k[sp];
-                    y[q][sp] = u[q][sp] + dtT * k[sp];
+                    acc[q][sp] = fma(T(2), k[sp], acc[q][sp]);
+                    y[q][sp] = fma(c_full, k[sp], u[q][sp]);
                 } else {
-                    const T inc = dt6 * (acc[q][sp] + k[sp]);
+                    const T inc = c_sixth * (acc[q][sp] + k[sp]);
                     if constexpr (KAHAN) {
                         const T yk = inc - cm[q][sp];
                         const T un = u[q][sp] + yk;
