@@ -427,15 +427,15 @@ def cpu_baseline(w, u0h, T, K64, k64):
     threads = cpus["threads"]
     pb = oracle.problem(w.kind, w.nx, w.ny, w.domain, w.params)
     dtF, dtG = T / w.F[1], T / w.G[1]
-    # all threads: one slot each, 250 RK4 steps
-    steps_all = 250
+    # all threads: one slot each, 1500 RK4 steps (about 7 s)
+    steps_all = 1500
     X = np.tile(u0h, (threads, 1))
     t0 = time.perf_counter()
     oracle.propagate_many(pb, w.F[0], steps_all, dtF, X, nthreads=threads)
     t_all = time.perf_counter() - t0
     rate_all = threads * steps_all / t_all
-    # one thread: one slot, 100 RK4 steps
-    steps_one = 100
+    # one thread: one slot, 1000 RK4 steps (about 5 s)
+    steps_one = 1000
     t0 = time.perf_counter()
     oracle.propagate(pb, w.F[0], steps_one, dtF, u0h)
     t_one = time.perf_counter() - t0
