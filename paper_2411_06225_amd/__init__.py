@@ -340,7 +340,7 @@ class BatchPlan:
 
     def __init__(self, problems, *, tol=1e-6, precision: int = RPR_FP64, correction: int = RPR_CORR_RANDNET,
                  k_max: int = 0, poll_every: int = 0, features: int = RPR_FEAT_AUTO, seed: int = 0, graph: int = 0,
-                 stability: int = 0):
+                 stability: int = 0, autotune: int = 0):
         """problems: list of dicts with keys h, d, t0, tN, N, F, G, M, activation, lam, A, zeta
         (and m_nn for RPR_CORR_RANDNET_NN, default 4)."""
         import numpy as np
@@ -370,8 +370,8 @@ class BatchPlan:
                 z = np.ascontiguousarray(q["zeta"], dtype=np.float64)
                 self._keep += [a, z]
                 Ap[b], Zp[b] = a.ctypes.data, z.ctypes.data
-        opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features), 0, int(graph),
-                          int(stability), 0, 0)
+        opt = rpr_options(int(precision), int(correction), int(k_max), int(poll_every), int(features), int(autotune),
+                          int(graph), int(stability), 0, 0)
         self._handle = C.c_void_p()
         _live.add(self)
         check(lib().rpr_plan_create_batch(C.byref(self._handle), n, H, D, T0, TN, NN, F, G, TOL, NET,

@@ -293,3 +293,85 @@ rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus)
 
 template rpr_status autotune_plan<double>(rpr_plan *, int, int);
 template rpr_status autotune_plan<float>(rpr_plan *, int, int);
+
+// ------------------------------------------------------- batch autotuner --
+// The persistent fine-solve launch of a batch takes the next (instance, slot)
+// item from a counter until the list is done; how many work-groups to launch
+// (1 to 4 per CU) is timed on the batch's own buffers, zero-filled, with at
+// most 32 steps per item, and kept per shape class of the batch (rhs, largest
+// grid, precision, strip length, item count).  The chains have one shape per
+// batch (one work-group per instance), so nothing else is left to choose.
+template <typename T>
+static rpr_status autotune_batch_run(rpr_plan *p, int cus, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    const int n = (int)p->sub.size();
+    std::ostringstream key;
+    key << "batch:" << p->bgmax.kind << ":" << p->bgmax.nx << "x" << p->bgmax.ny << ":" << p->esz << ":cpt"
+        << p->bshF.cpt << ":items" << p->bn_items;
+    const std::string kg = key.str() + ":grid";
+    if (g_tune.count(kg) == 0) {
+        std::vector<BatchInst<T>> hi(n);
+        for (int b = 0; b < n; ++b) {
+            rpr_plan *q = p->sub[b];
+            RPR_TRY(zero(static_cast<T *>(q->U), (size_t)(q->N + 1) * q->g.d, st));
+            RPR_TRY(zero(static_cast<T *>(q->Fv), (size_t)(q->N + 1) * q->g.d, st));
+            RPR_TRY(launch_init_ctrl(q->ctrl, q->L_hist, q->chg_hist, st));
+            hi[b] = BatchInst<T>{q->g, q->F.method, (long long)std::min<int64_t>(q->F.steps, 32), q->dtF,
+                                 static_cast<const T *>(q->U), static_cast<T *>(q->Fv),
+                                 reinterpret_cast<const int *>(q->ctrl)};
+        }
+        DevBuf ti;
+        RPR_HIP(hipMalloc(&ti.p, sizeof(BatchInst<T>) * n));
+        RPR_HIP(hipMemcpyAsync(ti.p, hi.data(), sizeof(BatchInst<T>) * n, hipMemcpyHostToDevice, st));
+        RPR_HIP(hipStreamSynchronize(st));
+        const auto *insts = static_cast<const BatchInst<T> *>(ti.p);
+        float best = 1e30f;
+        int best_m = 2;
+        for (int m = 1; m <= 4; ++m) {
+            const int grid = std::min(p->bn_items, m * cus);
+            auto launch = [&]() -> rpr_status {
+                RPR_TRY(zero(p->bcounter, 1, st));
+                return launch_prop_persistent<T>(insts, p->bitems, p->bn_items, p->bcounter, p->bgmax, p->bshF, grid,
+                                                 st);
+            };
+            RPR_TRY(launch());
+            RPR_HIP(hipEventRecord(e0, st));
+            RPR_TRY(launch());
+            RPR_HIP(hipEventRecord(e1, st));
+            RPR_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
+            g_tune[kg + ":t:" + std::to_string(m)] = (int)(ms * 1000.f);
+            if (ms < best) {
+                best = ms;
+                best_m = m;
+            }
+            if (grid == p->bn_items) break;  // more work-groups than items add nothing
+        }
+        g_tune[kg] = best_m;
+        tune_store();
+    }
+    p->bgrid = std::min(p->bn_items, g_tune[kg] * cus);
+    return RPR_OK;
+}
+
+template <typename T>
+rpr_status autotune_batch(rpr_plan *p, int cus)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rpr_status rc = RPR_OK;
+    if (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(RPR_ERR_HIP, "autotune: cannot create a stream or events");
+    if (rc == RPR_OK) rc = autotune_batch_run<T>(p, cus, st, e0, e1);
+    if (st) (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    return rc;
+}
+
+template rpr_status autotune_batch<double>(rpr_plan *, int);
+template rpr_status autotune_batch<float>(rpr_plan *, int);

@@ -27,8 +27,8 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
         return st;
     };
     rpr_options o = *opt;
-    o.autotune = 0;
-    o.graph = 0;  // the batch captures its own iteration block
+    o.autotune = 0;  // the instances take the batch's shapes; the batch is tuned as a whole below
+    o.graph = 0;     // the batch captures its own iteration block
     for (int b = 0; b < n_inst; ++b) {
         rpr_plan *q = nullptr;
         const rpr_status st = rpr_plan_create(&q, &h[b], d[b], t0[b], tN[b], N[b], &F[b], &G[b], tol[b],
@@ -115,6 +115,10 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     p->bgrid = p->bn_items < 2 * cus ? p->bn_items : 2 * cus;
+    if (opt->autotune) {
+        st = p->esz == 8 ? autotune_batch<double>(p, cus) : autotune_batch<float>(p, cus);
+        if (st != RPR_OK) return bail(st);
+    }
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
         return bail(fail(RPR_ERR_HIP, "batch: event creation failed"));
     p->use_graph = opt->graph;

@@ -237,6 +237,11 @@ int tuned_variant(const Geom &g, int esz, int method);
 template <typename T>
 rpr_status autotune_plan(rpr_plan *p, int max_wg, int cus);
 
+// Times the persistent fine-solve launch of batch p over 1 to 4 work-groups
+// per CU and keeps the fastest in p->bgrid.
+template <typename T>
+rpr_status autotune_batch(rpr_plan *p, int cus);
+
 // ---- phases of a solve (shared by single and batched plans) ----
 template <typename T>
 inline ChainArgs<T> chain_args(rpr_plan *p, double s)

@@ -74,6 +74,23 @@ def test_batch_at_workload_sizes_matches_oracle_per_instance(c4):
         assert_same_run(Ug, ig, Uo, io, w.N)
 
 
+def test_autotuned_batch_at_workload_sizes_matches_oracle_per_instance(c4, tmp_path, monkeypatch):
+    # the batch autotuner picks the persistent launch's work-group count by
+    # timing it; the items are independent, so the values are those of the
+    # untuned batch bit for bit, and the choice lands in the tuning table
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("RPR_TUNE_CACHE", str(cache))
+    ws, runs, _ = c4
+    status, Us, infos = run_batch(ws, autotune=1)
+    assert status == rpr.RPR_OK
+    _, Up, _ = run_batch(ws)
+    for w, Ug, ig, Ub, (Uo, io) in zip(ws, Us, infos, Up, runs):
+        assert_same_run(Ug, ig, Uo, io, w.N)
+        np.testing.assert_array_equal(Ug, Ub)
+    text = cache.read_text() if cache.exists() else ""
+    print(text[:400])
+
+
 def test_reduced_precision_batch_at_workload_sizes_within_tau(c4):
     # every instance: E of the reduced-precision solve against the FP64
     # serial fine solution exceeds that of the FP64 iterate after as many
