@@ -112,6 +112,9 @@ def parse():
                     help="only time the random-feature GEMMs at the workloads' shapes and a compute-bound one")
     ap.add_argument("--robustness", action="store_true",
                     help="only run the sweep over neighbour counts, neurons and weight draws (App. D)")
+    ap.add_argument("--robustness-grid", choices=["reduced", "paper"], default="reduced",
+                    help="reduced: 8 m x 6 M x 10 draws in one batch per system; paper: App. D's "
+                         "19 m x 49 M x 100 draws, one batch per draw")
     ap.add_argument("--f-only", choices=["swe_192x192", "bruss_128x128"], default=None,
                     help="only time the fine propagator of this workload in FP64 and FP32 (for counter runs)")
     ap.add_argument("--trace-summary", metavar="CSV", default=None,
@@ -173,7 +176,14 @@ def main():
         print(json.dumps({"extra": extra_workloads(torch, rpr, W, dev, only=args.solve_only)}))
         return
     if args.robustness:
-        print(json.dumps({"robustness": robustness_sweep(torch, rpr, W, dev)}))
+        if args.robustness_grid == "paper":
+            # App. D: m = 2..20, M = 20..500 in steps of 10, 100 weight draws;
+            # one batch per draw
+            res = robustness_sweep(torch, rpr, W, dev, n_seeds=100, ms=tuple(range(2, 21)),
+                                   Ms=tuple(range(20, 501, 10)), seeds_per_batch=1)
+        else:
+            res = robustness_sweep(torch, rpr, W, dev)
+        print(json.dumps({"robustness": res}))
         return
     if args.model_only:
         print(json.dumps({"model_fp64": model_roofline(torch, rpr, W, dev, reps=max(args.steps, 1))}))
@@ -612,14 +622,15 @@ def gemm_demo(torch, rpr, dev, reps=5):
 
 
 def robustness_sweep(torch, rpr, W, dev, n_seeds=10, ms=(2, 3, 4, 6, 8, 12, 16, 20),
-                     Ms=(20, 50, 100, 200, 300, 500)):
+                     Ms=(20, 50, 100, 200, 300, 500), seeds_per_batch=None):
     """Iterations to convergence K of RandNet-Parareal with the per-prediction
     refit on the m nearest pairs (eq. "randnet"), over neighbour counts m,
     neuron counts M and independent draws of the weights A, zeta: the study
     of App. D, on a Burgers system with d = 128 and a diffusion-reaction
     system with d = 722 (19 x 19 cells, two species).  Every (draw, m, M)
     combination is one instance of one batch plan (same initial state, its
-    own weights), so each system is a single batched solve.  Returns, per
+    own weights), so each system is a single batched solve, or one per
+    `seeds_per_batch` weight draws when the grid is large.  Returns, per
     system, the histograms of K by m and by M, and K of classical Parareal
     on the same problem for reference.  Progress goes to stderr."""
     from collections import Counter
@@ -632,30 +643,42 @@ def robustness_sweep(torch, rpr, W, dev, n_seeds=10, ms=(2, 3, 4, 6, 8, 12, 16, 
         "diffreact_19x19": W.small(W.DIFFREACT_64, nx=19, ny=19, F=(4, 200), G=(1, 4)),
     }
     out = {}
+    per_batch = seeds_per_batch or n_seeds
     for name, w in systems.items():
         u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
         h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
-        combos, problems = [], []
-        for sd in range(n_seeds):
-            for M in Ms:
-                wM = w.replace(M=M)
-                A, z = W.random_weights(wM, seed=1000 + sd)
-                for m in ms:
-                    combos.append((sd, m, M))
-                    problems.append(dict(h=h, d=w.d, t0=w.t0, tN=w.tN, N=w.N, F=w.F, G=w.G, M=M, activation=w.act,
-                                         lam=w.lam, A=A, zeta=z, m_nn=m))
         k_max = min(w.N, 32)
-        t0 = time.perf_counter()
-        plan = rpr.BatchPlan(problems, tol=[w.eps] * len(problems), correction=rpr.RPR_CORR_RANDNET_NN,
-                             k_max=k_max)
-        outs = [torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev) for _ in problems]
-        t1 = time.perf_counter()
-        plan.execute([u0] * len(problems), outs)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        Ks = [plan.instance(b).info()["K"] for b in range(len(problems))]
-        conv = [plan.instance(b).info()["converged"] for b in range(len(problems))]
-        plan.close()
+        combos, Ks, conv = [], [], []
+        t_create = t_solve = 0.0
+        for s0 in range(0, n_seeds, per_batch):
+            problems = []
+            for sd in range(s0, min(n_seeds, s0 + per_batch)):
+                for M in Ms:
+                    wM = w.replace(M=M)
+                    A, z = W.random_weights(wM, seed=1000 + sd)
+                    for m in ms:
+                        combos.append((sd, m, M))
+                        problems.append(dict(h=h, d=w.d, t0=w.t0, tN=w.tN, N=w.N, F=w.F, G=w.G, M=M,
+                                             activation=w.act, lam=w.lam, A=A, zeta=z, m_nn=m))
+            t0 = time.perf_counter()
+            plan = rpr.BatchPlan(problems, tol=[w.eps] * len(problems), correction=rpr.RPR_CORR_RANDNET_NN,
+                                 k_max=k_max)
+            outs = [torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev) for _ in problems]
+            t1 = time.perf_counter()
+            plan.execute([u0] * len(problems), outs)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            Ks += [plan.instance(b).info()["K"] for b in range(len(problems))]
+            conv += [plan.instance(b).info()["converged"] for b in range(len(problems))]
+            plan.close()
+            del outs
+            t_create += t1 - t0
+            t_solve += t2 - t1
+            if per_batch < n_seeds:
+                print(f"robustness {name}: draws {s0}..{min(n_seeds, s0 + per_batch) - 1} done "
+                      f"({len(problems)} instances, solve {t2 - t1:.2f} s)", file=sys.stderr, flush=True)
+        t1, t2 = t_create, t_create + t_solve
+        t0 = 0.0
         by_m = {m: Counter() for m in ms}
         by_M = {M: Counter() for M in Ms}
         for (sd, m, M), K, c in zip(combos, Ks, conv):
@@ -668,12 +691,12 @@ def robustness_sweep(torch, rpr, W, dev, n_seeds=10, ms=(2, 3, 4, 6, 8, 12, 16, 
         torch.cuda.synchronize()
         K_para = pp.info()["K"]
         pp.close()
-        out[name] = {"d": w.d, "N": w.N, "instances": len(problems), "weight_draws": n_seeds, "k_max": k_max,
+        out[name] = {"d": w.d, "N": w.N, "instances": len(combos), "weight_draws": n_seeds, "k_max": k_max,
                      "create_s": t1 - t0, "solve_s": t2 - t1, "K_classical_parareal": K_para,
                      "K_median": float(np.median(Ks)),
                      "K_by_m": {str(m): hist(c) for m, c in by_m.items()},
                      "K_by_M": {str(M): hist(c) for M, c in by_M.items()}}
-        print(f"robustness {name}: {len(problems)} instances, solve {t2 - t1:.2f} s, median K "
+        print(f"robustness {name}: {len(combos)} instances, solve {t2 - t1:.2f} s, median K "
               f"{np.median(Ks)}, classical K {K_para}", file=sys.stderr, flush=True)
     return out
 
