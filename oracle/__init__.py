@@ -92,6 +92,12 @@ def lib():
         L.orc_ridge_fit_dual.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, C.c_double, dp]
         L.orc_cholesky.restype = C.c_int32
         L.orc_cholesky.argtypes = [C.c_int32, dp, dp]
+        L.orc_ridgeless_fit.restype = C.c_int32
+        L.orc_ridgeless_fit.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32)]
+        L.orc_ridgeless_stats.restype = C.c_int32
+        L.orc_ridgeless_stats.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32)]
+        L.orc_sym_eig.restype = None
+        L.orc_sym_eig.argtypes = [C.c_int32, dp, dp, dp]
         L.orc_nearest.restype = None
         L.orc_nearest.argtypes = [C.c_int32, C.c_int32, dp, dp, C.c_int32, ip]
         L.orc_splitmix64.restype = C.c_uint64
@@ -199,6 +205,32 @@ def ridge_fit(Phi, Y, lam: float) -> np.ndarray:
     if rc:
         raise np.linalg.LinAlgError(f"orc_ridge_fit failed ({rc})")
     return W
+
+
+def ridgeless_fit(Phi, Y):
+    """eq. "ridgeless" at lambda -> 0: W = Phi^+ Y, and the rank of the Gram."""
+    Phi, Y = _f64(Phi), _f64(Y)
+    W = np.empty((Phi.shape[1], Y.shape[1]))
+    r = C.c_int32(0)
+    lib().orc_ridgeless_fit(Phi.shape[1], Y.shape[1], Phi.shape[0], _dp(Phi), _dp(Y), _dp(W), C.byref(r))
+    return W, r.value
+
+
+def ridgeless_stats(G, B, n: int):
+    """The same limit from G = Phi^T Phi and B = Phi^T Y of n rows: W = G^+ B, rank."""
+    G, B = _f64(G), _f64(B)
+    W = np.empty_like(B)
+    r = C.c_int32(0)
+    lib().orc_ridgeless_stats(G.shape[0], B.shape[1], int(n), _dp(G), _dp(B), _dp(W), C.byref(r))
+    return W, r.value
+
+
+def sym_eig(S):
+    """Eigenvalues and eigenvectors (columns) of a symmetric matrix, cyclic Jacobi."""
+    S = _f64(S)
+    w, V = np.empty(S.shape[0]), np.empty_like(S)
+    lib().orc_sym_eig(S.shape[0], _dp(S), _dp(w), _dp(V))
+    return w, V
 
 
 def ridge_fit_dual(Phi, Y, lam: float) -> np.ndarray:

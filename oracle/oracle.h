@@ -83,7 +83,7 @@ enum { ORC_TANH = 0, ORC_RELU = 1 };
 typedef struct {
     int32_t M;             /* hidden neurons */
     int32_t act;           /* ORC_TANH / ORC_RELU */
-    double lambda;         /* ridge penalty */
+    double lambda;         /* ridge penalty; 0 = the ridgeless limit (pseudo-inverse) */
     double scale;          /* input scale s: the network sees x / s */
     const double *A;       /* M x d, row-major */
     const double *zeta;    /* M */
@@ -93,13 +93,29 @@ typedef struct {
 void orc_features(const orc_randnet *net, int32_t d, int32_t n, const double *X, double *Phi);
 
 /* Ridge readout from explicit rows: W (M x d) = (Phi^T Phi + lambda I)^{-1} Phi^T Y,
- * by Cholesky.  Returns 0, or -6 if the matrix is not numerically positive definite. */
+ * by Cholesky.  Returns 0, or -6 if the matrix is not numerically positive definite;
+ * lambda = 0 gives the ridgeless limit (orc_ridgeless_fit). */
 int32_t orc_ridge_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y,
                       double lambda, double *W);
 
 /* Dual (kernel) form of the same estimator: W = Phi^T (Phi Phi^T + lambda I_n)^{-1} Y. */
 int32_t orc_ridge_fit_dual(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y,
                            double lambda, double *W);
+
+/* The limit lambda -> 0 of eq. "ridgeless": W = Phi^+ Y (Moore-Penrose), through
+ * the pseudo-inverse of the smaller Gram; *rank (may be NULL) receives its rank.
+ * orc_ridge_fit and orc_ridge_fit_dual take this branch for lambda = 0. */
+int32_t orc_ridgeless_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y, double *W,
+                          int32_t *rank);
+
+/* The same from accumulated statistics G = Phi^T Phi (M x M), B = Phi^T Y (M x d)
+ * of n rows: W = G^+ B. */
+int32_t orc_ridgeless_stats(int32_t M, int32_t d, int32_t n, const double *G, const double *B, double *W,
+                            int32_t *rank);
+
+/* Eigenvalues w (s) and eigenvectors (columns of V, s x s row-major) of a symmetric
+ * s x s matrix S, cyclic Jacobi. */
+void orc_sym_eig(int32_t s, const double *S, double *w, double *V);
 
 /* Cholesky factor of an s x s symmetric matrix (lower triangle read), returned in
  * the lower triangle of Lout (upper part zeroed).  Returns 0 or -6. */

@@ -15,7 +15,8 @@
  *     eq. "HA" whose readout solves eq. "ridgeless" at penalty lambda on every
  *     pair of eq. "Dk" collected so far (global mode), or on the m nearest
  *     pairs of the query (eq. "randnet", Algorithm "RandNets training
- *     procedure"; penalty lambda > 0, dual form);
+ *     procedure"; dual form); lambda = 0 takes the limit itself, the
+ *     pseudo-inverse solution of that algorithm;
  *   - the pairs are (U_{i-1}^{k-1}, F(U_{i-1}^{k-1}) - G(U_{i-1}^{k-1})) for the
  *     slots run at iteration k; pairs with a non-finite entry are dropped;
  *   - convergence (eq. "stop_crit"): after the update L advances over the exact
@@ -158,7 +159,10 @@ int32_t orc_parareal(const orc_problem *pb, const orc_parareal_cfg *cfg, const o
                 n_rows++;
             }
             inf.rows_used = n_rows;
-            if (!nn_mode) {
+            if (!nn_mode && net->lambda == 0.0) {
+                /* eq. "ridgeless" at its limit lambda -> 0 on every pair so far */
+                orc_ridgeless_stats(M, d, n_rows, Gacc, Bacc, W, NULL);
+            } else if (!nn_mode) {
                 /* eq. "ridgeless" at penalty lambda on every pair so far */
                 memcpy(Gl, Gacc, sizeof(double) * M * M);
                 for (int a = 0; a < M; ++a) Gl[a * M + a] += net->lambda;

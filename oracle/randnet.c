@@ -62,12 +62,193 @@ static void chol_solve(int s, const double *L, int nrhs, double *Bm)
 }
 
 /*
+ * Eigendecomposition S = V diag(w) V^T of a symmetric s x s matrix by the
+ * cyclic Jacobi method (Jacobi 1846; Golub and Van Loan, Matrix
+ * Computations, Sec. 8.5): each off-diagonal entry in row order is zeroed by
+ * a plane rotation, sweep after sweep, until the off-diagonal squares sum to
+ * at most 2^-104 of all squares (at most 100 sweeps).  V row-major, its
+ * columns the eigenvectors.
+ */
+void orc_sym_eig(int32_t s, const double *S, double *w, double *V)
+{
+    double *A = malloc(sizeof(double) * (size_t)s * s);
+    memcpy(A, S, sizeof(double) * (size_t)s * s);
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) V[(size_t)i * s + j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, all = 0.0;
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < s; ++j) {
+                const double a2 = A[(size_t)i * s + j] * A[(size_t)i * s + j];
+                all += a2;
+                if (i != j) off += a2;
+            }
+        if (off <= 0x1p-104 * all) break;
+        for (int p = 0; p < s - 1; ++p)
+            for (int q = p + 1; q < s; ++q) {
+                const double apq = A[(size_t)p * s + q];
+                if (apq == 0.0) continue;
+                /* rotation [c sn; -sn c] in the (p, q) plane that zeroes apq */
+                const double tau = (A[(size_t)q * s + q] - A[(size_t)p * s + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+                for (int k = 0; k < s; ++k) { /* A <- A J */
+                    const double akp = A[(size_t)k * s + p], akq = A[(size_t)k * s + q];
+                    A[(size_t)k * s + p] = c * akp - sn * akq;
+                    A[(size_t)k * s + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < s; ++k) { /* A <- J^T A */
+                    const double apk = A[(size_t)p * s + k], aqk = A[(size_t)q * s + k];
+                    A[(size_t)p * s + k] = c * apk - sn * aqk;
+                    A[(size_t)q * s + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < s; ++k) { /* V <- V J */
+                    const double vkp = V[(size_t)k * s + p], vkq = V[(size_t)k * s + q];
+                    V[(size_t)k * s + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * s + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < s; ++i) w[i] = A[(size_t)i * s + i];
+    free(A);
+}
+
+/*
+ * Moore-Penrose pseudo-inverse of a symmetric positive semi-definite s x s
+ * matrix S from its eigendecomposition: eigenvalues at or below
+ * cut * max(eigenvalue) count as zero (their reciprocal is replaced by 0).
+ * Returns the rank, the count of the others.
+ */
+static int32_t psd_pinv(int32_t s, const double *S, double cut, double *Sp)
+{
+    double *w = malloc(sizeof(double) * (size_t)s);
+    double *V = malloc(sizeof(double) * (size_t)s * s);
+    orc_sym_eig(s, S, w, V);
+    double wmax = 0.0;
+    for (int i = 0; i < s; ++i)
+        if (w[i] > wmax) wmax = w[i];
+    int32_t rank = 0;
+    for (int i = 0; i < s; ++i) {
+        if (w[i] > cut * wmax && wmax > 0.0) {
+            w[i] = 1.0 / w[i];
+            rank++;
+        } else {
+            w[i] = 0.0;
+        }
+    }
+    for (int a = 0; a < s; ++a)
+        for (int b = 0; b < s; ++b) {
+            double t = 0.0;
+            for (int i = 0; i < s; ++i) t += V[(size_t)a * s + i] * w[i] * V[(size_t)b * s + i];
+            Sp[(size_t)a * s + b] = t;
+        }
+    free(w);
+    free(V);
+    return rank;
+}
+
+/*
+ * Readout of eq. "ridgeless" at its limit lambda -> 0, the Moore-Penrose
+ * solution W = X^+ Y (X = Phi, n x M; Y, n x d).  Alg. "RandNets training
+ * procedure" writes it as (X^T X)^{-1} X^T Y when rank(X^T X) = M <= n and as
+ * (X^T X)^+ X^T Y otherwise; both are X^+ Y, computed here as
+ * (X^T X)^+ X^T Y when n >= M and as X^T (X X^T)^+ Y when n < M (the smaller
+ * Gram), with eigenvalues of the Gram at or below max(n, M) 2^-52 times the
+ * largest counted as zero.  *rank (if not NULL) receives the Gram's rank.
+ */
+int32_t orc_ridgeless_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y, double *W,
+                          int32_t *rank)
+{
+    const double cut = (double)(n > M ? n : M) * 0x1p-52;
+    int32_t r;
+    if (n >= M) {
+        double *G = calloc((size_t)M * M, sizeof(double));
+        double *Gp = malloc(sizeof(double) * (size_t)M * M);
+        double *B = malloc(sizeof(double) * (size_t)M * d);
+        if (!G || !Gp || !B) { free(G); free(Gp); free(B); return -4; }
+        for (int a = 0; a < M; ++a)
+            for (int b = 0; b < M; ++b) {
+                double t = 0.0;
+                for (int q = 0; q < n; ++q) t += Phi[(size_t)q * M + a] * Phi[(size_t)q * M + b];
+                G[(size_t)a * M + b] = t;
+            }
+        for (int a = 0; a < M; ++a)
+            for (int j = 0; j < d; ++j) {
+                double t = 0.0;
+                for (int q = 0; q < n; ++q) t += Phi[(size_t)q * M + a] * Y[(size_t)q * d + j];
+                B[(size_t)a * d + j] = t;
+            }
+        r = psd_pinv(M, G, cut, Gp);
+        for (int a = 0; a < M; ++a)
+            for (int j = 0; j < d; ++j) {
+                double t = 0.0;
+                for (int b = 0; b < M; ++b) t += Gp[(size_t)a * M + b] * B[(size_t)b * d + j];
+                W[(size_t)a * d + j] = t;
+            }
+        free(G);
+        free(Gp);
+        free(B);
+    } else {
+        double *K = calloc((size_t)n * n, sizeof(double));
+        double *Kp = malloc(sizeof(double) * (size_t)n * n);
+        double *Cm = malloc(sizeof(double) * (size_t)n * d);
+        if (!K || !Kp || !Cm) { free(K); free(Kp); free(Cm); return -4; }
+        for (int q = 0; q < n; ++q)
+            for (int p = 0; p < n; ++p) {
+                double t = 0.0;
+                for (int a = 0; a < M; ++a) t += Phi[(size_t)q * M + a] * Phi[(size_t)p * M + a];
+                K[(size_t)q * n + p] = t;
+            }
+        r = psd_pinv(n, K, cut, Kp);
+        for (int q = 0; q < n; ++q)
+            for (int j = 0; j < d; ++j) {
+                double t = 0.0;
+                for (int p = 0; p < n; ++p) t += Kp[(size_t)q * n + p] * Y[(size_t)p * d + j];
+                Cm[(size_t)q * d + j] = t;
+            }
+        for (int a = 0; a < M; ++a)
+            for (int j = 0; j < d; ++j) {
+                double t = 0.0;
+                for (int q = 0; q < n; ++q) t += Phi[(size_t)q * M + a] * Cm[(size_t)q * d + j];
+                W[(size_t)a * d + j] = t;
+            }
+        free(K);
+        free(Kp);
+        free(Cm);
+    }
+    if (rank) *rank = r;
+    return 0;
+}
+
+/*
+ * The same limit from accumulated statistics G = X^T X (M x M) and
+ * B = X^T Y (M x d) of n rows: W = G^+ B, the cut as in orc_ridgeless_fit.
+ */
+int32_t orc_ridgeless_stats(int32_t M, int32_t d, int32_t n, const double *G, const double *B, double *W,
+                            int32_t *rank)
+{
+    double *Gp = malloc(sizeof(double) * (size_t)M * M);
+    const int32_t r = psd_pinv(M, G, (double)(n > M ? n : M) * 0x1p-52, Gp);
+    for (int a = 0; a < M; ++a)
+        for (int j = 0; j < d; ++j) {
+            double t = 0.0;
+            for (int b = 0; b < M; ++b) t += Gp[(size_t)a * M + b] * B[(size_t)b * d + j];
+            W[(size_t)a * d + j] = t;
+        }
+    free(Gp);
+    if (rank) *rank = r;
+    return 0;
+}
+
+/*
  * Ridge readout of eq. "ridgeless" at a fixed penalty:
- *   W = (X^T X + lambda I_M)^{-1} X^T Y, X = Phi (n x M), Y (n x d).
+ *   W = (X^T X + lambda I_M)^{-1} X^T Y, X = Phi (n x M), Y (n x d);
+ * lambda = 0 is the limit itself (orc_ridgeless_fit).
  */
 int32_t orc_ridge_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y,
                       double lambda, double *W)
 {
+    if (lambda == 0.0) return orc_ridgeless_fit(M, d, n, Phi, Y, W, NULL);
     double *G = malloc(sizeof(double) * (size_t)M * M);
     double *L = malloc(sizeof(double) * (size_t)M * M);
     if (!G || !L) { free(G); free(L); return -4; }
@@ -90,10 +271,12 @@ int32_t orc_ridge_fit(int32_t M, int32_t d, int32_t n, const double *Phi, const 
     return rc;
 }
 
-/* Same estimator in dual form: W = X^T (X X^T + lambda I_n)^{-1} Y. */
+/* Same estimator in dual form: W = X^T (X X^T + lambda I_n)^{-1} Y
+ * (lambda = 0: orc_ridgeless_fit). */
 int32_t orc_ridge_fit_dual(int32_t M, int32_t d, int32_t n, const double *Phi, const double *Y,
                            double lambda, double *W)
 {
+    if (lambda == 0.0) return orc_ridgeless_fit(M, d, n, Phi, Y, W, NULL);
     double *K = malloc(sizeof(double) * (size_t)n * n);
     double *L = malloc(sizeof(double) * (size_t)n * n);
     double *C = malloc(sizeof(double) * (size_t)n * d);
