@@ -24,7 +24,7 @@ stream), the 64 x 64 diffusion-reaction workload in FP64, and the CPU oracle
 timed on the host cores.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
-                    [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128]
+                    [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128 [--shape S]]
                     [--solve-only NAME] [--gemm] [--robustness] [--model-only]
                     [--trace-summary KERNEL_TRACE_CSV]
 
@@ -33,7 +33,8 @@ timed on the host cores.
 which takes minutes.  --copy-calibration runs a device copy of 256 MiB, the
 reference a hardware-counter run uses to scale its byte counters.  --f-only
 times only the fine propagator of the named workload (all N slot states,
---steps RK4 steps, FP64 and FP32) and prints its roofline, for counter runs;
+--steps RK4 steps, FP64 and FP32; --shape pins a tile shape of the one-pass
+kernel where the precision has it) and prints its roofline, for counter runs;
 --model-only times the model phase's FP64 matrix products (features, ridge
 fit) at the shallow-water shape, for counter runs.
 """
@@ -80,8 +81,9 @@ ALGO_BYTES_PER_DOF_STEP = {8: 16, 4: 8}
 PROP_SOURCES = ("paper_2411_06225_amd/csrc/swefused.h", "paper_2411_06225_amd/csrc/tiled.hip",
                 "paper_2411_06225_amd/csrc/tiledprop.h", "paper_2411_06225_amd/csrc/slotprop.h",
                 "paper_2411_06225_amd/csrc/common.h")
-PROP_TRAFFIC = {"sources": "22cd509a3460e719", "fetch_kib": 110684.8, "fetch_scale": 2.0, "write_kib": 221324.8,
-                "write_scale": 1.0}
+PROP_TRAFFIC = {"sources": None, "fetch_scale": 2.0, "write_scale": 1.0,
+                # tile shape -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch, FP32, 256 states
+                "shapes": {}}
 
 
 def sources_hash(paths):
@@ -91,11 +93,31 @@ def sources_hash(paths):
     return hashlib.sha1(digests.encode()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(shape):
+    """HBM bytes per dispatch of the fine propagator in tile shape `shape`,
+    or None when no counters were taken on these sources for that shape."""
     t = PROP_TRAFFIC
-    if t["sources"] is None or sources_hash(PROP_SOURCES) != t["sources"]:
+    if t["sources"] is None or sources_hash(PROP_SOURCES) != t["sources"] or shape not in t["shapes"]:
         return None
-    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+    fetch_kib, write_kib = t["shapes"][shape]
+    return (fetch_kib * t["fetch_scale"] + write_kib * t["write_scale"]) * 1024
+
+
+def swe_kernel_name(shape, real="float"):
+    """The kernel that a one-pass shallow-water tile shape launches."""
+    import re
+    m = re.fullmatch(r"rows:C(\d+)R(\d+)NW(\d+)", shape)
+    if m:
+        return f"k_prop_swe_rows<{real}, {m[1]}, {m[2]}, {m[3]}>"
+    m = re.fullmatch(r"R(\d+)NW(\d+)", shape)
+    return f"k_prop_swe_fused<{real}, {m[1]}, {m[2]}>" if m else shape
+
+
+def chosen_shape(rpr, w, prec):
+    """The tile shape the autotuner chose for workload w's fine propagator
+    (the default shape when it has not run)."""
+    v = rpr.rpr_tune_get(rpr.prop_tune_key(w.kind, w.nx, w.ny, prec, w.F[0]) + ":v")
+    return rpr.tile_shapes(w.kind, prec)[v or 0]
 
 
 def parse():
@@ -115,6 +137,8 @@ def parse():
     ap.add_argument("--robustness-grid", choices=["reduced", "paper"], default="reduced",
                     help="reduced: 8 m x 6 M x 10 draws in one batch per system; paper: App. D's "
                          "19 m x 49 M x 100 draws, one batch per draw")
+    ap.add_argument("--shape", default=None,
+                    help="with --f-only: pin this tile shape of the one-pass kernel (names: rpr.tile_shapes)")
     ap.add_argument("--f-only", choices=["swe_192x192", "bruss_128x128"], default=None,
                     help="only time the fine propagator of this workload in FP64 and FP32 (for counter runs)")
     ap.add_argument("--trace-summary", metavar="CSV", default=None,
@@ -190,6 +214,12 @@ def main():
         return
     if args.f_only:
         wf = W.WORKLOADS[args.f_only]
+        if args.shape:
+            for prec in (rpr.RPR_FP64, rpr.RPR_MIXED):
+                names = rpr.tile_shapes(wf.kind, prec)
+                if args.shape in names:
+                    rpr.rpr_tune_set(rpr.prop_tune_key(wf.kind, wf.nx, wf.ny, prec, wf.F[0]) + ":v",
+                                     names.index(args.shape))
         cb = copy_bandwidth(torch, dev)
         res = {"workload": wf.name, "F_roofline": {
             "fp64": f_roofline(torch, rpr, wf, rpr.RPR_FP64, dev, steps=args.steps, copy_bw=cb),
@@ -306,9 +336,13 @@ def main():
     ev[1].record(stream)
     torch.cuda.synchronize()
     alone = ev[0].elapsed_time(ev[1]) / 1e3 / f_steps
+    shape = chosen_shape(rpr, w, rpr.RPR_MIXED)
+    traffic = measured_traffic(shape)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
-                "kernel": "k_prop_swe_fused<float,5,8> (fine RK4, one launch per step, shallow water 192x192)",
+                "frac": achieved / HBM_PEAK,
+                "traffic": traffic * algo_bytes / (ALGO_BYTES_PER_DOF_STEP[4] * w.d * w.N) if traffic else None,
+                "kernel": swe_kernel_name(shape) + " (fine RK4, one launch per step, shallow water 192x192)",
+                "tile_shape": shape,
                 "launch": {"launches": fine_launches, "ms": f_launch * 1e3, "algorithmic_bytes": algo_bytes,
                            "bytes_per_dof_step": ALGO_BYTES_PER_DOF_STEP[4],
                            "alu_TFLOPs": flops / f_launch / 1e12,
@@ -522,10 +556,14 @@ def f_roofline(torch, rpr, w, prec, dev, steps=20, copy_bw=None):
     bpd = ALGO_BYTES_PER_DOF_STEP[esz]
     bytes_ = w.N * w.d * steps * bpd
     achieved = bytes_ / sec
-    kernel = ("k_prop_swe_fused" if w.kind == rpr.RPR_SWE2D else "k_prop_rk4_fused") + \
-        " (fine RK4, one launch per step)"
+    if w.kind == rpr.RPR_SWE2D:
+        shape = chosen_shape(rpr, w, prec)
+        kernel = swe_kernel_name(shape, "double" if prec == rpr.RPR_FP64 else "float")
+    else:
+        shape, kernel = None, "k_prop_rk4_fused"
+    kernel += " (fine RK4, one launch per step)"
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "kernel": kernel,
+            "frac": achieved / HBM_PEAK, "kernel": kernel, "tile_shape": shape,
             "measured_copy_GBps": copy_bw / 1e9 if copy_bw else None,
             "frac_of_copy": achieved / copy_bw if copy_bw else None,
             "launch": {"slots": w.N, "steps": steps, "ms_per_step": sec * 1e3 / steps,

@@ -325,6 +325,35 @@ rpr_status rpr_plan_instance(const rpr_plan *batch, int32_t b, const rpr_plan **
 rpr_status rpr_stability(const rpr_rhs *h, int32_t d, const rpr_propagator *P, double dt, double umax,
                          double speed, double *ratio);
 
+/*
+ * The autotuner's table of launch shapes (rpr_options.autotune), shared by
+ * every plan and call of the process; a shape changes the launch, not the
+ * arithmetic of any value.  rpr_tune_set stores value under key (a negative
+ * value removes the key, so that the autotuner measures that class again);
+ * rpr_tune_get reads it (RPR_ERR_INVALID_ARG if absent).  Keys of the fine
+ * propagator, for right-hand side kind on an nx x ny grid, values of
+ * `bytes` (8 or 4) and method m:
+ *   "prop:<kind>:<nx>x<ny>:<bytes>:<m>"    work-group size (1024, 512, or 256 =
+ *                                          the tiled form)
+ *   "prop:<kind>:<nx>x<ny>:<bytes>:<m>:v"  tile shape of the tiled form's
+ *                                          one-pass RK4 kernel, 0 ..
+ *                                          rpr_tile_shapes() - 1
+ * rpr_propagate with threads 256 takes the tile shape stored for its class;
+ * a shape that does not serve the grid returns RPR_ERR_UNSUPPORTED.
+ * Errors: RPR_ERR_INVALID_ARG (null or empty key, null value).
+ */
+rpr_status rpr_tune_set(const char *key, int32_t value);
+rpr_status rpr_tune_get(const char *key, int32_t *value);
+
+/* Number of tile shapes of the one-pass RK4 kernel for right-hand side kind
+ * at precision (1 where the kind has none), and the name of shape v
+ * (NULL outside 0 .. count - 1): "R<rows per wavefront>NW<wavefronts>" for
+ * 56-column tiles with a 4-cell halo, "rows:C<cells per lane>R..NW.." for
+ * the full-row form (grids with nx <= 64 C and nx a multiple of C),
+ * "FY<tile rows>NT<threads>" for the Laplacian systems. */
+int32_t rpr_tile_shapes(int32_t kind, int32_t precision);
+const char *rpr_tile_shape_name(int32_t kind, int32_t precision, int32_t v);
+
 /* Release every buffer of the plan (a batch releases its instances).  NULL is accepted. */
 rpr_status rpr_plan_destroy(rpr_plan *plan);
 

@@ -37,7 +37,8 @@ RPR_FEAT_AUTO, RPR_FEAT_FP64, RPR_FEAT_BF16 = 0, 1, 2
 EXPORTED = ("rpr_last_error", "rpr_version", "rpr_plan_create", "rpr_plan_execute", "rpr_plan_info",
             "rpr_plan_history", "rpr_plan_destroy", "rpr_propagate", "rpr_randnet_features", "rpr_ridge_fit",
             "rpr_randnet_readout", "rpr_uniform_pm1", "rpr_randnet_features_bf16", "rpr_plan_create_batch",
-            "rpr_plan_execute_batch", "rpr_plan_instance", "rpr_stability", "rpr_randnet_features_noalloc")
+            "rpr_plan_execute_batch", "rpr_plan_instance", "rpr_stability", "rpr_randnet_features_noalloc",
+            "rpr_tune_set", "rpr_tune_get", "rpr_tile_shapes", "rpr_tile_shape_name")
 
 
 class RprError(RuntimeError):
@@ -136,6 +137,10 @@ def lib() -> C.CDLL:
             "rpr_randnet_readout": (i32, [i32, i32, i32, vp, vp, vp, vp]),
             "rpr_uniform_pm1": (i32, [u64, u64, i64, vp, vp]),
             "rpr_stability": (i32, [C.POINTER(rpr_rhs), i32, C.POINTER(rpr_propagator), dbl, dbl, dbl, dp]),
+            "rpr_tune_set": (i32, [C.c_char_p, i32]),
+            "rpr_tune_get": (i32, [C.c_char_p, C.POINTER(C.c_int32)]),
+            "rpr_tile_shapes": (i32, [i32, i32]),
+            "rpr_tile_shape_name": (C.c_char_p, [i32, i32, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -259,6 +264,29 @@ def rpr_stability(h: rpr_rhs, d: int, method: int, steps: int, dt: float, umax: 
     r = C.c_double(0.0)
     check(lib().rpr_stability(C.byref(h), int(d), C.byref(P), float(dt), float(umax), float(speed), C.byref(r)))
     return r.value
+
+
+def rpr_tune_set(key: str, value: int) -> int:
+    """Store a launch shape in the autotuner's table (value < 0 removes the key)."""
+    return check(lib().rpr_tune_set(key.encode(), int(value)))
+
+
+def rpr_tune_get(key: str):
+    """The launch shape stored under key, or None."""
+    v = C.c_int32(0)
+    return v.value if lib().rpr_tune_get(key.encode(), C.byref(v)) == 0 else None
+
+
+def tile_shapes(kind: int, precision: int) -> list:
+    """Names of the one-pass RK4 kernel's tile shapes, in index order."""
+    L = lib()
+    return [L.rpr_tile_shape_name(int(kind), int(precision), v).decode()
+            for v in range(L.rpr_tile_shapes(int(kind), int(precision)))]
+
+
+def prop_tune_key(kind: int, nx: int, ny: int, precision: int, method: int) -> str:
+    """Table key of the fine propagator's class (append ":v" for the tile shape)."""
+    return f"prop:{int(kind)}:{int(nx)}x{int(ny)}:{8 if precision == RPR_FP64 else 4}:{int(method)}"
 
 
 # ---- plans ---------------------------------------------------------------------

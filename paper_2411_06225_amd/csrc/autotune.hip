@@ -81,6 +81,39 @@ int tuned_variant(const Geom &g, int esz, int method)
     return it == g_tune.end() ? 0 : it->second;
 }
 
+extern "C" rpr_status rpr_tune_set(const char *key, int32_t value)
+{
+    if (key == nullptr || *key == 0) return fail(RPR_ERR_INVALID_ARG, "rpr_tune_set: empty key");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    if (value < 0) g_tune.erase(key);
+    else g_tune[key] = value;
+    return RPR_OK;
+}
+
+extern "C" rpr_status rpr_tune_get(const char *key, int32_t *value)
+{
+    if (key == nullptr || *key == 0 || value == nullptr) return fail(RPR_ERR_INVALID_ARG, "rpr_tune_get: null argument");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    const auto it = g_tune.find(key);
+    if (it == g_tune.end()) return fail(RPR_ERR_INVALID_ARG, std::string("rpr_tune_get: no entry ") + key);
+    *value = it->second;
+    return RPR_OK;
+}
+
+extern "C" int32_t rpr_tile_shapes(int32_t kind, int32_t precision)
+{
+    return fused_variants(kind, precision == RPR_FP64 ? 8 : 4);
+}
+
+extern "C" const char *rpr_tile_shape_name(int32_t kind, int32_t precision, int32_t v)
+{
+    const size_t elem = precision == RPR_FP64 ? 8 : 4;
+    if (v < 0 || v >= fused_variants(kind, elem)) return nullptr;
+    return fused_variant_name(kind, elem, v);
+}
+
 // Device memory released when it goes out of scope.
 struct DevBuf {
     void *p = nullptr;
@@ -142,6 +175,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
             }
             const TiledWork<T> *wp = mt == TILED_THREADS ? &w : nullptr;
             for (int v = 0; v < (mt == TILED_THREADS ? nvar : 1); ++v) {
+                if (mt == TILED_THREADS && !fused_variant_fits(g, p->esz, v)) continue;
                 RPR_TRY(launch_propagate<T>(g, p->F.method, steps, p->dtF, N, U, Fv + d, nullptr, st, mt, wp, v));
                 float ms = 0.f;
                 RPR_HIP(hipEventRecord(e0, st));

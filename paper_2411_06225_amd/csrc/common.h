@@ -266,6 +266,8 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
 // and a short name of shape v for the autotuner's records.
 int fused_variants(int kind, size_t elem);
 const char *fused_variant_name(int kind, size_t elem, int v);
+// Whether tile shape v of the one-pass RK4 kernel serves this grid.
+bool fused_variant_fits(const Geom &g, size_t elem, int v);
 
 // The generic propagator (rkgen.hip): any explicit tableau (method 1, 4 or
 // 8), one launch per stage over the cells of all n states; work arrays as

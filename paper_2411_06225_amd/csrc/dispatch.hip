@@ -1,6 +1,7 @@
 // dispatch.hip -- host-side shape selection and the dispatch from a runtime
 // right-hand-side kind to the per-kind kernel objects.
 #include "chain.h"
+#include "swefused.h"
 #include "rkgen.h"
 #include "slotprop.h"
 #include "tiledprop.h"
@@ -144,14 +145,17 @@ template rpr_status launch_propagate<float>(const Geom &, int, int64_t, double, 
 // tiled.hip): shallow water (rows per wavefront R, wavefronts NW), the
 // Laplacian systems (tile rows FY, threads NT).
 namespace {
-const char *const kSweF32[] = {"R5NW8", "R4NW8", "R4NW10", "R8NW5", "R2NW16"};
-const char *const kSweF64[] = {"R4NW8", "R4NW6", "R3NW8", "R2NW12"};
+const char *const kSweF32[] = {"R5NW8", "R4NW8", "R4NW10", "R8NW5", "R2NW16", "rows:C3R2NW12", "rows:C2R3NW12"};
+const char *const kSweF64[] = {"R4NW8", "R4NW6", "R3NW8", "R2NW12", "rows:C3R2NW8", "rows:C2R3NW8"};
 const char *const kLap[] = {"FY32NT512", "FY16NT256", "FY32NT256", "FY64NT512"};
+// cells per lane of the full-row shapes (0: the 56-column tiles, any grid)
+const int kSweF32C[] = {0, 0, 0, 0, 0, 3, 2};
+const int kSweF64C[] = {0, 0, 0, 0, 3, 2};
 }  // namespace
 
 int fused_variants(int kind, size_t elem)
 {
-    if (kind == RPR_SWE2D) return elem == 4 ? 5 : 4;
+    if (kind == RPR_SWE2D) return elem == 4 ? 7 : 6;
     if (kind == RPR_DIFFREACT2D || kind == RPR_BRUSS2D) return 4;
     return 1;
 }
@@ -162,6 +166,14 @@ const char *fused_variant_name(int kind, size_t elem, int v)
     if (kind == RPR_SWE2D) return elem == 4 ? kSweF32[v] : kSweF64[v];
     if (kind == RPR_DIFFREACT2D || kind == RPR_BRUSS2D) return kLap[v];
     return "default";
+}
+
+bool fused_variant_fits(const Geom &g, size_t elem, int v)
+{
+    if (v < 0 || v >= fused_variants(g.kind, elem)) return false;
+    if (g.kind != RPR_SWE2D) return true;
+    const int C = elem == 4 ? kSweF32C[v] : kSweF64C[v];
+    return C == 0 || swr_fits(g, C);
 }
 
 size_t chain_lds(const OnchipShape &sh, int M)

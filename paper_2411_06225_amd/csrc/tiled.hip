@@ -1,7 +1,8 @@
 // tiled.hip -- the propagators F and G over one slice (Sec. 2) for slot
 // states too large for one work-group: passes over the tiles of every slot
 // state (tiledprop.h), one per RK stage (64 x 16-cell tiles), or one per RK4
-// step for the 5-point Laplacian systems (64 x 32-cell tiles).
+// step for the 5-point Laplacian systems (64 x 32-cell tiles) and for
+// shallow water (swefused.h: 56-column tiles, or whole rows per wavefront).
 #include "swefused.h"
 #include "tiledprop.h"
 
@@ -76,6 +77,48 @@ __global__ __launch_bounds__(64 * NW) void k_prop_swe_fused(Geom g, long long st
                            reinterpret_cast<T *>(lds_raw));
 }
 
+// One whole RK4 step of a shallow-water tile in the full-row form
+// (swe_rk4_rows).
+template <typename T, int C, int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_prop_swe_rows(Geom g, long long step, long long steps, double dt, int n,
+                                                           const T *__restrict__ in, T *__restrict__ out,
+                                                           TiledWork<T> w, const int *__restrict__ ctrl)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int tile, b;
+    tile_of_block((int)blockIdx.x, swr_tiles_of<C, R, NW>(g), n, tile, b);
+    if (ctrl != nullptr && (ctrl[2] != 0 || b < ctrl[0])) return;
+    const size_t off = (size_t)b * g.d;
+    T *buf[2] = {w.u + off, w.ya + off};
+    const T *src = step == 0 ? in + off : buf[(step - 1) & 1];
+    T *dst = step == steps - 1 ? out + off : buf[step & 1];
+    swe_rk4_rows<T, C, R, NW>(g, tile, dt, src, dst, w.cmp ? w.cmp + off : nullptr, step == 0 ? 1 : 0,
+                              reinterpret_cast<T *>(lds_raw));
+}
+
+template <typename T, int C, int R, int NW>
+static rpr_status launch_swe_rows(const Geom &g, int64_t steps, double dt, int n, const T *in, T *out,
+                                  const TiledWork<T> &w, const int *ctrl, hipStream_t st)
+{
+    static_assert((size_t)NW * 9 * 64 * C * sizeof(T) <= kMaxLds, "full-row tile exceeds LDS");
+    if (!swr_fits(g, C)) return fail(RPR_ERR_UNSUPPORTED, "shallow-water full-row tile: grid rows do not fit");
+    auto kern = k_prop_swe_rows<T, C, R, NW>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        RPR_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+        attr_set = true;
+    }
+    if ((long long)swr_tiles_of<C, R, NW>(g) * n > 0x7fffffffLL)
+        return fail(RPR_ERR_UNSUPPORTED, "tiled propagator: more than 2^31 tiles per launch");
+    const dim3 grid((unsigned)(swr_tiles_of<C, R, NW>(g) * n));
+    const size_t lds = swr_lds<C, R, NW>(sizeof(T));
+    for (long long s = 0; s < (long long)steps; ++s) {
+        hipLaunchKernelGGL(kern, grid, dim3(64 * NW), lds, st, g, s, (long long)steps, dt, n, in, out, w, ctrl);
+        RPR_HIP(hipGetLastError());
+    }
+    return RPR_OK;
+}
+
 template <typename T, int R, int NW>
 static rpr_status launch_swe_fused(const Geom &g, int64_t steps, double dt, int n, const T *in, T *out,
                                    const TiledWork<T> &w, const int *ctrl, hipStream_t st)
@@ -144,6 +187,8 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
                     case 2: return launch_swe_fused<T, 4, 10>(g, steps, dt, n, in, out, w, ctrl, st);
                     case 3: return launch_swe_fused<T, 8, 5>(g, steps, dt, n, in, out, w, ctrl, st);
                     case 4: return launch_swe_fused<T, 2, 16>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 5: return launch_swe_rows<T, 3, 2, 12>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 6: return launch_swe_rows<T, 2, 3, 12>(g, steps, dt, n, in, out, w, ctrl, st);
                     default: return launch_swe_fused<T, 5, 8>(g, steps, dt, n, in, out, w, ctrl, st);
                     }
                 } else {
@@ -151,6 +196,8 @@ rpr_status launch_prop_tiled_kind(const Geom &g, int method, int64_t steps, doub
                     case 1: return launch_swe_fused<T, 4, 6>(g, steps, dt, n, in, out, w, ctrl, st);
                     case 2: return launch_swe_fused<T, 3, 8>(g, steps, dt, n, in, out, w, ctrl, st);
                     case 3: return launch_swe_fused<T, 2, 12>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 4: return launch_swe_rows<T, 3, 2, 8>(g, steps, dt, n, in, out, w, ctrl, st);
+                    case 5: return launch_swe_rows<T, 2, 3, 8>(g, steps, dt, n, in, out, w, ctrl, st);
                     default: return launch_swe_fused<T, 4, 8>(g, steps, dt, n, in, out, w, ctrl, st);
                     }
                 }

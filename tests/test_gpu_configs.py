@@ -46,7 +46,7 @@ def oracle_run(orc, w, k_max=None):
                         net=orc.Net(A, z, w.act, w.lam, 0.0), nthreads=8, k_max=k_max)
 
 
-def tests_orc():
+def _oracle_module():
     import oracle
     return oracle
 
@@ -99,7 +99,7 @@ def test_reduced_precision_batch_at_workload_sizes_within_tau(c4):
     status, Us, infos = run_batch(ws, precision=rpr.RPR_MIXED)
     for w, Ug, ig, Uf in zip(ws, Us, infos, fine):
         assert ig["converged"] == 1
-        Uo, io = oracle_run(tests_orc(), w, k_max=ig["K"])
+        Uo, io = oracle_run(_oracle_module(), w, k_max=ig["K"])
         tau = 10.0 * E_err(gpu_serial_fine_fp32(w), Uf)
         print(w.name, "mixed K", ig["K"], "E %.2e" % E_err(Ug, Uf), "FP64 E %.2e" % E_err(Uo, Uf), "tau %.2e" % tau)
         assert E_err(Ug, Uf) <= E_err(Uo, Uf) + tau

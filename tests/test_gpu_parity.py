@@ -15,6 +15,7 @@ Tolerances (relative to the largest magnitude of the reference):
     the forward-error bound of a backward-stable Cholesky solve.
   - generator: bitwise.
 """
+import ctypes as C
 import math
 
 import numpy as np
@@ -164,6 +165,55 @@ def test_tiled_propagate_matches_oracle(orc, case, prec):
     print(name, "tiled", "fp64" if prec == rpr.RPR_FP64 else "fp32", "rel err %.2e" % err)
     assert np.all(np.isfinite(host(xout)))
     assert err <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5)
+
+
+SHAPE_GRIDS = [(rpr.RPR_SWE2D, 192, 192, 4), (rpr.RPR_SWE2D, 96, 80, 30), (rpr.RPR_SWE2D, 57, 33, 30),
+               (rpr.RPR_SWE2D, 4, 4, 30), (rpr.RPR_SWE2D, 130, 70, 30), (rpr.RPR_SWE2D, 126, 29, 31),
+               (rpr.RPR_DIFFREACT2D, 130, 70, 20), (rpr.RPR_BRUSS2D, 70, 37, 21)]
+
+
+@pytest.mark.parametrize("kind,nx,ny,steps", SHAPE_GRIDS, ids=lambda v: str(v))
+@pytest.mark.parametrize("prec", [rpr.RPR_FP64, rpr.RPR_MIXED], ids=["fp64", "fp32"])
+def test_every_tile_shape_matches_oracle(orc, kind, nx, ny, steps, prec):
+    """Each tile shape of the one-pass RK4 kernels, pinned through the
+    autotuner's table: the 56-column tiles with a 4-cell halo and the
+    full-row form (whole rows per wavefront, C cells per lane; 192 = 64 x 3
+    fills every lane, 57 and 126 leave lanes past the east wall, 4 x 4 puts
+    both walls on one lane), on grids each shape serves; a shape that does
+    not serve the grid is refused."""
+    rng = np.random.default_rng(nx * 1000 + ny)
+    d = rpr.nspecies(kind) * nx * ny
+    dom = (0, 1, 0, 1) if kind == rpr.RPR_SWE2D else (-1, 1, -1, 1)
+    params = {rpr.RPR_SWE2D: (9.81,), rpr.RPR_DIFFREACT2D: (1e-3, 5e-3, 5e-3),
+              rpr.RPR_BRUSS2D: (1.0, 3.0, 0.02, 0.01)}[kind]
+    dt = 2e-5 if nx >= 192 else 2e-4
+    X = np.stack([initial_state(kind, nx, ny, rng) for _ in range(3)])
+    ref = orc.propagate_many(orc.problem(kind, nx, ny, dom, params), 4, steps, dt, X)
+    h = rpr.make_rhs(kind, nx, ny, dom, params)
+    key = rpr.prop_tune_key(kind, nx, ny, prec, 4) + ":v"
+    dtype = torch.float64 if prec == rpr.RPR_FP64 else torch.float32
+    served = 0
+    try:
+        for v, name in enumerate(rpr.tile_shapes(kind, prec)):
+            rpr.rpr_tune_set(key, v)
+            xin, xout = dev(X, dtype), torch.zeros((3, d), dtype=dtype, device="cuda")
+            st = rpr.lib().rpr_propagate(C.byref(h), d, C.byref(rpr.rpr_propagator(4, 256, steps)), prec, dt, 3,
+                                         xin.data_ptr(), xout.data_ptr(), None)
+            rows = name.startswith("rows:")
+            C_ = int(name[6]) if rows else 0
+            fits = not rows or (nx <= 64 * C_ and nx % C_ == 0)
+            if not fits:
+                assert st == rpr.RPR_ERR_UNSUPPORTED, name
+                continue
+            assert st == 0, (name, rpr.last_error())
+            err = rel_err(host(xout), ref)
+            print(nx, ny, name, "fp64" if prec == rpr.RPR_FP64 else "fp32", "rel err %.2e" % err)
+            assert np.all(np.isfinite(host(xout))), name
+            assert err <= (1e-12 if prec == rpr.RPR_FP64 else 2e-5), name
+            served += 1
+    finally:
+        rpr.rpr_tune_set(key, -1)
+    assert served >= 1
 
 
 @pytest.mark.parametrize("steps", [1, 3])
