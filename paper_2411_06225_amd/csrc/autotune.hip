@@ -114,6 +114,10 @@ extern "C" const char *rpr_tile_shape_name(int32_t kind, int32_t precision, int3
     return fused_variant_name(kind, elem, v);
 }
 
+// Fraction by which a fine-propagator candidate must beat the best one timed
+// before it (the work-group sizes, then the tile shapes in index order).
+constexpr float kSwitchMargin = 0.05f;
+
 // Device memory released when it goes out of scope.
 struct DevBuf {
     void *p = nullptr;
@@ -187,7 +191,10 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
                 std::ostringstream kt;
                 kt << kf << ":t:" << mt << ":" << (mt == TILED_THREADS ? fused_variant_name(g.kind, p->esz, v) : "onchip");
                 g_tune[kt.str()] = (int)(ms * 1000.f / 3.f);
-                if (ms < best) { best = ms; best_mt = mt; best_v = mt == TILED_THREADS ? v : 0; }
+                // a later candidate must win by kSwitchMargin: shapes within
+                // the timing noise of each other would otherwise flip from
+                // one process to the next
+                if (ms < best * (1.f - kSwitchMargin)) { best = ms; best_mt = mt; best_v = mt == TILED_THREADS ? v : 0; }
             }
         }
         if (!forced_tiled) g_tune[kf] = best_mt;
