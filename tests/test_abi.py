@@ -214,3 +214,37 @@ def test_stability_ratio_closed_forms():
     # bad arguments
     with pytest.raises(rpr.RprError):
         rpr.rpr_stability(hs, 3 * 192 * 192, 1, 8, 1e-3, -1.0)
+
+
+def test_tuning_table_set_get_and_remove():
+    # host-only table of launch shapes: no device is touched
+    key = "prop:3:96x80:4:4:v"
+    assert rpr.rpr_tune_get(key) is None
+    try:
+        rpr.rpr_tune_set(key, 5)
+        assert rpr.rpr_tune_get(key) == 5
+        rpr.rpr_tune_set(key, 2)
+        assert rpr.rpr_tune_get(key) == 2
+    finally:
+        rpr.rpr_tune_set(key, -1)
+    assert rpr.rpr_tune_get(key) is None
+    L = rpr.lib()
+    assert L.rpr_tune_set(b"", 1) == rpr.RPR_ERR_INVALID_ARG
+    assert L.rpr_tune_set(None, 1) == rpr.RPR_ERR_INVALID_ARG
+    assert L.rpr_tune_get(b"prop:none", None) == rpr.RPR_ERR_INVALID_ARG
+    v = C.c_int32(0)
+    assert L.rpr_tune_get(b"prop:none", C.byref(v)) == rpr.RPR_ERR_INVALID_ARG
+    assert "no entry" in rpr.last_error()
+
+
+def test_tile_shape_names():
+    swe32 = rpr.tile_shapes(rpr.RPR_SWE2D, rpr.RPR_MIXED)
+    swe64 = rpr.tile_shapes(rpr.RPR_SWE2D, rpr.RPR_FP64)
+    assert swe32[0] == "R5NW8" and swe64[0] == "R4NW8"
+    assert any(s.startswith("rows:C3") for s in swe32) and any(s.startswith("rows:C3") for s in swe64)
+    assert len(set(swe32)) == len(swe32) and len(set(swe64)) == len(swe64)
+    assert rpr.tile_shapes(rpr.RPR_DIFFREACT2D, rpr.RPR_FP64)[0] == "FY32NT512"
+    assert rpr.tile_shapes(rpr.RPR_BURGERS1D, rpr.RPR_FP64) == ["default"]
+    L = rpr.lib()
+    assert L.rpr_tile_shape_name(rpr.RPR_SWE2D, rpr.RPR_MIXED, len(swe32)) is None
+    assert L.rpr_tile_shape_name(rpr.RPR_SWE2D, rpr.RPR_MIXED, -1) is None
