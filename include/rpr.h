@@ -338,6 +338,14 @@ rpr_status rpr_stability(const rpr_rhs *h, int32_t d, const rpr_propagator *P, d
  *   "prop:<kind>:<nx>x<ny>:<bytes>:<m>:v"  tile shape of the tiled form's
  *                                          one-pass RK4 kernel, 0 ..
  *                                          rpr_tile_shapes() - 1
+ * and of the predictor-corrector sweep of a plan with M neurons, N slots,
+ * correction c and bf16 training features f (0 or 1):
+ *   "chain:<kind>:<nx>x<ny>:<bytes>:M<M>:N<N>:<c>:<f>"    work-groups
+ *   "chain:...:<f>:B"  work-group size of a sweep in segment kernels over a
+ *                      tiled grid with a forward-Euler G: 256, or 1024 for
+ *                      four times the wavefronts per CU
+ * (a plan with autotune = 1 takes the stored entries of its class and times
+ * the missing ones).
  * rpr_propagate with threads 256 takes the tile shape stored for its class;
  * a shape that does not serve the grid returns RPR_ERR_UNSUPPORTED.
  * Errors: RPR_ERR_INVALID_ARG (null or empty key, null value).

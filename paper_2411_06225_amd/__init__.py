@@ -289,6 +289,14 @@ def prop_tune_key(kind: int, nx: int, ny: int, precision: int, method: int) -> s
     return f"prop:{int(kind)}:{int(nx)}x{int(ny)}:{8 if precision == RPR_FP64 else 4}:{int(method)}"
 
 
+def chain_tune_key(kind: int, nx: int, ny: int, precision: int, M: int, N: int, correction: int = 0,
+                   bf16_features: bool | None = None) -> str:
+    """Table key of a plan's sweep (append ":B" for its work-group size)."""
+    f = (precision == RPR_MIXED) if bf16_features is None else bf16_features
+    return (f"chain:{int(kind)}:{int(nx)}x{int(ny)}:{8 if precision == RPR_FP64 else 4}:M{int(M)}:N{int(N)}:"
+            f"{int(correction)}:{1 if f else 0}")
+
+
 # ---- plans ---------------------------------------------------------------------
 class Plan:
     """One IVP solved by RandNet-Parareal (rpr_plan_create / execute / destroy)."""

@@ -246,7 +246,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         nn_args<T>(p, a);
         if (p->nn) RPR_TRY(zero(p->nrows, 1, st));  // the trials run with an empty store
         float best = 1e30f;
-        int best_n = p->nwg, best_gt = p->shG.maxt;
+        int best_n = p->nwg, best_gt = p->shG.maxt, best_b = p->shG.block;
         // coarse-solver shapes: the plan's, and for an on-chip G of free
         // thread count the 512-thread one too (longer strips, twice the
         // registers per thread)
@@ -255,6 +255,12 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         if (p->G.threads == 0 && p->shG.maxt == 1024 && onchip_shape(g, p->esz, &gshapes[1], 512) &&
             check_threads(g, p->esz, 512) == RPR_OK)
             n_shapes = 2;
+        // a tiled forward-Euler G in segment kernels: also the wide work-groups
+        const bool wide_ok = p->seg_sweep && p->shG.maxt == TILED_THREADS && p->G.method == RPR_RK1;
+        if (wide_ok) {
+            gshapes[1].block = SWEEP_WIDE;
+            n_shapes = 2;
+        }
         const int cands[] = {1, cus / 16, cus / 8, cus / 4, cus / 2, cus};
         // the trials run the sweep in the plan's form
         if (p->seg_sweep) RPR_HIP(hipMemcpy(p->gchain, &a, sizeof(a), hipMemcpyHostToDevice));
@@ -266,7 +272,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         for (int s = 0; s < n_shapes; ++s) {
             const OnchipShape &sh = gshapes[s];
             int mwg = max_wg;  // grids beyond the plan's max_wg have no partial-sum rows
-            if (s > 0) {
+            if (s > 0 && !wide_ok) {
                 int m2 = 0;
                 RPR_TRY(launch_chain<T>(a, sh, 0, nullptr, &m2));
                 mwg = std::min(mwg, m2);
@@ -286,11 +292,12 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
                 RPR_HIP(hipEventRecord(e1, st));
                 RPR_HIP(hipEventSynchronize(e1));
                 RPR_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; best_n = c; best_gt = sh.maxt; }
+                if (ms < best) { best = ms; best_n = c; best_gt = sh.maxt; best_b = sh.block; }
             }
         }
         g_tune[kc.str()] = best_n;
         g_tune[kc.str() + ":G"] = best_gt;
+        g_tune[kc.str() + ":B"] = best_b;
     }
     // the coarse solver's work-group size (tuned only where G's is free)
     const auto gt = g_tune.find(kc.str() + ":G");
@@ -309,6 +316,11 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
             }
         }
     }
+    // the tiled sweep's work-group size
+    const auto gb = g_tune.find(kc.str() + ":B");
+    if (p->seg_sweep && p->shG.maxt == TILED_THREADS && p->G.method == RPR_RK1 && gb != g_tune.end() &&
+        gb->second == SWEEP_WIDE)
+        p->shG.block = SWEEP_WIDE;
     if (!p->fixed_nwg) p->nwg = g_tune[kc.str()] < max_wg ? g_tune[kc.str()] : max_wg;
     if (!haveF || !haveC || !haveV) tune_store();
     return RPR_OK;

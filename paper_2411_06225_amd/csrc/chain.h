@@ -8,6 +8,10 @@
 
 namespace rpr {
 
+// Work-group size of the wide form of the sweep segments over a tiled grid
+// (forward-Euler G).
+constexpr int SWEEP_WIDE = 1024;
+
 enum { CHAIN_SWEEP = 0, CHAIN_RANDNET = 1, CHAIN_PARAREAL = 2, CHAIN_RANDNET_NN = 3 };
 
 // Largest number of nearest neighbours of the refit-per-prediction mode.

@@ -410,8 +410,10 @@ __device__ __forceinline__ void chain_columns(const int d, const int wg, const i
 
 // Coarse solver of the sweep: on one work-group (CM_ONCHIP), in tiles over
 // the grid (CM_TILED), or cell by cell over the grid by its tableau
-// (CM_GENERIC: the 3D system, the eighth-order method).
-enum { CM_ONCHIP = 0, CM_TILED = 1, CM_GENERIC = 2 };
+// (CM_GENERIC: the 3D system, the eighth-order method).  CM_TILED_EULER is
+// CM_TILED for forward Euler only: its multi-step tiles take any work-group
+// size (the per-stage tiles of the other methods assume TT_THREADS).
+enum { CM_ONCHIP = 0, CM_TILED = 1, CM_GENERIC = 2, CM_TILED_EULER = 3 };
 
 // Passes of the grid-wide coarse solvers per slot: tiled forward Euler takes
 // up to EH steps per pass (euler_tile_multi), tiled RK4 one pass per stage,
@@ -446,11 +448,11 @@ __device__ __forceinline__ void generic_coarse_pass(const ChainArgs<T> &a, const
 // arrays u and ya from pass to pass, the FP32 compensation between cmp and
 // acc (forward Euler has no slope sum), so that no tile reads a value another
 // tile of the same pass has already replaced.  RK4: one pass per stage.
-template <int KIND, typename T>
+template <int KIND, typename T, bool EULER_ONLY>
 __device__ __forceinline__ void tiled_coarse_pass(const ChainArgs<T> &a, const T *src, T *dst, T *dst2,
                                                   const long long pass, const int wg, const int nwg, T *lds)
 {
-    if (a.G_method == RPR_RK1) {
+    if (EULER_ONLY || a.G_method == RPR_RK1) {
         T *buf[2] = {a.gw.u, a.gw.ya};
         T *cbuf[2] = {a.gw.cmp, a.gw.acc};
         const long long s = pass * EH;
@@ -469,11 +471,13 @@ __device__ __forceinline__ void tiled_coarse_pass(const ChainArgs<T> &a, const T
         else run(SweepEuler{});
         return;
     }
-    const int nt = tiles_of(a.g);
-    const long long step = pass / 4;
-    const int stage = (int)(pass % 4) + 1;
-    const StageIO<T> io = stage_io<T>(a.G_method, stage, step, a.G_steps, src, dst, dst2, a.gw);
-    for (int tile = wg; tile < nt; tile += nwg) stage_tile_any<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
+    if constexpr (!EULER_ONLY) {
+        const int nt = tiles_of(a.g);
+        const long long step = pass / 4;
+        const int stage = (int)(pass % 4) + 1;
+        const StageIO<T> io = stage_io<T>(a.G_method, stage, step, a.G_steps, src, dst, dst2, a.gw);
+        for (int tile = wg; tile < nt; tile += nwg) stage_tile_any<KIND, T>(a.g, tile, stage, a.dtG, io, lds);
+    }
 }
 
 // One pass of a grid-wide coarse solver.
@@ -485,7 +489,7 @@ __device__ __forceinline__ void coarse_pass(const ChainArgs<T> &a, const T *src,
         (void)lds;
         generic_coarse_pass<KIND, T>(a, src, dst, dst2, pass, wg, nwg);
     } else if constexpr (KIND != RPR_BURGERS1D && KIND != RPR_BRUSS3D) {
-        tiled_coarse_pass<KIND, T>(a, src, dst, dst2, pass, wg, nwg, lds);
+        tiled_coarse_pass<KIND, T, CM == CM_TILED_EULER>(a, src, dst, dst2, pass, wg, nwg, lds);
     }
 }
 
@@ -1062,6 +1066,9 @@ rpr_status launch_sweep_segments_kind(const ChainArgs<T> &a, const OnchipShape &
     } else {
         if (sh.maxt != TILED_THREADS)
             return fail(RPR_ERR_UNSUPPORTED, "sweep segments: the on-chip coarse solver runs in one work-group");
+        if (sh.block == SWEEP_WIDE && a.G_method == RPR_RK1)
+            return run(k_sweep_pass<KIND, T, SWEEP_WIDE, CM_TILED_EULER>, SWEEP_WIDE,
+                       coarse_passes(CM_TILED, a.G_method, a.G_steps, a.tbG.s));
         return run(k_sweep_pass<KIND, T, TT_THREADS, CM_TILED>, TT_THREADS,
                    coarse_passes(CM_TILED, a.G_method, a.G_steps, a.tbG.s));
     }
@@ -1126,9 +1133,15 @@ rpr_status launch_chain_graph_kind(const ChainArgs<T> *args_dev, const ChainArgs
             if constexpr (KIND == RPR_BURGERS1D) {
                 return fail(RPR_ERR_UNSUPPORTED, "the tiled chain serves 2D grids only");
             } else {
+                // work-groups of TT_THREADS, or for a forward-Euler G of
+                // SWEEP_WIDE threads (four times the wavefronts per CU for
+                // the latency-bound coarse passes and the readout's loads)
+                const long long passes = coarse_passes(CM_TILED, a.G_method, a.G_steps, a.tbG.s);
+                if (sh.block == SWEEP_WIDE && a.G_method == RPR_RK1)
+                    return L.sequence(k_chain_seg<KIND, T, 1, false, false, 0, 0, SWEEP_WIDE, CM_TILED_EULER, true>,
+                                      SWEEP_WIDE, chain_lds(sh, a.M), passes);
                 return L.sequence(k_chain_seg<KIND, T, 1, false, false, 0, 0, TT_THREADS, CM_TILED, true>,
-                                  TT_THREADS, chain_lds(sh, a.M),
-                                  coarse_passes(CM_TILED, a.G_method, a.G_steps, a.tbG.s));
+                                  TT_THREADS, chain_lds(sh, a.M), passes);
             }
         }
         return visit_shape_kind<KIND, T>(a.g, sh, L);

@@ -238,6 +238,37 @@ GRAPH_EQ = [("diffreact_32x32", DR_SMALL, 0, 0), ("diffreact_32x32_mixed", DR_SM
             ("bruss_32x32_tiled_rk4_G", tiled(BRUSS_SMALL.replace(G=(4, 4))), 0, 0)]
 
 
+WIDE_SWEEPS = [("swe_16x16_tiled", tiled(SWE_SMALL), 0, 8),
+               ("swe_130x40_tiled_mixed", tiled(W.small(W.SWE_192, nx=130, ny=40, N=8, tN=0.2, F=(4, 40),
+                                                         G=(1, 20), M=40)), 1, 40),
+               ("diffreact_32x32_tiled", tiled(DR_SMALL), 0, 16)]
+
+
+@pytest.mark.parametrize("name,w,prec,nwg", WIDE_SWEEPS, ids=[c[0] for c in WIDE_SWEEPS])
+def test_wide_sweep_work_groups_match_the_narrow_ones_and_the_oracle(orc, name, w, prec, nwg):
+    # the sweep's segment kernels over a tiled grid with a forward-Euler G,
+    # in work-groups of 256 and of 1024 threads, pinned through the
+    # autotuner's table: the same run (the forward-Euler tiles give the same
+    # bits; the hidden layer's partial sums may be summed in another order)
+    key = rpr.chain_tune_key(w.kind, w.nx, w.ny, prec, w.M, w.N)
+    runs = {}
+    for block in (256, 1024):
+        rpr.rpr_tune_set(key, nwg)
+        rpr.rpr_tune_set(key + ":B", block)
+        try:
+            runs[block] = gpu_solve(w, prec=prec, autotune=1)
+        finally:
+            rpr.rpr_tune_set(key, -1)
+            rpr.rpr_tune_set(key + ":B", -1)
+    (Un, i_n), (Uw, iw) = runs[256], runs[1024]
+    assert i_n["K"] == iw["K"] and i_n["L_hist"].tolist() == iw["L_hist"].tolist()
+    scale = np.abs(Un).max()
+    assert np.abs(Uw - Un).max() <= (w.N * 1e-12 if prec == rpr.RPR_FP64 else 1e-5) * scale
+    if prec == rpr.RPR_FP64:
+        Uo, io = orc_solve(orc, w)
+        assert_same_run(Uw, iw, Uo, io, w.N)
+
+
 @pytest.mark.parametrize("name,w,corr,prec", GRAPH_EQ, ids=[c[0] for c in GRAPH_EQ])
 def test_captured_sweep_segments_equal_the_cooperative_sweep(name, w, corr, prec):
     # the captured sweep runs the segments of the cooperative one as kernels
