@@ -26,7 +26,7 @@ timed on the host cores.
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
                     [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128 [--shape S]]
                     [--solve-only NAME] [--gemm] [--robustness] [--model-only]
-                    [--trace-summary KERNEL_TRACE_CSV]
+                    [--sweep-only 256|1024] [--trace-summary CSV] [--segment-summary CSV]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
 (Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems),
@@ -36,7 +36,9 @@ times only the fine propagator of the named workload (all N slot states,
 --steps RK4 steps, FP64 and FP32; --shape pins a tile shape of the one-pass
 kernel where the precision has it) and prints its roofline, for counter runs;
 --model-only times the model phase's FP64 matrix products (features, ridge
-fit) at the shallow-water shape, for counter runs.
+fit) at the shallow-water shape, for counter runs; --sweep-only runs the
+reduced shallow-water solve for one iteration with its sweeps in work-groups
+of the given size, for kernel traces (--segment-summary reads them).
 """
 from __future__ import annotations
 
@@ -138,6 +140,10 @@ def parse():
     ap.add_argument("--robustness-grid", choices=["reduced", "paper"], default="reduced",
                     help="reduced: 8 m x 6 M x 10 draws in one batch per system; paper: App. D's "
                          "19 m x 49 M x 100 draws, one batch per draw")
+    ap.add_argument("--sweep-only", type=int, choices=[256, 1024], default=None,
+                    help="one-iteration reduced shallow-water solve, sweeps on 256 work-groups of this size")
+    ap.add_argument("--segment-summary", default=None,
+                    help="summarise the sweep segments of a kernel trace of --sweep-only (CSV path)")
     ap.add_argument("--shape", default=None,
                     help="with --f-only: pin this tile shape of the one-pass kernel (names: rpr.tile_shapes)")
     ap.add_argument("--f-only", choices=["swe_192x192", "bruss_128x128"], default=None,
@@ -179,13 +185,66 @@ def trace_summary(path, top=25):
               f"{max(v) / 1e3:.2f} | {sum(v) / 1e6:.3f} |")
 
 
+def segment_summary(path, N=256):
+    """The sweep's segment kernels in a kernel trace of `bench.py
+    --sweep-only`, in dispatch order: a sweep of N slots is a prologue, N - 1
+    pairs (phase 1: coarse pass and hidden layer of slot i; phase 2: readout,
+    update, change norm, hidden-layer partial sums of slot i) and the
+    stopping rule; the k = 0 sweep's coarse passes are k_sweep_pass."""
+    import csv
+    import statistics as stt
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    seg = [r for r in rows if "k_chain_seg" in r["Kernel_Name"]]
+    sw = [dur(r) for r in rows if "k_sweep_pass" in r["Kernel_Name"]]
+    print("| sweep | kernel | prologue us | phase 1 us (mean / median) | phase 2 us (mean / median) | "
+          "stopping rule us | sweep ms |")
+    print("|---|---|---|---|---|---|---|")
+    for s0 in range(0, len(seg) - 2 * N + 1, 2 * N):
+        sweep = seg[s0:s0 + 2 * N]
+        p1 = [dur(r) for r in sweep[1:-1:2]]
+        p2 = [dur(r) for r in sweep[2:-1:2]]
+        name = sweep[1]["Kernel_Name"].split("(")[0].replace("void ", "")
+        print(f"| {s0 // (2 * N) + 1} | `{name}` | {dur(sweep[0]):.1f} | {stt.mean(p1):.2f} / {stt.median(p1):.2f} | "
+              f"{stt.mean(p2):.2f} / {stt.median(p2):.2f} | {dur(sweep[-1]):.1f} | "
+              f"{sum(map(dur, sweep)) / 1e3:.2f} |")
+    if sw:
+        print(f"\nk = 0 sweep coarse passes (k_sweep_pass): {len(sw)} dispatches, mean {stt.mean(sw):.2f} us")
+
+
+def sweep_only(torch, rpr, W, dev, block):
+    """The reduced-precision shallow-water solve stopped after one
+    iteration, its sweeps in segment kernels on 256 work-groups of `block`
+    threads (pinned in the autotuner's table), run twice: the trace of it
+    shows each segment's duration."""
+    w = W.SWE_192
+    h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+    A, z = W.random_weights(w)
+    u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
+    key = rpr.chain_tune_key(w.kind, w.nx, w.ny, rpr.RPR_MIXED, w.M, w.N)
+    rpr.rpr_tune_set(key, 256)
+    rpr.rpr_tune_set(key + ":B", block)
+    p = rpr.Plan(h, w.d, w.t0, w.tN, w.N, F=w.F, G=w.G, tol=w.eps, M=w.M, activation=w.act, lam=w.lam, A=A,
+                 zeta=z, precision=rpr.RPR_MIXED, k_max=1, autotune=1)
+    U = torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev)
+    for _ in range(2):
+        p.execute(u0, U)
+        torch.cuda.synchronize()
+    info = p.info()
+    p.close()
+    return {"block": block, "sweep_s": info["t_sweep"], "total_s": info["t_total"]}
+
+
 def main():
     args = parse()
     if args.trace_summary:
         trace_summary(args.trace_summary)
         return
+    if args.segment_summary:
+        segment_summary(args.segment_summary)
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -209,6 +268,9 @@ def main():
         else:
             res = robustness_sweep(torch, rpr, W, dev)
         print(json.dumps({"robustness": res}))
+        return
+    if args.sweep_only:
+        print(json.dumps({"sweep_only": sweep_only(torch, rpr, W, dev, args.sweep_only)}))
         return
     if args.model_only:
         print(json.dumps({"model_fp64": model_roofline(torch, rpr, W, dev, reps=max(args.steps, 1))}))
