@@ -27,6 +27,7 @@ timed on the host cores.
                     [--extra] [--copy-calibration] [--f-only swe_192x192|bruss_128x128 [--shape S]]
                     [--solve-only NAME] [--gemm] [--robustness] [--model-only]
                     [--sweep-only 256|1024] [--trace-summary CSV] [--segment-summary CSV]
+                    [--trace-window CSV NAME GRID SKIP COUNT]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
 (Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems),
@@ -144,6 +145,8 @@ def parse():
                     help="one-iteration reduced shallow-water solve, sweeps on 256 work-groups of this size")
     ap.add_argument("--segment-summary", default=None,
                     help="summarise the sweep segments of a kernel trace of --sweep-only (CSV path)")
+    ap.add_argument("--trace-window", nargs=5, metavar=("CSV", "NAME", "GRID", "SKIP", "COUNT"), default=None,
+                    help="mean duration of COUNT dispatches of a kernel, ending SKIP before its last one")
     ap.add_argument("--shape", default=None,
                     help="with --f-only: pin this tile shape of the one-pass kernel (names: rpr.tile_shapes)")
     ap.add_argument("--f-only", choices=["swe_192x192", "bruss_128x128"], default=None,
@@ -183,6 +186,22 @@ def trace_summary(path, top=25):
         short = name.split("(")[0].replace("void ", "")
         print(f"| `{short}` | {grid} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | {min(v) / 1e3:.2f} | "
               f"{max(v) / 1e3:.2f} | {sum(v) / 1e6:.3f} |")
+
+
+def trace_window(path, name, grid, skip, count):
+    """Mean and median duration of `count` dispatches of the kernel whose
+    name contains `name` at grid size `grid`, ending `skip` dispatches before
+    its last one (in time order): the launches of one timed solve."""
+    import csv
+    import statistics as stt
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    g = lambda r: int(r["Grid_Size"]) if "Grid_Size" in r else \
+        int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+         if name in r["Kernel_Name"] and g(r) == grid]
+    win = d[len(d) - skip - count:len(d) - skip]
+    print(json.dumps({"kernel": name, "grid": grid, "dispatches": len(d), "window": [len(d) - skip - count,
+                      len(d) - skip], "mean_us": stt.mean(win), "median_us": stt.median(win)}))
 
 
 def segment_summary(path, N=256):
@@ -242,6 +261,10 @@ def main():
         return
     if args.segment_summary:
         segment_summary(args.segment_summary)
+        return
+    if args.trace_window:
+        path, name, grid, skip, count = args.trace_window
+        trace_window(path, name, int(grid), int(skip), int(count))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus})",

@@ -70,3 +70,14 @@ def test_traffic_only_for_the_sources_and_shape_the_counters_were_taken_on(monke
     assert bench.measured_traffic("R4NW8") is None
     monkeypatch.setattr(bench, "PROP_TRAFFIC", dict(t, sources="0" * 16))
     assert bench.measured_traffic("R5NW8") is None
+
+
+def test_trace_window_takes_the_dispatches_of_one_solve(tmp_path, capsys):
+    import json
+    rows = [("void k<float, 5, 8>(int)", 96, d) for d in (1, 2, 3, 4, 5, 6)] + [("void k<float, 5, 8>(int)", 48, 100)]
+    p = tmp_path / "w.csv"
+    _trace(p, rows)
+    bench.trace_window(str(p), "k<float, 5, 8>", 96, 1, 3)
+    out = json.loads(capsys.readouterr().out)
+    assert out["dispatches"] == 6 and out["window"] == [2, 5]
+    assert abs(out["mean_us"] - 0.004) < 1e-12
