@@ -30,7 +30,8 @@ timed on the host cores.
                     [--trace-window CSV NAME GRID SKIP COUNT]
 
 --extra adds one FP64 and one mixed-precision solve of the other workloads
-(Burgers d = 128; Brusselator 128 x 128; the batch of 64 Burgers problems),
+(Burgers d = 128; Brusselator 128 x 128; the 3D Brusselator 20^3 with the
+eighth-order fine solver; the batch of 64 Burgers problems),
 which takes minutes.  --copy-calibration runs a device copy of 256 MiB, the
 reference a hardware-counter run uses to scale its byte counters.  --f-only
 times only the fine propagator of the named workload (all N slot states,
@@ -132,7 +133,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--solve-only", choices=["burgers_d128", "bruss_128x128", "swe_192x192"], default=None,
+    ap.add_argument("--solve-only", choices=["burgers_d128", "bruss_128x128", "swe_192x192", "bruss3d_20"],
+                    default=None,
                     help="only run the --extra solves of this workload (for traces)")
     ap.add_argument("--gemm", action="store_true",
                     help="only time the random-feature GEMMs at the workloads' shapes and a compute-bound one")
@@ -854,7 +856,7 @@ def extra_workloads(torch, rpr, W, dev, only=None):
         return torch.stack(out)
 
     def single(w, with_tau=False):
-        h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+        h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params, nz=w.nz if w.kind == rpr.RPR_BRUSS3D else 0)
         A, z = W.random_weights(w)
         u0 = torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev)
         r = {"d": w.d, "N": w.N}
@@ -907,7 +909,7 @@ def extra_workloads(torch, rpr, W, dev, only=None):
         return r
 
     singles = {"burgers_d128": (W.BURGERS_D128, False), "bruss_128x128": (W.BRUSS_128, False),
-               "swe_192x192": (W.SWE_192, False)}
+               "swe_192x192": (W.SWE_192, False), "bruss3d_20": (W.BRUSS3D_20, False)}
     if only is not None:
         return {only: single(*singles[only])}
     for name, (w, tau) in singles.items():

@@ -217,19 +217,30 @@ __device__ __forceinline__ void dist_partial(const ChainArgs<T> &a, const T *__r
 #pragma unroll
         for (int r = 0; r < RB; ++r) acc[r] = 0.0;
         for (int jb = j0; jb < j1; jb += WL * JB) {
+            // every load goes to a clamped in-range address and the masks
+            // apply after it, so the RB x JB loads of a batch are in flight
+            // together (a load under its own bound check waits for itself)
             double xv[JB], v[RB][JB];
+            int jc[JB];
+            bool jin[JB];
 #pragma unroll
             for (int q = 0; q < JB; ++q) {
                 const int j = jb + q * WL + lane;
-                xv[q] = j < j1 ? double(x[j]) : 0.0;
+                jin[q] = j < j1;
+                jc[q] = jin[q] ? j : j1 - 1;
+                const double xl = double(x[jc[q]]);
+                xv[q] = jin[q] ? xl : 0.0;
             }
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
+            for (int r = 0; r < RB; ++r) {
+                const int l = l0 + r;
+                const T *row = a.Xs + (size_t)(l < n ? l : n - 1) * d;
 #pragma unroll
                 for (int q = 0; q < JB; ++q) {
-                    const int j = jb + q * WL + lane, l = l0 + r;
-                    v[r][q] = (l < n && j < j1) ? double(a.Xs[(size_t)l * d + j]) : xv[q];
+                    const double xl = double(row[jc[q]]);
+                    v[r][q] = (l < n && jin[q]) ? xl : xv[q];
                 }
+            }
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
