@@ -46,7 +46,7 @@ typedef enum {
     RPR_ERR_NONFINITE = -5,     /* non-finite values where the method needs finite ones */
     RPR_ERR_NOT_SPD = -6,       /* ridge matrix not numerically positive definite */
     RPR_ERR_UNSTABLE = -7,      /* stability pre-check failed (opt.stability = 1 only) */
-    RPR_ERR_UNSUPPORTED = -8    /* a valid combination this build does not implement */
+    RPR_ERR_UNSUPPORTED = -8    /* a valid combination the library does not implement */
 } rpr_status;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -215,7 +215,7 @@ typedef struct rpr_plan rpr_plan;
  *                       Ignored (may be NULL) for RPR_CORR_PARAREAL.
  * Allocates every device buffer the solve needs (the plan owns them).
  * Errors: RPR_ERR_INVALID_ARG, RPR_ERR_NO_DEVICE, RPR_ERR_OOM, RPR_ERR_HIP,
- * RPR_ERR_UNSUPPORTED (e.g. a state too large for this build's kernels).
+ * RPR_ERR_UNSUPPORTED (e.g. a state too large for the library's kernels).
  */
 rpr_status rpr_plan_create(rpr_plan **plan, const rpr_rhs *h, int32_t d, double t0, double tN,
                            int32_t N, const rpr_propagator *F, const rpr_propagator *G, double tol,

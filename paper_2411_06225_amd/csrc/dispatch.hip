@@ -92,7 +92,7 @@ rpr_status check_threads(const Geom &g, size_t elem, int threads)
                                        : RPR_OK;
     OnchipShape sh;
     if (!onchip_shape(g, elem, &sh, threads))
-        return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group's LDS in this build");
+        return fail(RPR_ERR_UNSUPPORTED, "the slot state does not fit one work-group's LDS");
     const rpr_status st = elem == 8 ? has_instance_t<double>(g, sh) : has_instance_t<float>(g, sh);
     if (st != RPR_OK)
         return fail(RPR_ERR_UNSUPPORTED, "no " + std::to_string(threads) + "-thread kernel for this grid");
