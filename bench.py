@@ -927,7 +927,8 @@ def extra_workloads(torch, rpr, W, dev, only=None):
     u0s = [torch.tensor(W.initial_condition(w), dtype=torch.float64, device=dev) for w in bw.instances]
     r = {"instances": len(problems), "slots": sum(w.N for w in bw.instances)}
     for name, prec, graph in (("fp64", rpr.RPR_FP64, 0), ("mixed", rpr.RPR_MIXED, 0), ("mixed_graph", rpr.RPR_MIXED, 1)):
-        plan = rpr.BatchPlan(problems, tol=[w.eps for w in bw.instances], precision=prec, graph=graph)
+        plan = rpr.BatchPlan(problems, tol=[w.eps for w in bw.instances], precision=prec, graph=graph,
+                             autotune=1)
         outs = [torch.empty((w.N + 1, w.d), dtype=torch.float64, device=dev) for w in bw.instances]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
