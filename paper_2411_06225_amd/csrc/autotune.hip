@@ -244,7 +244,19 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
         a.part = p->part;
         a.ctrl = p->ctrl;
         nn_args<T>(p, a);
-        if (p->nn) RPR_TRY(zero(p->nrows, 1, st));  // the trials run with an empty store
+        // the nearest-neighbour trials run with a store of two iterations'
+        // pairs: the refit's distance pass grows with the store and is spread
+        // over the sweep's work-groups, so an empty store would favour small
+        // grids.  The trial pairs are zeros flagged non-finite (no refit
+        // takes them); the store is emptied again after the trials.
+        if (p->nn) {
+            const int trial_rows = std::min(p->n_cap, 2 * N);
+            RPR_TRY(zero(static_cast<T *>(p->Xs), (size_t)trial_rows * d, st));
+            RPR_TRY(zero(p->Ps, (size_t)trial_rows * p->M, st));
+            RPR_TRY(zero(p->oks, (size_t)trial_rows, st));
+            RPR_HIP(hipStreamSynchronize(st));
+            RPR_HIP(hipMemcpy(p->nrows, &trial_rows, sizeof(int), hipMemcpyHostToDevice));
+        }
         float best = 1e30f;
         int best_n = p->nwg, best_gt = p->shG.maxt, best_b = p->shG.block;
         // coarse-solver shapes: the plan's, and for an on-chip G of free
@@ -295,6 +307,7 @@ static rpr_status autotune_run(rpr_plan *p, int max_wg, int cus, hipStream_t st,
                 if (ms < best) { best = ms; best_n = c; best_gt = sh.maxt; best_b = sh.block; }
             }
         }
+        if (p->nn) RPR_TRY(zero(p->nrows, 1, st));
         g_tune[kc.str()] = best_n;
         g_tune[kc.str() + ":G"] = best_gt;
         g_tune[kc.str() + ":B"] = best_b;

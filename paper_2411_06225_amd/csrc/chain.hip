@@ -204,7 +204,7 @@ __device__ __forceinline__ void hidden_finish(const ChainArgs<T> &a, const int h
 // after the grid barrier dist_finish: the owner of row l adds the partial
 // sums in work-group order.  Doubles in both precisions.
 template <typename T>
-__device__ __forceinline__ void dist_partial(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
+__device__ __forceinline__ void dist_partial_wave(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
                                              const int j1, const int wg, const int n)
 {
     const int t = threadIdx.x, B = blockDim.x, d = a.g.d;
@@ -259,6 +259,75 @@ __device__ __forceinline__ void dist_partial(const ChainArgs<T> &a, const T *__r
             if (lane == 0 && l0 + r < n) a.dpart[(size_t)wg * a.n_cap + l0 + r] = z;
         }
     }
+}
+
+// The same for a chunk of at most 2 G columns (G = 8, 16 or 32): groups of
+// G lanes take a row each (64 / G rows per wavefront at a time, 8 G / 64 rows
+// per group and pass), so that no lane idles and each row's sum needs a
+// reduction over G lanes only.
+template <typename T, int G>
+__device__ __forceinline__ void dist_partial_groups(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
+                                                    const int j1, const int wg, const int n)
+{
+    const int t = threadIdx.x, B = blockDim.x, d = a.g.d;
+    const int nw = B >= 64 ? B / 64 : 1;
+    const int lane = t & 63, wv = t >> 6;
+    if (wv >= nw) return;
+    constexpr int NG = 64 / G, RG = 8 / NG, JB = 2;  // groups per wavefront, rows per group and pass
+    const int gi = lane / G, sub = lane % G;
+    double xv[JB];
+    int jc[JB];
+    bool jin[JB];
+#pragma unroll
+    for (int q = 0; q < JB; ++q) {
+        const int j = j0 + q * G + sub;
+        jin[q] = j < j1;
+        jc[q] = jin[q] ? j : j1 - 1;
+        const double xl = double(x[jc[q]]);
+        xv[q] = jin[q] ? xl : 0.0;
+    }
+    for (int l0 = wv * 8; l0 < n; l0 += nw * 8) {
+        double acc[RG];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const int l = l0 + gi * RG + r;
+            const T *row = a.Xs + (size_t)(l < n ? l : n - 1) * d;
+            double v[JB];
+#pragma unroll
+            for (int q = 0; q < JB; ++q) {
+                const double xl = double(row[jc[q]]);
+                v[q] = (l < n && jin[q]) ? xl : xv[q];
+            }
+            acc[r] = 0.0;
+#pragma unroll
+            for (int q = 0; q < JB; ++q) {
+                const double e = v[q] - xv[q];
+                acc[r] = fma(e, e, acc[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            double z = acc[r];
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) z += __shfl_xor(z, off, 64);
+            const int l = l0 + gi * RG + r;
+            if (sub == 0 && l < n) a.dpart[(size_t)wg * a.n_cap + l] = z;
+        }
+    }
+}
+
+// Squared distances of x to the n stored rows over columns j0 .. j1 of this
+// work-group: lane groups for narrow chunks, whole wavefronts otherwise.
+template <typename T>
+__device__ __forceinline__ void dist_partial(const ChainArgs<T> &a, const T *__restrict__ x, const int j0,
+                                             const int j1, const int wg, const int n)
+{
+    const int chunk = j1 - j0;
+    const bool groups = blockDim.x % 64 == 0 && chunk > 0;  // every row of dpart gets written either way
+    if (groups && chunk <= 16) dist_partial_groups<T, 8>(a, x, j0, j1, wg, n);
+    else if (groups && chunk <= 32) dist_partial_groups<T, 16>(a, x, j0, j1, wg, n);
+    else if (groups && chunk <= 64) dist_partial_groups<T, 32>(a, x, j0, j1, wg, n);
+    else dist_partial_wave<T>(a, x, j0, j1, wg, n);
 }
 
 // Rows l = hw, hw + nh, ... of the distance vector: one wavefront per row.
