@@ -85,10 +85,10 @@ ALGO_BYTES_PER_DOF_STEP = {8: 16, 4: 8}
 PROP_SOURCES = ("paper_2411_06225_amd/csrc/swefused.h", "paper_2411_06225_amd/csrc/tiled.hip",
                 "paper_2411_06225_amd/csrc/tiledprop.h", "paper_2411_06225_amd/csrc/slotprop.h",
                 "paper_2411_06225_amd/csrc/common.h")
-PROP_TRAFFIC = {"sources": "0c956597e43a201d", "fetch_scale": 2.0, "write_scale": 1.0,
+PROP_TRAFFIC = {"sources": "0e929cc303205708", "fetch_scale": 2.0, "write_scale": 1.0,
                 # tile shape -> (FETCH_SIZE, WRITE_SIZE) KiB per steady-state
                 # dispatch (compensation read and written), FP32, 256 states
-                "shapes": {"R5NW8": (110682.0, 221357.4), "R4NW8": (110670.8, 221189.7)}}
+                "shapes": {"R5NW8": (110682.5, 221285.3), "R4NW8": (110670.7, 221190.2)}}
 
 
 def sources_hash(paths):

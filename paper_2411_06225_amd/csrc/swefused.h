@@ -299,7 +299,7 @@ __device__ __forceinline__ void swe_rk4_tile(const Geom &g, const int tile, cons
 // with the same 4-row halo and mirror ghost rows as above.  The faces on the
 // x walls take the mirror state of the wall cell explicitly (normal momentum
 // negated, so the mass and tangential fluxes vanish and the normal one is
-// twice the wall cell's pressure term plus its dissipation).  Lanes past the
+// 2 f -+ 2 a m from the wall cell's f = m u + g h^2 / 2 and speed a).  Lanes past the
 // last column read the row's last C cells (finite values) and feed no grid
 // cell.  Against the 56-column tiles: no halo columns or padding lanes to
 // recompute, and 9 lane moves per C cells instead of per cell; but C R
