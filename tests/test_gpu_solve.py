@@ -480,6 +480,19 @@ def test_nearest_neighbour_tiled_plan_matches_oracle(orc):
     assert np.abs(Ug - Uo).max() / np.abs(Uo).max() <= tol
 
 
+@pytest.mark.parametrize("name,w", [("diffreact_32x32", DR_SMALL), ("swe_16x16_tiled", tiled(SWE_SMALL))],
+                         ids=["diffreact_32x32", "swe_16x16_tiled"])
+def test_autotuned_nearest_neighbour_plan_matches_oracle(orc, name, w):
+    # the autotuner times the sweep with a store of two iterations' zero
+    # pairs and empties it again: the solve is the oracle's
+    Ug, ig = gpu_solve(w, corr=rpr.RPR_CORR_RANDNET_NN, m_nn=4, autotune=1)
+    Uo, io = orc_solve(orc, w, corr=2, m_nn=4, keep=True)
+    assert ig["K"] == io["K"] and ig["L_hist"].tolist() == io["L_hist"].tolist()
+    assert ig["rows_used"] == io["rows_used"] and ig["chol_fail"] == 0
+    tol = max(w.N * 1e-12, 10 * nn_refit_condition(orc, w, io, 4) * 2.0 ** -53)
+    assert np.abs(Ug - Uo).max() / np.abs(Uo).max() <= tol
+
+
 def test_nearest_neighbour_with_every_pair_equals_global_fit():
     # With m_nn at least the number of stored pairs the refit uses every pair,
     # and the dual form equals the global primal fit (push-through identity):
