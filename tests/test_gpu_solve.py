@@ -6,7 +6,10 @@ histories of the converged-slot counter L.  States are compared with the
 tolerance N * 1e-12 relative to max |U|: each slot value is produced by at
 most N sequential propagator applications (through the predictor-corrector
 chain), each of which agrees with the oracle to 1e-12 (see the propagator
-parity tests); the ridge solves contribute far less on these workloads.
+parity tests); the ridge solves contribute far less on most workloads.  Where
+they may not, intermediate iterates take the forward-error bound of the
+Cholesky solve, 10 kappa 2^-53, in addition, and the full shallow-water
+workload a bound on the paper's accuracy measure (see its test).
 """
 import json
 import math
@@ -423,6 +426,80 @@ def test_mixed_precision_solve_stays_within_fp32_error_of_oracle(orc, name, w):
     assert ig["converged"] == 1 and 1 <= ig["K"] <= w.N
     E_mixed, E_fp64 = E_err(Ug, Uf), E_err(Uo, Uf)
     print(f"mixed K {ig['K']} E {E_mixed:.2e}; FP64 at k = {io['K']}: E {E_fp64:.2e}; tau {tau:.2e}")
+    assert E_mixed <= E_fp64 + tau
+
+
+# ---- the shallow-water workload at full size (192 x 192, N = 256) ----------
+# Planned as the benchmark plans it (autotuned tile shapes, sweep form and
+# grid) and compared with a stored oracle run on a fixed sample of entries:
+# every slot, 16 seeded positions per slot.
+def swe_golden():
+    return json.load(open(os.path.join(GOLDEN, "swe_192x192_oracle.json")))
+
+
+def test_full_swe_fine_solver_matches_stored_oracle_serial_fine():
+    # F alone: 256 slices of 1000 RK4 steps chained slot after slot
+    g = swe_golden()
+    w = W.SWE_192
+    idx = np.asarray(g["sample_index"])
+    h = rpr.make_rhs(w.kind, w.nx, w.ny, w.domain, w.params)
+    cur = torch.tensor(W.initial_condition(w), dtype=torch.float64, device="cuda")[None].contiguous()
+    out = [cur[0, idx].cpu().numpy()]
+    for _ in range(w.N):
+        nxt = torch.empty_like(cur)
+        rpr.rpr_propagate(h, w.d, w.F[0], w.F[1], rpr.RPR_FP64, (w.tN - w.t0) / w.N / w.F[1], 1, cur, nxt)
+        cur = nxt
+        out.append(cur[0, idx].cpu().numpy())
+    err = np.abs(np.stack(out) - np.asarray(g["serial_fine_sample"])).max() / g["U_absmax"]
+    print(f"serial fine rel err on the sample {err:.2e}")
+    assert err <= w.N * 1e-12
+
+
+def test_full_swe_workload_matches_stored_oracle_run():
+    # The iteration's decisions (K, the L history, the rows fitted) must be
+    # the oracle's, and slot 1, F(u0) from the plan's fine launch, must agree
+    # to 1e-12.  Every other slot carries ridge predictions of the chain.  The
+    # oracle's ridge systems here have kappa_2(Phi^T Phi + lambda I) up to
+    # ~7e14 (1268 nearly collinear pairs, lambda = 1e-6), so the forward-error
+    # bound 10 kappa 2^-53 of the fitted coefficients says nothing (~0.8); the
+    # predictions are far less sensitive than the coefficients.  The stated
+    # tolerance is on the paper's accuracy measure instead: the sampled
+    # states may differ from the oracle's by at most 1 % of the oracle run's
+    # error E against the serial fine solution, so the two runs have the same
+    # accuracy to two digits.
+    g = swe_golden()
+    w = W.SWE_192
+    Ug, ig = gpu_solve(w, prec=rpr.RPR_FP64, autotune=1)
+    print("K", ig["K"], "L", ig["L_hist"].tolist(), "rows", ig["rows_used"])
+    assert ig["K"] == g["K"]
+    assert ig["L_hist"].tolist() == g["L_hist"]
+    assert ig["rows_used"] == g["rows_used"]
+    idx = np.asarray(g["sample_index"])
+    diff = np.abs(Ug[:, idx] - np.asarray(g["U_sample"])).max(axis=1)
+    tol = 0.01 * g["E_vs_serial_fine"]
+    print(f"abs diff on the sample: slot 1 {diff[1]:.2e}, all slots {diff.max():.2e} (bound {tol:.1e}); "
+          f"oracle kappa up to {max(g['ridge_kappa']):.1e}")
+    assert diff[1] <= 1e-12 * g["U_absmax"]
+    assert diff.max() <= tol
+    Ef = E_err(Ug[:, idx], np.asarray(g["serial_fine_sample"]))
+    assert Ef <= g["E_vs_serial_fine"] + tol
+
+
+def test_full_swe_workload_reduced_precision_within_fp32_error_of_oracle():
+    # the reduced-precision solve to the stopping rule (FP32 states take more
+    # iterations than FP64 ones here) against the oracle's serial fine
+    # solution on the stored sample: at most the error of the oracle's FP64
+    # run plus tau = 10 x the error of the GPU's FP32 serial fine solution on
+    # the same sample (the FP32 floor of the fine solver)
+    g = swe_golden()
+    w = W.SWE_192
+    idx = np.asarray(g["sample_index"])
+    Uf = np.asarray(g["serial_fine_sample"])
+    Ug, ig = gpu_solve(w, prec=rpr.RPR_MIXED, autotune=1)
+    tau = 10.0 * E_err(gpu_serial_fine_fp32(w)[:, idx], Uf)
+    E_mixed, E_fp64 = E_err(Ug[:, idx], Uf), E_err(np.asarray(g["U_sample"]), Uf)
+    print(f"mixed K {ig['K']} E {E_mixed:.2e}; FP64 oracle K {g['K']} E {E_fp64:.2e}; tau {tau:.2e}")
+    assert ig["converged"] == 1 and 1 <= ig["K"] <= w.N
     assert E_mixed <= E_fp64 + tau
 
 
