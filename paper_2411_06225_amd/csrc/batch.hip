@@ -93,9 +93,10 @@ extern "C" rpr_status rpr_plan_create_batch(rpr_plan **plan, int32_t n_inst, con
     char *tmp;
     if ((st = dalloc(&tmp, isz * n_inst)) != RPR_OK) return bail(st);
     p->binsts = tmp;
-    if ((st = dalloc(&tmp, csz * n_inst)) != RPR_OK) return bail(st);
+    // chain arguments of the iterations, then those of the k = 0 sweep
+    if ((st = dalloc(&tmp, 2 * csz * n_inst)) != RPR_OK) return bail(st);
     p->bchain = tmp;
-    p->hchain.assign(csz * n_inst, 0);
+    p->hchain.assign(2 * csz * n_inst, 0);
     std::vector<char> hinst(isz * n_inst);
     for (int b = 0; b < n_inst; ++b) {
         rpr_plan *q = p->sub[b];
@@ -167,10 +168,19 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
         return ms * 1e-3;
     };
     RPR_HIP(hipEventRecord(p->ev0, st));
-    std::vector<ChainArgs<T>> args(n);
-    for (int b = 0; b < n; ++b) RPR_TRY(phase_setup<T>(p->sub[b], u0[b], umax[b], st, &args[b]));
-    std::memcpy(p->hchain.data(), args.data(), sizeof(ChainArgs<T>) * n);
-    RPR_HIP(hipMemcpyAsync(p->bchain, p->hchain.data(), sizeof(ChainArgs<T>) * n, hipMemcpyHostToDevice, st));
+    // the k = 0 coarse sweeps of all instances in one launch, one work-group
+    // each (each touches only its own instance's buffers), as the
+    // iterations' sweeps run; the values are those of one sweep per instance
+    std::vector<ChainArgs<T>> args(2 * n);
+    for (int b = 0; b < n; ++b) RPR_TRY(phase_setup<T>(p->sub[b], u0[b], umax[b], st, &args[b], false));
+    for (int b = 0; b < n; ++b) {
+        args[n + b] = args[b];
+        args[n + b].mode = CHAIN_SWEEP;
+    }
+    std::memcpy(p->hchain.data(), args.data(), sizeof(ChainArgs<T>) * 2 * n);
+    RPR_HIP(hipMemcpyAsync(p->bchain, p->hchain.data(), sizeof(ChainArgs<T>) * 2 * n, hipMemcpyHostToDevice, st));
+    RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->bchain) + n, n, p->bgmax, p->bshG, p->bM,
+                                  st));
     if (timed) RPR_HIP(hipEventRecord(p->pev[0], st));
     const auto *insts = static_cast<const BatchInst<T> *>(p->binsts);
     // (ev: the first of the iteration's three phase events, or -1)

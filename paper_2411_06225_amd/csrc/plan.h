@@ -298,9 +298,11 @@ inline rpr_status phase_check_u0(rpr_plan *p, const double *u0, hipStream_t st)
 }
 
 // input scale (Algorithm "Parareal (generic)", initialisation), control block,
-// U_0 = u0, zeroed ridge statistics, coarse sweep
+// U_0 = u0, zeroed ridge statistics, coarse sweep (left to the caller with
+// sweep = false: a batch sweeps all its instances in one launch)
 template <typename T>
-inline rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStream_t st, ChainArgs<T> *out)
+inline rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStream_t st, ChainArgs<T> *out,
+                              bool sweep = true)
 {
     double s = p->scale_opt;
     if (!(s > 0)) {
@@ -324,8 +326,8 @@ inline rpr_status phase_setup(rpr_plan *p, const double *u0, double umax, hipStr
     // generic coarse solvers spread each slot's tiles or cells over the plan's
     // grid, in one cooperative kernel or one kernel per pass
     const bool grid = p->shG.maxt == TILED_THREADS || p->shG.maxt == GENERIC_THREADS;
-    if (grid && p->seg_sweep) RPR_TRY(launch_sweep_segments<T>(a, p->shG, p->nwg, st));
-    else RPR_TRY(launch_chain<T>(a, p->shG, grid ? p->nwg : 1, st));
+    if (sweep && grid && p->seg_sweep) RPR_TRY(launch_sweep_segments<T>(a, p->shG, p->nwg, st));
+    else if (sweep) RPR_TRY(launch_chain<T>(a, p->shG, grid ? p->nwg : 1, st));
     a.mode = chain_mode(p);
     *out = a;
     return RPR_OK;
