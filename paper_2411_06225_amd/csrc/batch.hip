@@ -183,6 +183,11 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
                                   st));
     if (timed) RPR_HIP(hipEventRecord(p->pev[0], st));
     const auto *insts = static_cast<const BatchInst<T> *>(p->binsts);
+    // instances not known to be done: eager bursts enqueue the model phase
+    // of these only (a done instance's model kernels find no rows and return
+    // at once, so leaving them out changes nothing but the launches);
+    // captured blocks hold every instance
+    std::vector<char> live(n, 1);
     // (ev: the first of the iteration's three phase events, or -1)
     auto iteration = [&](hipStream_t s, int ev) -> rpr_status {
         // every unfinished (instance, slot) fine solve in one persistent launch
@@ -190,7 +195,8 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
         RPR_TRY(launch_prop_persistent<T>(insts, p->bitems, p->bn_items, p->bcounter, p->bgmax, p->bshF, p->bgrid,
                                           s));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev], s));
-        for (int b = 0; b < n; ++b) RPR_TRY(phase_model<T>(p->sub[b], args[b].inv_s, s));
+        for (int b = 0; b < n; ++b)
+            if (live[b]) RPR_TRY(phase_model<T>(p->sub[b], args[b].inv_s, s));
         if (ev >= 0) RPR_HIP(hipEventRecord(p->pev[ev + 1], s));
         // every instance's predictor-corrector sweep, one work-group each
         RPR_TRY(launch_chain_multi<T>(static_cast<const ChainArgs<T> *>(p->bchain), n, p->bgmax, p->bshG, p->bM, s));
@@ -228,7 +234,10 @@ static rpr_status execute_batch_impl(rpr_plan *p, const double *const *u0, doubl
             RPR_HIP(hipMemcpyAsync(p->sub[b]->ctrl_host, p->sub[b]->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
         RPR_HIP(hipStreamSynchronize(st));
         done = true;
-        for (int b = 0; b < n; ++b) done = done && p->sub[b]->ctrl_host->done != 0;
+        for (int b = 0; b < n; ++b) {
+            done = done && p->sub[b]->ctrl_host->done != 0;
+            live[b] = p->sub[b]->ctrl_host->done == 0;
+        }
         if (timed) {
             if (first) {
                 float ms0 = 0.f;
